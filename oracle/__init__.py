@@ -1,0 +1,231 @@
+"""FP64 CPU oracle for the EPIC direct imager -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library never links, loads or
+calls it, and it shares no code with the GPU library.
+
+Two independent implementations live here:
+
+* ``epic_oracle.c`` -- plain C99 in double precision (own radix-2 FFT and a
+  direct DFT), wrapped by the functions below through ctypes;
+* ``numpy_oracle.py`` -- a second, separately written numpy version (own plan,
+  ``np.add.at`` gridding, ``numpy.fft``) used to cross-check the first.
+
+Both follow Sec. 5.2, Eq. 3 (grid the element voltages with the element
+kernel, then the 2-D transform with the + sign) and Eq. 2 (polarisation outer
+product averaged over the cadence).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "epic_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_build", "libepic_oracle.so")
+
+KERNEL_NEAREST = 0
+KERNEL_GAUSSIAN = 1
+VOLT_CI8 = 0
+VOLT_CF32 = 1
+VOLT_CF64 = 2
+
+ERR_ARG = -1
+ERR_OFFGRID = -2
+
+_lib = None
+
+
+def build(src: str = _SRC, out: str = _LIB_PATH, extra_flags: tuple = ()) -> str:
+    """Compile the C oracle with gcc (OpenMP, -O2, strict IEEE: no fast-math)."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           *extra_flags, src, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load (building first if needed) the C oracle; cached for the default path."""
+    global _lib
+    if path is None:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        path = _LIB_PATH
+    lib = ctypes.CDLL(path)
+    _declare(lib)
+    if path == _LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _declare(lib):
+    P = ctypes.c_void_p
+    i32, f64 = ctypes.c_int, ctypes.c_double
+    lib.eo_element_taps.argtypes = [f64, f64, f64, i32, i32, i32, i32, f64, P, P, P, P]
+    lib.eo_element_taps.restype = i32
+    lib.eo_plan.argtypes = [i32, P, f64, f64, i32, i32, i32, i32, f64, P, P, P, P]
+    lib.eo_plan.restype = i32
+    lib.eo_fft2_batched.argtypes = [P, ctypes.c_long, i32, i32]
+    lib.eo_fft2_batched.restype = None
+    lib.eo_dft2.argtypes = [P, P, i32, i32]
+    lib.eo_dft2.restype = None
+    lib.eo_power_mean.argtypes = [i32, i32, i32, i32, P, i32, P]
+    lib.eo_power_mean.restype = None
+    lib.eo_grid.argtypes = [i32, P, f64, f64, i32, i32, i32, i32, f64, i32, i32, P, i32, i32, P]
+    lib.eo_grid.restype = i32
+    lib.eo_image.argtypes = [i32, P, i32, P, f64, i32, i32, i32, i32, i32, i32, f64, i32, P,
+                             i32, i32, P]
+    lib.eo_image.restype = i32
+    lib.eo_max_threads.argtypes = []
+    lib.eo_max_threads.restype = i32
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code):
+        super().__init__(f"oracle error {code}")
+        self.code = code
+
+
+def _volt_type(volts: np.ndarray) -> tuple[int, np.ndarray]:
+    """Map a voltage array to (type code, contiguous raw array).
+
+    complex64 -> cf32, complex128 -> cf64, int8 with a trailing axis of 2
+    (re, im) -> ci8."""
+    if volts.dtype == np.complex64:
+        return VOLT_CF32, np.ascontiguousarray(volts)
+    if volts.dtype == np.complex128:
+        return VOLT_CF64, np.ascontiguousarray(volts)
+    if volts.dtype == np.int8:
+        assert volts.shape[-1] == 2, "ci8 voltages carry a trailing (re, im) axis"
+        return VOLT_CI8, np.ascontiguousarray(volts)
+    raise TypeError(f"unsupported voltage dtype {volts.dtype}")
+
+
+def plan(pos_m, wavelength_m, grid_spacing_wl, nx, ny, kernel_type, K, sigma_cells,
+         lib=None):
+    """Per-element nearest cells and separable kernel weights (Sec. 5.2, Eq. 3).
+
+    Returns (ix, iy, wx, wy) with wx, wy of shape [n_elem, K]."""
+    lib = lib or load()
+    pos = np.ascontiguousarray(pos_m, dtype=np.float64)
+    n = pos.shape[0]
+    ix = np.zeros(n, np.int32)
+    iy = np.zeros(n, np.int32)
+    wx = np.zeros((n, K), np.float64)
+    wy = np.zeros((n, K), np.float64)
+    rc = lib.eo_plan(n, _ptr(pos), float(wavelength_m), float(grid_spacing_wl), nx, ny,
+                     kernel_type, K, float(sigma_cells), _ptr(ix), _ptr(iy), _ptr(wx), _ptr(wy))
+    if rc != 0:
+        raise OracleError(rc)
+    return ix, iy, wx, wy
+
+
+def grid(pos_m, wavelength_m, grid_spacing_wl, nx, ny, kernel_type, K, sigma_cells, volts,
+         t0=0, nt=None, lib=None):
+    """Gridded field G (inner bracket of Eq. 3) of one channel.
+
+    volts: [n_time, n_elem, n_pol] complex (or [..., 2] int8).  Returns
+    complex128 [nt, n_pol, ny, nx]."""
+    lib = lib or load()
+    vt, v = _volt_type(volts)
+    n_time, n_elem, n_pol = v.shape[:3]
+    nt = n_time - t0 if nt is None else nt
+    pos = np.ascontiguousarray(pos_m, dtype=np.float64)
+    out = np.zeros((nt, n_pol, ny, nx), np.complex128)
+    rc = lib.eo_grid(n_elem, _ptr(pos), float(wavelength_m), float(grid_spacing_wl), nx, ny,
+                     kernel_type, K, float(sigma_cells), n_pol, vt, _ptr(v), t0, nt, _ptr(out))
+    if rc != 0:
+        raise OracleError(rc)
+    return out
+
+
+def fft2(data: np.ndarray, lib=None) -> np.ndarray:
+    """Unnormalised 2-D transform with the + sign of Eq. 3 over the last two
+    axes, by the oracle's own radix-2 FFT.  Returns complex128."""
+    lib = lib or load()
+    a = np.array(data, dtype=np.complex128, copy=True, order="C")
+    ny, nx = a.shape[-2:]
+    lib.eo_fft2_batched(_ptr(a), a.size // (nx * ny), nx, ny)
+    return a
+
+
+def dft2(data: np.ndarray, lib=None) -> np.ndarray:
+    """The same transform as fft2, as a direct O(N^4) sum (small grids only)."""
+    lib = lib or load()
+    a = np.ascontiguousarray(data, dtype=np.complex128)
+    ny, nx = a.shape[-2:]
+    flat = a.reshape(-1, ny, nx)
+    out = np.zeros_like(flat)
+    for b in range(flat.shape[0]):
+        lib.eo_dft2(_ptr(flat[b]), _ptr(out[b]), nx, ny)
+    return out.reshape(a.shape)
+
+
+def power_mean(field: np.ndarray, n_div: int = 0, lib=None) -> np.ndarray:
+    """Eq. 2 on a per-sample field [nt, n_pol, ny, nx]: returns complex128
+    [n_pol*n_pol, ny, nx] = sum_t F^a conj(F^b) / (n_div or nt)."""
+    lib = lib or load()
+    f = np.ascontiguousarray(field, dtype=np.complex128)
+    nt, n_pol, ny, nx = f.shape
+    out = np.zeros((n_pol * n_pol, ny, nx), np.complex128)
+    lib.eo_power_mean(n_pol, nx, ny, nt, _ptr(f), int(n_div), _ptr(out))
+    return out
+
+
+def image(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K, sigma_cells,
+          volts, use_dft=False, n_threads=0, lib=None):
+    """EPIC image of one station (Eq. 3 then Eq. 2) for every channel.
+
+    volts: [n_chan, n_time, n_elem, n_pol] complex64/complex128, or
+    [n_chan, n_time, n_elem, n_pol, 2] int8.  Returns complex128
+    [n_chan, n_pol*n_pol, ny, nx] (mean over n_time, products XX, XY, YX, YY)."""
+    lib = lib or load()
+    vt, v = _volt_type(volts)
+    n_chan, n_time, n_elem, n_pol = v.shape[:4]
+    lam = np.ascontiguousarray(wavelengths_m, dtype=np.float64)
+    assert lam.shape == (n_chan,)
+    pos = np.ascontiguousarray(pos_m, dtype=np.float64)
+    assert pos.shape == (n_elem, 2)
+    out = np.zeros((n_chan, n_pol * n_pol, ny, nx), np.complex128)
+    rc = lib.eo_image(n_elem, _ptr(pos), n_chan, _ptr(lam), float(grid_spacing_wl), n_time,
+                      n_pol, nx, ny, kernel_type, K, float(sigma_cells), vt, _ptr(v),
+                      1 if use_dft else 0, int(n_threads), _ptr(out))
+    if rc != 0:
+        raise OracleError(rc)
+    return out
+
+
+def max_threads(lib=None) -> int:
+    return (lib or load()).eo_max_threads()
+
+
+def image_error(img: np.ndarray, ref: np.ndarray, n_pol: int) -> np.ndarray:
+    """Per-image error: max |I - I_ref| over pixels divided by the image scale.
+
+    The scale is max |I_ref^{aa}| for the auto products and
+    sqrt(max I_ref^{XX} * max I_ref^{YY}) for the cross products (their
+    Cauchy-Schwarz bound); a per-pixel relative error is meaningless where a
+    cross product crosses zero.  img, ref: [..., n_pol*n_pol, ny, nx].
+    Returns [..., n_pol*n_pol]."""
+    img = np.asarray(img)
+    ref = np.asarray(ref)
+    diff = np.abs(img - ref).max(axis=(-1, -2))
+    auto = np.stack([np.abs(ref[..., a * n_pol + a, :, :]).max(axis=(-1, -2))
+                     for a in range(n_pol)], axis=-1)
+    scale = np.empty(diff.shape, np.float64)
+    for a in range(n_pol):
+        for b in range(n_pol):
+            scale[..., a * n_pol + b] = np.sqrt(auto[..., a] * auto[..., b])
+    return diff / np.maximum(scale, np.finfo(np.float64).tiny)

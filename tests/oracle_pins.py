@@ -1,0 +1,290 @@
+"""Pins of the FP64 oracle to facts fixed outside the oracle itself.
+
+Each ``pin_*`` function takes a loaded oracle library (so the mutation test can
+run it against deliberately broken builds of the oracle) and returns a
+non-negative error that is ~1e-12 or smaller when the oracle is right.  The
+thresholds live in ``PIN_TOL``.
+
+What each pin is tied to:
+
+* pin_fft_vs_bruteforce   -- the transform of Eq. 3 evaluated as a direct sum
+                             (brute force) and by numpy's FFT library routine.
+* pin_bf_equivalence      -- Eq. 1 (voltage beamforming over elements, not
+                             cells) for elements on cell centres: EPIC with a
+                             nearest-cell kernel must give the same image.
+* pin_parseval            -- Parseval's theorem on the unnormalised transform.
+* pin_point_source_centre -- a common signal on every element: the (0,0) pixel
+                             is N_e^2 <|A|^2> and is the image maximum.
+* pin_point_source_offset -- a plane wave from pixel k lands on pixel +k (sign).
+* pin_xfft_equivalence    -- Eq. 4 then Eq. 6: visibilities (autocorrelations
+                             included) gridded with the cross-correlated element
+                             kernels and transformed equal the EPIC image
+                             (Wiener-Khinchin on the circular grid).
+* pin_translation         -- shifting every element by whole cells leaves the
+                             power image unchanged.
+* pin_pol_symmetry        -- YX = conj(XY) and Im XX = 0 exactly, XX >= 0.
+* pin_golden_two_element  -- the hand-derived 4-cell example in tests/golden.
+* pin_weights_closed_form -- the Gaussian weights' closed forms in tests/golden.
+* pin_numpy_crosscheck    -- the separately written numpy oracle.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+import oracle
+from oracle import numpy_oracle as npo
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+PIN_TOL = {
+    "fft_vs_bruteforce": 1e-12,
+    "bf_equivalence": 1e-12,
+    "parseval": 1e-12,
+    "point_source_centre": 1e-12,
+    "point_source_offset": 1e-12,
+    "xfft_equivalence": 1e-12,
+    "translation": 1e-12,
+    "pol_symmetry": 0.0,
+    "golden_two_element": 1e-13,
+    "weights_closed_form": 1e-14,
+    "numpy_crosscheck": 1e-12,
+}
+
+
+def _rng(tag):
+    return np.random.default_rng([17804, tag])
+
+
+def _cnormal(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def pin_fft_vs_bruteforce(lib):
+    rng = _rng(1)
+    worst = 0.0
+    for ny, nx in [(4, 8), (8, 8), (16, 16), (16, 4), (2, 16)]:
+        g = _cnormal(rng, (2, ny, nx))
+        f = oracle.fft2(g, lib=lib)
+        d = oracle.dft2(g, lib=lib)
+        ref = np.fft.ifft2(g, axes=(-2, -1)) * (nx * ny)
+        # the direct sum itself, written out for one output pixel as a third witness
+        ky, kx = ny // 2 - 1, 1
+        yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        one = np.sum(g[0] * np.exp(2j * np.pi * (kx * xx / nx + ky * yy / ny)))
+        worst = max(worst, _rel(f, d), _rel(f, ref), abs(f[0, ky, kx] - one) / np.abs(ref).max())
+    return worst
+
+
+def _on_grid_layout(rng, n_elem, nx, ny, lam, dwl, margin):
+    delta = dwl * lam
+    cells = set()
+    while len(cells) < n_elem:
+        cells.add((int(rng.integers(margin, nx - margin)), int(rng.integers(margin, ny - margin))))
+    cells = np.array(sorted(cells))
+    pos = np.stack([(cells[:, 0] - nx // 2) * delta, (cells[:, 1] - ny // 2) * delta], axis=1)
+    return pos
+
+
+def pin_bf_equivalence(lib):
+    rng = _rng(2)
+    nx, ny, lam, dwl = 16, 8, 2.0, 0.5
+    pos = _on_grid_layout(rng, 11, nx, ny, lam, dwl, 0)
+    n_time, n_pol = 5, 2
+    E = _cnormal(rng, (1, n_time, pos.shape[0], n_pol))
+    img = oracle.image(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_NEAREST, 1, 0.0, E,
+                       lib=lib)[0]
+    # Eq. 1 with unit directional weights: beamform towards every pixel direction
+    kx = np.fft.fftfreq(nx, 1.0 / nx)            # natural order, signed k'
+    ky = np.fft.fftfreq(ny, 1.0 / ny)
+    l = kx / (nx * dwl)
+    m = ky / (ny * dwl)
+    phase = np.exp(2j * np.pi * (m[:, None, None] * pos[None, None, :, 1]
+                                 + l[None, :, None] * pos[None, None, :, 0]) / lam)  # [ny,nx,a]
+    beam = np.einsum("yxa,tap->tpyx", phase, E[0])
+    ref = np.stack([np.mean(beam[:, a] * np.conj(beam[:, b]), axis=0)
+                    for a in range(n_pol) for b in range(n_pol)])
+    return _rel(img, ref)
+
+
+def pin_parseval(lib):
+    rng = _rng(3)
+    nx, ny, lam, dwl, K, sig = 16, 16, 2.0, 0.5, 3, 0.5
+    pos = rng.uniform(-3.0, 3.0, (9, 2))
+    E = _cnormal(rng, (1, 7, 9, 2))
+    img = oracle.image(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, E,
+                       lib=lib)[0]
+    G = oracle.grid(pos, lam, dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, E[0], lib=lib)
+    worst = 0.0
+    for a in range(2):
+        for b in range(2):
+            lhs = img[a * 2 + b].sum()
+            rhs = nx * ny * np.mean(np.sum(G[:, a] * np.conj(G[:, b]), axis=(-1, -2)))
+            worst = max(worst, abs(lhs - rhs) / abs(img[0].sum()))
+    return worst
+
+
+def pin_point_source_centre(lib):
+    rng = _rng(4)
+    nx, ny, lam, dwl, K, sig = 32, 32, 2.0, 0.5, 3, 0.5
+    pos = rng.uniform(-6.0, 6.0, (13, 2))
+    A = _cnormal(rng, 6)
+    E = np.broadcast_to(A[None, :, None, None], (1, 6, 13, 1)).copy()
+    img = oracle.image(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, E,
+                       lib=lib)[0, 0].real
+    expect = 13 ** 2 * np.mean(np.abs(A) ** 2)
+    err = abs(img[0, 0] - expect) / expect
+    if img.max() > img[0, 0] * (1 + 1e-12):
+        err = max(err, 1.0)
+    return err
+
+
+def pin_point_source_offset(lib):
+    rng = _rng(5)
+    nx, ny, lam, dwl = 16, 16, 2.0, 0.5
+    pos = _on_grid_layout(rng, 12, nx, ny, lam, dwl, 0)
+    kxp, kyp = 3, -5                             # signed pixel of the source
+    l, m = kxp / (nx * dwl), kyp / (ny * dwl)
+    A = _cnormal(rng, 4)
+    phase = np.exp(-2j * np.pi * (l * pos[:, 0] + m * pos[:, 1]) / lam)
+    E = (A[:, None] * phase[None, :])[None, :, :, None]
+    img = oracle.image(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_NEAREST, 1, 0.0, E,
+                       lib=lib)[0, 0].real
+    expect = 12 ** 2 * np.mean(np.abs(A) ** 2)
+    err = abs(img[kyp % ny, kxp % nx] - expect) / expect
+    if np.unravel_index(np.argmax(img), img.shape) != (kyp % ny, kxp % nx):
+        err = max(err, 1.0)
+    return err
+
+
+def pin_xfft_equivalence(lib):
+    rng = _rng(6)
+    nx, ny, lam, dwl, K, sig = 16, 16, 2.0, 0.5, 3, 0.5
+    n_el, n_time, n_pol = 10, 9, 2
+    pos = rng.uniform(-3.5, 3.5, (n_el, 2))
+    E = _cnormal(rng, (1, n_time, n_el, n_pol))
+    img = oracle.image(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, E,
+                       lib=lib)[0]
+    ix, iy, wx, wy = oracle.plan(pos, lam, dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, lib=lib)
+    # Eq. 4: visibilities including the a = b autocorrelations, averaged over time
+    V = np.einsum("tap,tbq->pqab", E[0], np.conj(E[0])) / n_time
+    h = (K - 1) // 2
+    ref = np.zeros((n_pol * n_pol, ny, nx), np.complex128)
+    for p in range(n_pol):
+        for q in range(n_pol):
+            Gv = np.zeros((ny, nx), np.complex128)
+            # Eq. 6 gridding with B_ab = w_a (cross-correlated with) w_b
+            for d1y in range(-h, h + 1):
+                for d1x in range(-h, h + 1):
+                    wa = wx[:, d1x + h] * wy[:, d1y + h]
+                    for d2y in range(-h, h + 1):
+                        for d2x in range(-h, h + 1):
+                            wb = wx[:, d2x + h] * wy[:, d2y + h]
+                            cx = ((ix + d1x)[:, None] - (ix + d2x)[None, :]) % nx
+                            cy = ((iy + d1y)[:, None] - (iy + d2y)[None, :]) % ny
+                            np.add.at(Gv, (cy, cx), wa[:, None] * wb[None, :] * V[p, q])
+            ref[p * n_pol + q] = np.fft.ifft2(Gv) * (nx * ny)
+    return _rel(img, ref)
+
+
+def pin_translation(lib):
+    rng = _rng(7)
+    nx, ny, lam, dwl, K, sig = 32, 32, 2.0, 0.5, 3, 0.5
+    pos = rng.uniform(-4.0, 4.0, (15, 2))
+    E = _cnormal(rng, (1, 4, 15, 2))
+    a = oracle.image(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, E, lib=lib)
+    shift = np.array([3.0, -2.0]) * dwl * lam
+    b = oracle.image(pos + shift, np.array([lam]), dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, E,
+                     lib=lib)
+    return _rel(b, a)
+
+
+def pin_pol_symmetry(lib):
+    rng = _rng(8)
+    nx, ny, lam, dwl, K, sig = 16, 16, 2.0, 0.5, 3, 0.5
+    pos = rng.uniform(-3.0, 3.0, (8, 2))
+    E = _cnormal(rng, (2, 5, 8, 2))
+    img = oracle.image(pos, np.array([lam, 2.1]), dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, E,
+                       lib=lib)
+    bad = 0.0
+    bad += float(np.max(np.abs(img[:, 2] - np.conj(img[:, 1]))))
+    bad += float(np.max(np.abs(img[:, 0].imag))) + float(np.max(np.abs(img[:, 3].imag)))
+    bad += float(max(0.0, -img[:, 0].real.min())) + float(max(0.0, -img[:, 3].real.min()))
+    return bad
+
+
+def pin_golden_two_element(lib):
+    g = json.load(open(os.path.join(GOLDEN, "two_element_fringe.json")))
+    vx = np.array([complex(*v) for v in g["volts_x"]])
+    vy = np.array([complex(*v) for v in g["volts_y"]])
+    E = np.stack([vx, vy], axis=-1)[None, None]          # [1 chan, 1 time, 2 el, 2 pol]
+    img = oracle.image(np.array(g["pos_m"]), np.array([g["wavelength_m"]]), g["grid_spacing_wl"],
+                       g["nx"], g["ny"], oracle.KERNEL_NEAREST, 1, 0.0, E, lib=lib)[0]
+    worst = 0.0
+    for i, name in enumerate(["XX", "XY", "YX", "YY"]):
+        want = np.array([complex(*v) for v in g[name]]).reshape(g["ny"], g["nx"])
+        worst = max(worst, float(np.max(np.abs(img[i] - want))))
+    return worst
+
+
+def pin_weights_closed_form(lib):
+    g = json.load(open(os.path.join(GOLDEN, "gaussian_weights.json")))
+    worst = 0.0
+    nx = ny = 16
+    lam, dwl = 2.0, 0.5
+    delta = lam * dwl
+    for case in g["cases"]:
+        K, sig, off = case["K"], case["sigma"], case["offset_cells"]
+        # element off cell 5 by `off` cells in x and by -off in y
+        pos = np.array([[(5 + off - nx // 2) * delta, (9 - off - ny // 2) * delta]])
+        ix, iy, wx, wy = oracle.plan(pos, lam, dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, lib=lib)
+        want = np.array(case["w"])
+        # x: offset +off; round-half-up moves +0.5 to the next cell
+        want_ix = 6 if off == 0.5 else 5
+        worst = max(worst, float(np.max(np.abs(wx[0] - want))))
+        # y: offset -off is the mirror image (for -0.5 the cell stays, offset -0.5)
+        want_y = want[::-1] if off != 0.5 else np.array(case["w"])
+        worst = max(worst, float(np.max(np.abs(wy[0] - want_y))))
+        if ix[0] != want_ix or iy[0] != 9:
+            worst = max(worst, 1.0)
+    return worst
+
+
+def pin_numpy_crosscheck(lib):
+    import workloads as W
+    cfg = W.make_config(1, n_time=32)
+    st = cfg.stations[0]
+    v = W.station_volts(cfg, 0)
+    a = oracle.image(st.pos_m, cfg.wavelengths_m, W.GRID_SPACING_WL, st.nx, st.ny,
+                     st.kernel_type, st.support, st.sigma_cells, v, lib=lib)
+    b = npo.image(st.pos_m, cfg.wavelengths_m, W.GRID_SPACING_WL, st.nx, st.ny, st.support,
+                  st.sigma_cells, True, v)
+    cfg2 = W.make_config(2, n_chan=2, n_time=4)
+    st2 = cfg2.stations[0]
+    v2 = W.station_volts(cfg2, 0)
+    c = oracle.image(st2.pos_m, cfg2.wavelengths_m, W.GRID_SPACING_WL, st2.nx, st2.ny,
+                     st2.kernel_type, st2.support, st2.sigma_cells, v2, lib=lib)
+    d = npo.image(st2.pos_m, cfg2.wavelengths_m, W.GRID_SPACING_WL, st2.nx, st2.ny, st2.support,
+                  st2.sigma_cells, False, v2)
+    return max(_rel(a, b), _rel(c, d))
+
+
+ALL_PINS = {
+    "fft_vs_bruteforce": pin_fft_vs_bruteforce,
+    "bf_equivalence": pin_bf_equivalence,
+    "parseval": pin_parseval,
+    "point_source_centre": pin_point_source_centre,
+    "point_source_offset": pin_point_source_offset,
+    "xfft_equivalence": pin_xfft_equivalence,
+    "translation": pin_translation,
+    "pol_symmetry": pin_pol_symmetry,
+    "golden_two_element": pin_golden_two_element,
+    "weights_closed_form": pin_weights_closed_form,
+    "numpy_crosscheck": pin_numpy_crosscheck,
+}

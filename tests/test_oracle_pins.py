@@ -1,0 +1,112 @@
+"""The FP64 oracle against facts fixed outside it (CPU only).
+
+See tests/oracle_pins.py for what each pin is tied to.  The mutation test
+compiles deliberately broken copies of the oracle (one plausible mistake each:
+a flipped sign, a dropped conjugate, transposed axes, a missing normalisation,
+...) and checks that every one of them fails at least one pin other than the
+numpy cross-check.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import oracle_pins as P
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return oracle.load()
+
+
+@pytest.mark.parametrize("name", sorted(P.ALL_PINS))
+def test_pin(lib, name):
+    err = P.ALL_PINS[name](lib)
+    assert err <= P.PIN_TOL[name], f"pin {name}: error {err:.3e} > {P.PIN_TOL[name]:.1e}"
+
+
+def test_offgrid_is_an_error(lib):
+    # an element whose 3x3 footprint crosses the grid edge (never wrapped)
+    pos = np.array([[-7.6, 0.0]])                 # u = 0.4 -> cell 0, footprint -1..1
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.plan(pos, 2.0, 0.5, 16, 16, oracle.KERNEL_GAUSSIAN, 3, 0.5, lib=lib)
+    assert e.value.code == oracle.ERR_OFFGRID
+    with pytest.raises(oracle.OracleError):
+        oracle.plan(pos, 2.0, 0.5, 16, 16, oracle.KERNEL_NEAREST, 3, 0.5, lib=lib)  # K must be 1
+
+
+def test_channel_geometry_scales_with_wavelength(lib):
+    # the grid is fixed in wavelengths: doubling lambda halves the cell offset of an element
+    pos = np.array([[4.0, -2.0]])
+    ix1, iy1, _, _ = oracle.plan(pos, 1.0, 0.5, 32, 32, oracle.KERNEL_NEAREST, 1, 0.0, lib=lib)
+    ix2, iy2, _, _ = oracle.plan(pos, 2.0, 0.5, 32, 32, oracle.KERNEL_NEAREST, 1, 0.0, lib=lib)
+    assert (ix1[0] - 16, iy1[0] - 16) == (8, -4)
+    assert (ix2[0] - 16, iy2[0] - 16) == (4, -2)
+
+
+def test_ci8_conversion_is_exact(lib):
+    rng = np.random.default_rng(3)
+    raw = rng.integers(-127, 128, (1, 3, 5, 2, 2)).astype(np.int8)
+    as_c = (raw[..., 0].astype(np.float64) + 1j * raw[..., 1]).astype(np.complex128)
+    pos = rng.uniform(-2, 2, (5, 2))
+    a = oracle.image(pos, np.array([2.0]), 0.5, 16, 16, oracle.KERNEL_GAUSSIAN, 3, 0.5, raw, lib=lib)
+    b = oracle.image(pos, np.array([2.0]), 0.5, 16, 16, oracle.KERNEL_GAUSSIAN, 3, 0.5, as_c, lib=lib)
+    assert np.array_equal(a, b)
+
+
+# (source fragment, replacement) -- each a plausible slip in the oracle
+MUTANTS = {
+    "transform_sign": ("const double ang = EO_TWO_PI *", "const double ang = -EO_TWO_PI *"),
+    "dropped_conj": ("s[k] += fa[k] * conj(fb[k]);", "s[k] += fa[k] * fb[k];"),
+    "transposed_cells": ("(size_t)(iy[a] + dy) * nx + (ix[a] + dx)",
+                         "(size_t)(ix[a] + dx) * nx + (iy[a] + dy)"),
+    "unnormalised_kernel": ("wx[d] /= sx;", "wx[d] /= 1.0;"),
+    "mean_divisor": ("out[k] = S[k] / (double)n_time;", "out[k] = S[k] / (double)(n_time + 1);"),
+    "offset_sign": ("const double ex = ((double)d - du)", "const double ex = ((double)d + du)"),
+    "product_order": ("S + (size_t)(a * n_pol + b) * npix", "S + (size_t)(b * n_pol + a) * npix"),
+    "twiddle_index": ("const double complex w = eo_root(k, len);",
+                      "const double complex w = eo_root(k, n);"),
+    "rounding": ("const double ci = floor(u + 0.5);", "const double ci = floor(u);"),
+    "origin": ("const double u = x_m / delta_m + (double)(nx / 2);",
+               "const double u = x_m / delta_m + (double)(nx / 2) + 0.5;"),
+}
+
+
+_RUN_PINS = """
+import sys, numpy as np
+sys.path.insert(0, {root!r})
+import oracle
+from tests import oracle_pins as P
+lib = oracle.load({so!r})
+for name, fn in P.ALL_PINS.items():
+    if name == "numpy_crosscheck":
+        continue
+    try:
+        err = fn(lib)
+    except oracle.OracleError:
+        err = np.inf
+    if not err <= P.PIN_TOL[name]:
+        print("FAILED", name, flush=True)
+"""
+
+
+@pytest.mark.parametrize("mutant", sorted(MUTANTS))
+def test_every_plausible_mistake_fails_a_pin(mutant):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "epic_oracle.c")).read()
+    frag, repl = MUTANTS[mutant]
+    assert src.count(frag) == 1, f"mutation fragment for {mutant} not found exactly once"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "mut.c")
+        with open(path, "w") as f:
+            f.write(src.replace(frag, repl))
+        so = oracle.build(src=path, out=os.path.join(d, "libmut.so"))
+        # a mutant may also write out of bounds and crash: that counts as caught
+        r = subprocess.run([sys.executable, "-c", _RUN_PINS.format(root=root, so=so)],
+                           capture_output=True, text=True, timeout=300)
+        caught = "FAILED" in r.stdout or r.returncode != 0
+        assert caught, f"mutant {mutant} passes every paper/maths pin"
