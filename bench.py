@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Throughput of the EPIC imager hot path on one MI355X.
+
+A step is one whole cadence through image_cadence: every channel and every
+time sample of the workload is gridded, transformed, squared and averaged
+(Eq. 3 then Eq. 2).  The default workload is the station-scale layout: 256
+elements in a 38 m circle (1.5 m minimum spacing), 150 MHz, 64x64 grid at
+lambda/2, 3x3 Gaussian kernel, 2 pols, 1024 channels, 2048 samples per
+cadence, int8 complex voltages (sigma 16), FP32 FFT path.  Inputs are seeded,
+synthetic and already resident in HBM when the timed region starts.
+
+Prints one JSON line: grid pixel-samples/s (sum over stations of
+nx*ny*n_chan*n_time per cadence, divided by the cadence time), the roofline
+of the dominant kernel (timed live with HIP events on its own stream), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+# FP32 vector peak without packed FP32 math (the library is built with it off):
+# 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz.  The 157.3 TFLOP/s figure
+# counts packed FP32 (two FMAs per lane per instruction).
+PEAK_FP32_VALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+PEAK_FP16_MFMA_TFLOPS = 2500.0
+PREC_NAMES = {"fp32": W.FP32_FFT, "fp16": W.FP16_SPLIT, "bf16": W.BF16_SPLIT}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def flops_per_pixel_sample(cfg, st):
+    """Algorithmic FP32 work per grid pixel-sample of the FFT path.
+
+    transform: 5 N log2 N per complex N-point transform, per pol;
+    gridding: 4 flops (complex x real weight, complex add) per tap per pol;
+    products: XX and YY 3 flops each, XY 6 (YX is its conjugate); accumulation:
+    one add per real component (4 for two pols, 1 for one)."""
+    npix = st.nx * st.ny
+    fft = cfg.n_pol * 5.0 * math.log2(npix)
+    grid = 4.0 * st.n_elem * st.support ** 2 * cfg.n_pol / npix
+    prod = 12.0 + 4.0 if cfg.n_pol == 2 else 3.0 + 1.0
+    return fft + grid + prod
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--precision", choices=sorted(PREC_NAMES), default="fp32")
+    ap.add_argument("--n-chan", type=int, default=None, help="shrink the band (testing)")
+    ap.add_argument("--n-time", type=int, default=None, help="shrink the cadence (testing)")
+    ap.add_argument("--cpu-channels", type=int, default=64,
+                    help="channels of the workload the CPU oracle is timed on")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the path shards by channel "
+                          "with no exchange, and only the single-GPU figure is measured",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2411_17804_amd import epic
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    epic.load()
+
+    cfg = W.make_config(args.config, n_chan=args.n_chan, n_time=args.n_time,
+                        precision=PREC_NAMES[args.precision])
+    log(f"workload C{cfg.index}: {len(cfg.stations)} station(s), {cfg.n_chan} channels x "
+        f"{cfg.n_time} samples, precision {args.precision}")
+    t_gen = time.time()
+    stations = []
+    host_volts = []
+    for s, st in enumerate(cfg.stations):
+        v = W.station_volts(cfg, s, threads=16)
+        host_volts.append(v if not args.no_cpu_baseline else None)
+        if v.dtype == np.int8:
+            vd = torch.from_numpy(v).to(dev)
+        else:
+            vd = torch.from_numpy(v.view(np.float32)).to(dev)
+        img = torch.zeros((cfg.n_chan, cfg.n_pol * cfg.n_pol, st.ny, st.nx, 2),
+                          dtype=torch.float32, device=dev)
+        stations.append(epic.Station(st.pos_m, st.nx, st.ny, st.kernel_type, st.support,
+                                     st.sigma_cells, volts=vd, image=img))
+    common = epic.Common(cfg.n_pol, cfg.wavelengths_m, W.GRID_SPACING_WL, cfg.n_time,
+                         cfg.volt_type, cfg.precision)
+    torch.cuda.synchronize()
+    log(f"inputs generated and resident in HBM ({cfg.volt_bytes() / 1e9:.2f} GB) "
+        f"in {time.time() - t_gen:.1f} s")
+
+    for i in range(args.warmup):
+        epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} done")
+
+    epic.timing_reset()
+    epic.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    epic.timing_enable(False)
+    kern = epic.timing_report()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    pix = cfg.pixel_samples()
+    value = pix / (ms_per_step / 1e3)
+    log(f"{args.steps} steps: {ms_per_step:.2f} ms/step, {value:.3e} px-samples/s; kernels {kern}")
+
+    # dominant kernel and its roofline
+    dom_name, (dom_count, dom_ms) = max(kern.items(), key=lambda kv: kv[1][1])
+    dom_avg_ms = dom_ms / dom_count
+    launches_per_step = dom_count / args.steps
+    st0 = cfg.stations[0]
+    if args.precision == "fp32":
+        flop_px = flops_per_pixel_sample(cfg, st0)
+        work = flop_px * pix / launches_per_step
+        achieved = work / (dom_avg_ms / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3),
+                "peak": round(PEAK_FP32_VALU_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
+                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4),
+                "flop_per_pixel_sample": round(flop_px, 2)}
+    else:
+        roof = {"bound": "mfma", "achieved": None, "peak": PEAK_FP16_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": None, "traffic": None, "kernel": dom_name,
+                "avg_launch_ms": round(dom_avg_ms, 4)}
+
+    out = {
+        "metric": "grid pixel-samples/s per GPU",
+        "value": value,
+        "unit": "pixel-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16": "f16x3+f32acc", "bf16": "bf16x3+f32acc"}[args.precision],
+        "data": "synthetic (seeded layouts and voltages shaped like the paper's arrays)",
+        "config": {"workload": f"C{cfg.index}: " + {
+            1: "64 el, 32x32 grid, nearest, 1 pol, cf32",
+            2: "station: 256 el in 38 m circle, 64x64 grid, 3x3 Gaussian, 2 pols, ci8",
+            3: "dense 64x32 lattice, 128x128 grid, 3x3 Gaussian, 2 pols, cf32",
+            4: "96 stations of 64-1024 el, 32/64/128 grids, 2 pols, ci8",
+            5: "128x128 lattice -5%, 256x256 grid, 5x5 Gaussian, 2 pols, cf32"}[cfg.index],
+            "n_chan": cfg.n_chan, "n_time": cfg.n_time, "n_stations": len(cfg.stations),
+            "precision": args.precision, "pixel_samples_per_step": pix,
+            "realtime_factor": (cfg.n_time * 25e-6) / (ms_per_step / 1e3)},
+        "roofline": roof,
+        "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, stations, host_volts, args.cpu_channels)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cfg, stations, host_volts, n_sample_chan):
+    """Time the FP64 oracle on a bounded sample (the first station, a spread of
+    channels, every sample of the cadence) and check the GPU images there."""
+    import oracle
+    import torch
+    threads = min(16, os.cpu_count() or 1)
+    s = 0
+    st = cfg.stations[s]
+    n = min(n_sample_chan, cfg.n_chan)
+    chans = np.unique(np.linspace(0, cfg.n_chan - 1, n).astype(int))
+    v = host_volts[s][chans]
+    log(f"cpu_baseline: oracle on {len(chans)} channels x {cfg.n_time} samples, {threads} threads")
+    t0 = time.perf_counter()
+    ref = oracle.image(st.pos_m, cfg.wavelengths_m[chans], W.GRID_SPACING_WL, st.nx, st.ny,
+                       st.kernel_type, st.support, st.sigma_cells, v, n_threads=threads)
+    dt = time.perf_counter() - t0
+    a = stations[s].image[torch.as_tensor(chans, device=stations[s].image.device)].cpu().numpy()
+    got = a[..., 0].astype(np.float64) + 1j * a[..., 1]
+    err = oracle.image_error(got, ref, cfg.n_pol)
+    px = st.nx * st.ny * len(chans) * cfg.n_time
+    log(f"cpu_baseline: {dt:.1f} s, worst GPU error on the sample {err.max():.2e}")
+    return {"value": px / dt, "unit": "pixel-samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"station 0, {len(chans)} of {cfg.n_chan} channels (evenly spread), all "
+                      f"{cfg.n_time} samples; C99 FP64 oracle, OpenMP over channels",
+            "seconds": round(dt, 2), "gpu_max_error_on_sample": float(err.max())}
+
+
+if __name__ == "__main__":
+    main()

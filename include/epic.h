@@ -1,0 +1,198 @@
+/*
+ * epic.h -- C ABI of the EPIC direct-imager hot path on gfx950 (MI355X).
+ *
+ * The imager (Thyagarajan, "Comparison of Fast, Hybrid Imaging Architectures
+ * for Multi-scale, Hierarchical Aperture Arrays", Sec. 5.2) forms, for every
+ * channel and time sample, the gridded aperture field
+ *
+ *     G^p[j] = sum_a W~_a(r_j - r_a) E^p_a                        (Eq. 3, inner)
+ *
+ * transforms it to the sky,
+ *
+ *     F^p[k] = sum_j exp(+2 pi i k.j / N) G^p[j]                   (Eq. 3, outer)
+ *
+ * and averages the polarisation outer products over the cadence t_acc,
+ *
+ *     I^{ab}[k] = < F^a[k] conj(F^b[k]) >                           (Eq. 2).
+ *
+ * Conventions used by every call (the paper leaves them open):
+ *   - Channels are independent (Sec. 5.1).  The grid spacing is fixed in
+ *     wavelengths: channel c uses Delta_c = grid_spacing_wl * wavelength_m[c]
+ *     metres per cell, so sky pixels are the same directions in every channel.
+ *   - Element a sits at u = x/Delta_c + nx/2, v = y/Delta_c + ny/2 (cells),
+ *     nearest cell (floor(u+1/2), floor(v+1/2)).  The kernel covers the
+ *     support x support cells around the nearest cell.  NEAREST: support 1,
+ *     weight 1.  GAUSSIAN: separable exp(-d^2 / (2 sigma^2)) of the distance d
+ *     (cells) from the element's true position, normalised to unit sum.  The
+ *     kernel is real, so the conjugate of Eq. 3 changes nothing.  A footprint
+ *     that leaves the grid at any channel is an error (never wrapped).
+ *   - The transform has the + sign, no area factor (delta^2 r = 1) and
+ *     natural (unshifted) pixel order: pixel k <-> direction cosine
+ *     l = k'/(nx * grid_spacing_wl), k' = k - nx*[k >= nx/2]; same for m.
+ *   - Products are stored alpha-major: XX, XY, YX, YY (n_pol = 2) or XX
+ *     (n_pol = 1).  YX is written as the exact conjugate of XY; Im XX and
+ *     Im YY are exactly 0.
+ *   - Complex numbers are interleaved (re, im) pairs: "cf32" = 2 x float,
+ *     "ci8" = 2 x int8.
+ *
+ * Memory: device pointers are HIP device memory on the current device; host
+ * pointers are ordinary host memory, read during the call only.  The caller
+ * owns every buffer it passes.  The library owns its plan tables (kernel cells
+ * and weights per station and channel, uploaded once and cached by content),
+ * its transform tables and its workspaces; epic_cache_clear() frees them.
+ *
+ * Errors: every call validates all arguments before it launches anything and
+ * returns a status; 0 is success.  Launches are asynchronous on `stream`
+ * (NULL = the null stream); a fault inside a kernel surfaces at the caller's
+ * next synchronisation.  epic_last_error() gives a human-readable detail of
+ * the last failure on the calling thread.  Calls on different streams may run
+ * concurrently; the caches are internally locked.
+ */
+#ifndef EPIC_H
+#define EPIC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EPIC_OK = 0,
+    EPIC_ERR_INVALID_ARG = -1,   /* bad pointer, shape, enum or geometry */
+    EPIC_ERR_UNSUPPORTED = -2,   /* valid but not implemented here */
+    EPIC_ERR_OUT_OF_MEMORY = -3, /* a library-owned allocation failed */
+    EPIC_ERR_DEVICE = -4,        /* a HIP runtime call failed */
+    EPIC_ERR_INTERNAL = -5
+} epic_status;
+
+typedef enum { EPIC_CI8 = 0, EPIC_CF32 = 1 } epic_volt_type;
+
+/* How the 2-D transform is evaluated.
+ *   EPIC_FP32_FFT   : mixed-radix FFT in FP32 (adds and multiplies in FP32).
+ *   EPIC_FP16_SPLIT : dense DFT-matrix products F_y . X . F_x^T on FP16 matrix
+ *                     cores with FP32 accumulation; each operand is split into
+ *                     hi + lo FP16 parts and three products (hi.hi, hi.lo,
+ *                     lo.hi) are summed.  The DFT tables are generated in FP64.
+ *   EPIC_BF16_SPLIT : the same with BF16 parts. */
+typedef enum { EPIC_FP32_FFT = 0, EPIC_FP16_SPLIT = 1, EPIC_BF16_SPLIT = 2 } epic_precision;
+
+typedef enum { EPIC_KERNEL_NEAREST = 0, EPIC_KERNEL_GAUSSIAN = 1 } epic_kernel_type;
+
+/* Element gridding kernel W~ of Eq. 3.  support: odd, 1..7 (NEAREST: 1).
+ * sigma_cells: Gaussian width in cells (> 0; ignored for NEAREST). */
+typedef struct {
+    int32_t type;
+    int32_t support;
+    double sigma_cells;
+} epic_kernel;
+
+/* Parameters shared by all stations of one call. */
+typedef struct {
+    int32_t n_pol;                /* 1 or 2 */
+    int32_t n_chan;               /* >= 1 */
+    const double *wavelength_m;   /* host [n_chan], finite, > 0 */
+    double grid_spacing_wl;       /* cell size in wavelengths, > 0 (0.5 = lambda/2) */
+    int32_t n_time;               /* samples per cadence (t_acc / delta_t), >= 1 */
+    int32_t volt_type;            /* epic_volt_type */
+    int32_t precision;            /* epic_precision (image_cadence only) */
+} epic_common;
+
+/* One station: one independent imaging problem. */
+typedef struct {
+    int32_t n_elem;               /* >= 1 */
+    const double *pos_m;          /* host [n_elem][2]: x, y metres from the station phase centre */
+    int32_t nx, ny;               /* grid = image size; powers of two, 16..256 */
+    epic_kernel kernel;
+    const void *volts;            /* device [n_chan][n_time][n_elem][n_pol] of volt_type */
+    void *image;                  /* device out: cf32 [n_chan][n_pol*n_pol][ny][nx],
+                                     the mean over n_time (image_cadence only) */
+} epic_station;
+
+/*
+ * Gridding (Eq. 3, inner bracket) of samples t0 .. t0+nt-1 of every channel
+ * of one station.  Writes every cell of
+ *     grid: device cf32 [n_chan][nt][n_pol][ny][nx]
+ * (cells outside the kernel footprints are written as 0).  The gridded value
+ * of a cell is the FP32 sum of weight * voltage over the element taps that
+ * land on it, in ascending element order (deterministic; no atomics).
+ * station->image is not used.  0 <= t0, nt >= 1, t0 + nt <= common->n_time.
+ */
+epic_status grid_voltages(const epic_common *common, const epic_station *station,
+                          int32_t t0, int32_t nt, void *grid, hipStream_t stream);
+
+/*
+ * Batched 2-D transform of Eq. 3 (outer sum):
+ *     out[b][ky][kx] = sum_{y,x} in[b][y][x] exp(+2 pi i (kx x/nx + ky y/ny))
+ * in, out: device cf32 [batch][ny][nx]; nx, ny powers of two in 16..256;
+ * batch >= 1.  Unnormalised, natural order.  in == out is allowed for every
+ * precision (the split paths stage through a library-owned workspace).
+ */
+epic_status fft2_batched(int32_t nx, int32_t ny, int64_t batch, int32_t precision,
+                         const void *in, void *out, hipStream_t stream);
+
+/*
+ * Squaring and accumulation (Eq. 2) of nt samples of a per-sample field:
+ *     field: device cf32 [n_chan][nt][n_pol][ny][nx]
+ *     acc_sum, acc_comp: device cf32 [n_chan][n_pol*n_pol][ny][nx], the running
+ *         compensated sum (sum + comp) of F^a conj(F^b).  Zero them before the
+ *         first call of a cadence; keep them across calls to split a cadence.
+ * Each sample is added with an error-free two-sum, so a cadence split over
+ * several calls gives bit-identical results to one call over the same samples
+ * in the same order.  If finalize_n_time > 0 the mean
+ *     image = (acc_sum + acc_comp) * (1 / finalize_n_time)
+ * is also written to image (device cf32, same shape as acc_sum); otherwise
+ * image is not touched and may be NULL.
+ */
+epic_status accumulate_power(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_chan, int32_t nt,
+                             const void *field, void *acc_sum, void *acc_comp,
+                             int32_t finalize_n_time, void *image, hipStream_t stream);
+
+/*
+ * The whole cadence, all steps fused (Eq. 3 then Eq. 2): for every station
+ * and channel, grid each sample, transform it with common->precision, form the
+ * products and average them over common->n_time samples into station->image.
+ * Stations may differ in element count, layout, grid size and kernel; all of
+ * them run in one pass.  Plan tables are built on the host in FP64 on the first
+ * call for a geometry and reused afterwards.
+ */
+epic_status image_cadence(const epic_common *common, const epic_station *stations,
+                          int32_t n_stations, hipStream_t stream);
+
+/*
+ * Host-only check of everything image_cadence would check (arguments and
+ * geometry: every element's kernel footprint inside its grid at every
+ * channel), without touching a device.  Returns EPIC_OK or the error
+ * image_cadence would return; the volts and image pointers are not checked.
+ */
+epic_status epic_validate(const epic_common *common, const epic_station *stations,
+                          int32_t n_stations);
+
+/*
+ * Kernel timing (auxiliary instrumentation, off by default).  While enabled,
+ * every kernel the library launches is bracketed by a pair of HIP events
+ * recorded on the kernel's own stream.  epic_timing_report() waits for the
+ * recorded events and writes one line per kernel name, "name count total_ms",
+ * into buf (NUL-terminated, truncated to len); it returns the number of
+ * kernel names.  epic_timing_reset() drops the records.
+ */
+void epic_timing_enable(int32_t enable);
+int32_t epic_timing_report(char *buf, int32_t len);
+void epic_timing_reset(void);
+
+/* Static name of a status code. */
+const char *epic_status_string(epic_status status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *epic_last_error(void);
+
+/* Free every library-owned device table, workspace and graph.  Must not race
+ * with calls in flight on any stream. */
+void epic_cache_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPIC_H */

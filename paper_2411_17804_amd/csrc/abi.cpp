@@ -1,0 +1,288 @@
+// abi.cpp -- the C ABI of include/epic.h: argument validation, plan lookup
+// and dispatch to the HIP kernels.  No device work happens before every
+// argument has been checked.
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace epic {
+const char *last_error_cstr();
+}
+
+using namespace epic;
+
+namespace {
+
+bool is_pow2_grid(int n) { return n >= 16 && n <= 256 && (n & (n - 1)) == 0; }
+
+int ilog2(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+epic_status check_common(const epic_common *c)
+{
+    if (!c) return fail(EPIC_ERR_INVALID_ARG, "common is NULL");
+    if (c->n_pol != 1 && c->n_pol != 2) return fail(EPIC_ERR_INVALID_ARG, "n_pol must be 1 or 2");
+    if (c->n_chan < 1) return fail(EPIC_ERR_INVALID_ARG, "n_chan must be >= 1");
+    if (!c->wavelength_m) return fail(EPIC_ERR_INVALID_ARG, "wavelength_m is NULL");
+    for (int i = 0; i < c->n_chan; ++i)
+        if (!std::isfinite(c->wavelength_m[i]) || !(c->wavelength_m[i] > 0.0))
+            return fail(EPIC_ERR_INVALID_ARG, "wavelength_m[" + std::to_string(i) + "] must be finite and > 0");
+    if (!std::isfinite(c->grid_spacing_wl) || !(c->grid_spacing_wl > 0.0))
+        return fail(EPIC_ERR_INVALID_ARG, "grid_spacing_wl must be finite and > 0");
+    if (c->n_time < 1) return fail(EPIC_ERR_INVALID_ARG, "n_time must be >= 1");
+    if (c->volt_type != EPIC_CI8 && c->volt_type != EPIC_CF32)
+        return fail(EPIC_ERR_INVALID_ARG, "unknown volt_type");
+    if (c->precision != EPIC_FP32_FFT && c->precision != EPIC_FP16_SPLIT &&
+        c->precision != EPIC_BF16_SPLIT)
+        return fail(EPIC_ERR_INVALID_ARG, "unknown precision");
+    return EPIC_OK;
+}
+
+epic_status check_station(const epic_station *s, int idx)
+{
+    const std::string who = "station " + std::to_string(idx) + ": ";
+    if (s->n_elem < 1) return fail(EPIC_ERR_INVALID_ARG, who + "n_elem must be >= 1");
+    if (!s->pos_m) return fail(EPIC_ERR_INVALID_ARG, who + "pos_m is NULL");
+    for (int64_t i = 0; i < 2LL * s->n_elem; ++i)
+        if (!std::isfinite(s->pos_m[i])) return fail(EPIC_ERR_INVALID_ARG, who + "non-finite position");
+    if (!is_pow2_grid(s->nx) || !is_pow2_grid(s->ny))
+        return fail(EPIC_ERR_INVALID_ARG, who + "nx, ny must be powers of two in 16..256");
+    const epic_kernel &k = s->kernel;
+    if (k.type != EPIC_KERNEL_NEAREST && k.type != EPIC_KERNEL_GAUSSIAN)
+        return fail(EPIC_ERR_INVALID_ARG, who + "unknown kernel type");
+    if (k.support < 1 || k.support > 7 || (k.support % 2) == 0)
+        return fail(EPIC_ERR_INVALID_ARG, who + "kernel support must be odd, 1..7");
+    if (k.type == EPIC_KERNEL_NEAREST && k.support != 1)
+        return fail(EPIC_ERR_INVALID_ARG, who + "NEAREST kernel needs support 1");
+    if (k.type == EPIC_KERNEL_GAUSSIAN && (!std::isfinite(k.sigma_cells) || !(k.sigma_cells > 0.0)))
+        return fail(EPIC_ERR_INVALID_ARG, who + "Gaussian sigma_cells must be finite and > 0");
+    if (!s->volts) return fail(EPIC_ERR_INVALID_ARG, who + "volts is NULL");
+    return EPIC_OK;
+}
+
+epic_status current_device(int *dev)
+{
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    return EPIC_OK;
+}
+
+StationDev make_station_dev(const epic_station *s, const PlanHandle &p)
+{
+    StationDev d{};
+    d.chan = p.chan;
+    d.cell_start = p.cell_start;
+    d.taps = p.taps;
+    d.volts = s->volts;
+    d.image = static_cast<float2 *>(s->image);
+    d.n_elem = s->n_elem;
+    d.nx = s->nx;
+    d.ny = s->ny;
+    d.log2n = ilog2(s->nx);
+    return d;
+}
+
+size_t volt_bytes(int type) { return type == EPIC_CI8 ? 2 : 8; }
+
+// The composed cadence path: grid -> transform -> square/accumulate through a
+// library-owned workspace, in time chunks.  Used for the grids and precisions
+// that the fused kernel does not cover.
+epic_status cadence_composed(const epic_common *c, const epic_station *s, const PlanHandle &p,
+                             int device, hipStream_t stream)
+{
+    const int n_pol = c->n_pol, n_chan = c->n_chan;
+    const int64_t npix = static_cast<int64_t>(s->nx) * s->ny;
+    const int64_t per_sample = static_cast<int64_t>(n_chan) * n_pol * npix * 8;  // bytes
+    // chunk so that the field workspace stays near 1 GiB
+    int chunk = static_cast<int>(std::max<int64_t>(1, (1LL << 30) / per_sample));
+    chunk = std::min(chunk, c->n_time);
+    const size_t acc_bytes = static_cast<size_t>(n_chan) * n_pol * n_pol * npix * 8;
+    void *ws_field = nullptr, *ws_acc = nullptr;
+    epic_status st = get_workspace(device, stream, 0, static_cast<size_t>(per_sample) * chunk, &ws_field);
+    if (st != EPIC_OK) return st;
+    st = get_workspace(device, stream, 1, 2 * acc_bytes, &ws_acc);
+    if (st != EPIC_OK) return st;
+    float2 *acc_sum = static_cast<float2 *>(ws_acc);
+    float2 *acc_comp = acc_sum + acc_bytes / 8;
+    EPIC_HIP_TRY(hipMemsetAsync(ws_acc, 0, 2 * acc_bytes, stream));
+    const StationDev sd = make_station_dev(s, p);
+    float2 *field = static_cast<float2 *>(ws_field);
+    for (int t0 = 0; t0 < c->n_time; t0 += chunk) {
+        const int nt = std::min(chunk, c->n_time - t0);
+        st = launch_grid(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, field, stream);
+        if (st != EPIC_OK) return st;
+        const int64_t batch = static_cast<int64_t>(n_chan) * nt * n_pol;
+        if (c->precision == EPIC_FP32_FFT)
+            st = launch_fft2_f32(s->nx, s->ny, batch, field, field, device, stream);
+        else
+            st = launch_dft2_split(s->nx, s->ny, batch, c->precision, field, field, device, stream);
+        if (st != EPIC_OK) return st;
+        const bool last = t0 + nt >= c->n_time;
+        st = launch_power(n_pol, static_cast<int>(npix), n_chan, nt, field, acc_sum, acc_comp,
+                          last ? c->n_time : 0, static_cast<float2 *>(s->image), stream);
+        if (st != EPIC_OK) return st;
+    }
+    return EPIC_OK;
+}
+
+// Fused FP32 path for square grids up to 64x64: one kernel grids, transforms,
+// squares and accumulates a time chunk per (channel, chunk) work-group; a
+// second kernel reduces the chunks in order with compensation.
+epic_status cadence_fused_fft(const epic_common *c, const epic_station *s, const PlanHandle &p,
+                              int device, hipStream_t stream)
+{
+    const int n_pol = c->n_pol, n_chan = c->n_chan;
+    const int npix = s->nx * s->ny;
+    const int chunk = 32;
+    const int n_chunks = (c->n_time + chunk - 1) / chunk;
+    const int nreal = n_pol == 2 ? 4 : 1;
+    const size_t bytes = sizeof(float) * static_cast<size_t>(n_chan) * n_chunks * nreal * npix;
+    void *ws = nullptr;
+    epic_status st = get_workspace(device, stream, 2, bytes, &ws);
+    if (st != EPIC_OK) return st;
+    const float2 *tw = nullptr;
+    st = get_twiddles(s->nx, device, &tw);
+    if (st != EPIC_OK) return st;
+    const StationDev sd = make_station_dev(s, p);
+    st = launch_fused_fft_partials(sd, n_pol, n_chan, c->n_time, c->volt_type, chunk,
+                                   static_cast<float *>(ws), tw, stream);
+    if (st != EPIC_OK) return st;
+    const float inv = static_cast<float>(1.0 / static_cast<double>(c->n_time));
+    return launch_reduce_partials(n_pol, npix, n_chan, n_chunks, static_cast<const float *>(ws),
+                                  inv, static_cast<float2 *>(s->image), stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *epic_status_string(epic_status status)
+{
+    switch (status) {
+    case EPIC_OK: return "EPIC_OK";
+    case EPIC_ERR_INVALID_ARG: return "EPIC_ERR_INVALID_ARG";
+    case EPIC_ERR_UNSUPPORTED: return "EPIC_ERR_UNSUPPORTED";
+    case EPIC_ERR_OUT_OF_MEMORY: return "EPIC_ERR_OUT_OF_MEMORY";
+    case EPIC_ERR_DEVICE: return "EPIC_ERR_DEVICE";
+    case EPIC_ERR_INTERNAL: return "EPIC_ERR_INTERNAL";
+    }
+    return "EPIC_ERR_UNKNOWN";
+}
+
+const char *epic_last_error(void) { return last_error_cstr(); }
+
+void epic_cache_clear(void) { clear_all_caches(); }
+
+epic_status epic_validate(const epic_common *common, const epic_station *stations,
+                          int32_t n_stations)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!stations || n_stations < 1) return fail(EPIC_ERR_INVALID_ARG, "need >= 1 station");
+    for (int i = 0; i < n_stations; ++i) {
+        st = check_station(&stations[i], i);
+        if (st != EPIC_OK) return st;
+        st = check_geometry(common, &stations[i]);
+        if (st != EPIC_OK) return fail(st, "station " + std::to_string(i) + ": " + last_error_cstr());
+    }
+    return EPIC_OK;
+}
+
+epic_status grid_voltages(const epic_common *common, const epic_station *station, int32_t t0,
+                          int32_t nt, void *grid, hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!station) return fail(EPIC_ERR_INVALID_ARG, "station is NULL");
+    st = check_station(station, 0);
+    if (st != EPIC_OK) return st;
+    if (t0 < 0 || nt < 1 || static_cast<int64_t>(t0) + nt > common->n_time)
+        return fail(EPIC_ERR_INVALID_ARG, "need 0 <= t0, nt >= 1, t0 + nt <= n_time");
+    if (!grid) return fail(EPIC_ERR_INVALID_ARG, "grid is NULL");
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    PlanHandle p;
+    st = get_plan(common, station, dev, &p);
+    if (st != EPIC_OK) return st;
+    return launch_grid(make_station_dev(station, p), common->n_pol, common->n_chan, common->n_time,
+                       common->volt_type, t0, nt, static_cast<float2 *>(grid), stream);
+}
+
+epic_status fft2_batched(int32_t nx, int32_t ny, int64_t batch, int32_t precision, const void *in,
+                         void *out, hipStream_t stream)
+{
+    set_error("");
+    if (!is_pow2_grid(nx) || !is_pow2_grid(ny))
+        return fail(EPIC_ERR_INVALID_ARG, "nx, ny must be powers of two in 16..256");
+    if (batch < 1) return fail(EPIC_ERR_INVALID_ARG, "batch must be >= 1");
+    if (!in || !out) return fail(EPIC_ERR_INVALID_ARG, "in/out is NULL");
+    if (precision != EPIC_FP32_FFT && precision != EPIC_FP16_SPLIT && precision != EPIC_BF16_SPLIT)
+        return fail(EPIC_ERR_INVALID_ARG, "unknown precision");
+    int dev = 0;
+    epic_status st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    if (precision == EPIC_FP32_FFT)
+        return launch_fft2_f32(nx, ny, batch, static_cast<const float2 *>(in),
+                               static_cast<float2 *>(out), dev, stream);
+    return launch_dft2_split(nx, ny, batch, precision, static_cast<const float2 *>(in),
+                             static_cast<float2 *>(out), dev, stream);
+}
+
+epic_status accumulate_power(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_chan, int32_t nt,
+                             const void *field, void *acc_sum, void *acc_comp,
+                             int32_t finalize_n_time, void *image, hipStream_t stream)
+{
+    set_error("");
+    if (n_pol != 1 && n_pol != 2) return fail(EPIC_ERR_INVALID_ARG, "n_pol must be 1 or 2");
+    if (!is_pow2_grid(nx) || !is_pow2_grid(ny))
+        return fail(EPIC_ERR_INVALID_ARG, "nx, ny must be powers of two in 16..256");
+    if (n_chan < 1 || nt < 1) return fail(EPIC_ERR_INVALID_ARG, "n_chan and nt must be >= 1");
+    if (!field || !acc_sum || !acc_comp) return fail(EPIC_ERR_INVALID_ARG, "NULL buffer");
+    if (finalize_n_time < 0) return fail(EPIC_ERR_INVALID_ARG, "finalize_n_time must be >= 0");
+    if (finalize_n_time > 0 && !image) return fail(EPIC_ERR_INVALID_ARG, "image is NULL");
+    return launch_power(n_pol, nx * ny, n_chan, nt, static_cast<const float2 *>(field),
+                        static_cast<float2 *>(acc_sum), static_cast<float2 *>(acc_comp),
+                        finalize_n_time, static_cast<float2 *>(image), stream);
+}
+
+epic_status image_cadence(const epic_common *common, const epic_station *stations,
+                          int32_t n_stations, hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!stations || n_stations < 1) return fail(EPIC_ERR_INVALID_ARG, "need >= 1 station");
+    for (int i = 0; i < n_stations; ++i) {
+        st = check_station(&stations[i], i);
+        if (st != EPIC_OK) return st;
+        if (!stations[i].image) return fail(EPIC_ERR_INVALID_ARG, "station image is NULL");
+    }
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    // every plan first: geometry errors surface before any launch
+    std::vector<PlanHandle> plans(n_stations);
+    for (int i = 0; i < n_stations; ++i) {
+        st = get_plan(common, &stations[i], dev, &plans[i]);
+        if (st != EPIC_OK) return fail(st, "station " + std::to_string(i) + ": " + last_error_cstr());
+    }
+    for (int i = 0; i < n_stations; ++i) {
+        const epic_station *s = &stations[i];
+        const bool fused = common->precision == EPIC_FP32_FFT && s->nx == s->ny && s->nx <= 64;
+        st = fused ? cadence_fused_fft(common, s, plans[i], dev, stream)
+                   : cadence_composed(common, s, plans[i], dev, stream);
+        if (st != EPIC_OK) return st;
+    }
+    return EPIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// internal.hpp -- declarations shared by the host code and the HIP kernels of
+// the EPIC imager library.  Nothing here is part of the public ABI (epic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "epic.h"
+
+namespace epic {
+
+// ---------------------------------------------------------------------------
+// Plan tables (built on the host in FP64, stored in FP32 on the device).
+//
+// For one (station, channel) the kernel footprints of all elements cover the
+// cell box [x0, x0+bw) x [y0, y0+bh).  Gridding is a gather: every box cell
+// owns the list of (element, weight) taps that land on it, in ascending
+// element order, so each cell's sum has a fixed order and needs no atomics.
+// ---------------------------------------------------------------------------
+struct Tap {
+    int32_t elem;
+    float w;
+};
+
+struct ChanPlan {
+    int32_t x0, y0, bw, bh;   // footprint box of this channel
+    int64_t cell_off;         // first entry of this channel in cell_start[]
+    int64_t tap_off;          // first entry of this channel in taps[]
+};
+
+// Device-side view of one station's plan and buffers (kernel argument).
+struct StationDev {
+    const ChanPlan *chan;     // [n_chan]
+    const int32_t *cell_start;// per channel: [bw*bh + 1] offsets relative to tap_off
+    const Tap *taps;          // per channel: taps in cell order
+    const void *volts;        // [n_chan][n_time][n_elem][n_pol]
+    float2 *image;            // [n_chan][n_pol^2][ny][nx]
+    int32_t n_elem;
+    int32_t nx, ny;
+    int32_t log2n;            // log2(nx) (square grids in the fused kernels)
+};
+
+// ---------------------------------------------------------------------------
+// Error reporting (thread-local detail string).
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+epic_status fail(epic_status st, const std::string &msg);
+epic_status hip_fail(hipError_t e, const char *what);
+
+#define EPIC_HIP_TRY(call)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return ::epic::hip_fail(e_, #call); \
+    } while (0)
+
+// Brackets one kernel launch with HIP events on its stream while timing is
+// enabled (timing.cpp); a no-op otherwise.
+class KernelTimer {
+  public:
+    KernelTimer(const char *name, hipStream_t stream);
+    ~KernelTimer();
+    KernelTimer(const KernelTimer &) = delete;
+    KernelTimer &operator=(const KernelTimer &) = delete;
+
+  private:
+    const char *name_;
+    hipStream_t stream_;
+    hipEvent_t start_ = nullptr, stop_ = nullptr;
+    bool active_ = false;
+};
+
+// ---------------------------------------------------------------------------
+// Plan cache (plan.cpp).
+// ---------------------------------------------------------------------------
+struct PlanHandle {
+    const ChanPlan *chan = nullptr;
+    const int32_t *cell_start = nullptr;
+    const Tap *taps = nullptr;
+    int32_t max_box = 0;       // max bw*bh over channels
+    int32_t max_bw = 0, max_bh = 0;
+    int64_t n_taps_total = 0;
+};
+
+// Host-only geometry check (no device needed).
+epic_status check_geometry(const epic_common *common, const epic_station *st);
+
+// Validates the geometry and returns the (cached) device plan of one station.
+epic_status get_plan(const epic_common *common, const epic_station *st, int device,
+                     PlanHandle *out);
+
+// Device table of exp(+2 pi i k / n), k < n (FP64-generated, FP32 stored).
+epic_status get_twiddles(int n, int device, const float2 **out);
+
+// Split-precision DFT tables in MFMA fragment order (k_dft.hip).
+epic_status get_dft_tables(int n, int precision, int device, const void **out);
+
+// Library-owned device workspace, per (device, stream, slot); grows on demand.
+epic_status get_workspace(int device, hipStream_t stream, int slot, size_t bytes, void **out);
+
+void clear_all_caches();
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (each .hip file).  All validate nothing: the ABI layer has
+// already checked every argument against what the kernel assumes.
+// ---------------------------------------------------------------------------
+epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
+                        int t0, int nt, float2 *grid, hipStream_t stream);
+
+epic_status launch_fft2_f32(int nx, int ny, int64_t batch, const float2 *in, float2 *out,
+                            int device, hipStream_t stream);
+
+epic_status launch_power(int n_pol, int npix, int n_chan, int nt, const float2 *field,
+                         float2 *acc_sum, float2 *acc_comp, int finalize_n_time, float2 *image,
+                         hipStream_t stream);
+
+epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, const float2 *in,
+                              float2 *out, int device, hipStream_t stream);
+
+// Fused FP32 cadence for square grids n in {16, 32, 64}: partial sums of the
+// four real product components per (station-channel, time chunk).
+epic_status launch_fused_fft_partials(const StationDev &sd, int n_pol, int n_chan, int n_time,
+                                      int volt_type, int chunk, float *partials,
+                                      const float2 *twiddles, hipStream_t stream);
+
+// Ordered, compensated reduction of the partial sums of every chunk, then the
+// mean, written as the n_pol^2 complex products.
+epic_status launch_reduce_partials(int n_pol, int npix, int n_chan, int n_chunks,
+                                   const float *partials, float inv_n_time, float2 *image,
+                                   hipStream_t stream);
+
+}  // namespace epic

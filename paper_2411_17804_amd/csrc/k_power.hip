@@ -1,0 +1,156 @@
+// k_power.hip -- squaring and temporal averaging (Eq. 2): the polarisation
+// outer products F^a conj(F^b) summed over the cadence with compensated
+// (error-free two-sum) FP32 accumulation, then scaled by 1/n_time.
+//
+// Products are kept as four real components per pixel: XX, Re XY, Im XY, YY
+// (n_pol = 2) or XX (n_pol = 1).  XX and YY are formed as re^2 + im^2, so their
+// imaginary parts are exactly zero; YX is written as the exact conjugate of XY.
+#include "internal.hpp"
+
+namespace epic {
+
+// s + c accumulates x exactly up to the final rounding of s + c (Knuth's
+// two-sum; only additions, so contraction into FMA cannot change it).
+__device__ __forceinline__ void two_sum_acc(float &s, float &c, float x)
+{
+    const float t = s + x;
+    const float bp = t - s;
+    const float err = (s - (t - bp)) + (x - bp);
+    s = t;
+    c += err;
+}
+
+// Real components of the products of one pixel.
+template <int NP>
+__device__ __forceinline__ void products(const float2 *f, float *q)
+{
+    q[0] = fmaf(f[0].x, f[0].x, f[0].y * f[0].y);
+    if constexpr (NP == 2) {
+        q[1] = fmaf(f[0].x, f[1].x, f[0].y * f[1].y);       // Re F^X conj(F^Y)
+        q[2] = fmaf(f[0].y, f[1].x, -(f[0].x * f[1].y));    // Im F^X conj(F^Y)
+        q[3] = fmaf(f[1].x, f[1].x, f[1].y * f[1].y);
+    }
+}
+
+template <int NP>
+__device__ __forceinline__ void store_products(float2 *dst, size_t npix, size_t k, const float *v)
+{
+    if constexpr (NP == 1) {
+        dst[k] = make_float2(v[0], 0.f);
+    } else {
+        dst[k] = make_float2(v[0], 0.f);
+        dst[npix + k] = make_float2(v[1], v[2]);
+        dst[2 * npix + k] = make_float2(v[1], -v[2]);
+        dst[3 * npix + k] = make_float2(v[3], 0.f);
+    }
+}
+
+// One thread per (channel, pixel); loops over the nt samples in order.
+template <int NP>
+__global__ __launch_bounds__(256) void k_power(int npix, int n_chan, int nt,
+                                               const float2 *__restrict__ field,
+                                               float2 *__restrict__ acc_sum,
+                                               float2 *__restrict__ acc_comp, int finalize,
+                                               float inv_n, float2 *__restrict__ image)
+{
+    constexpr int NQ = NP == 2 ? 4 : 1;
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= static_cast<int64_t>(n_chan) * npix) return;
+    const int c = static_cast<int>(gid / npix);
+    const int k = static_cast<int>(gid - static_cast<int64_t>(c) * npix);
+    const size_t abase = static_cast<size_t>(c) * NP * NP * npix;
+    float s[NQ], cc[NQ];
+    {
+        const float2 a0 = acc_sum[abase + k], c0 = acc_comp[abase + k];
+        s[0] = a0.x;
+        cc[0] = c0.x;
+        if constexpr (NP == 2) {
+            const float2 a1 = acc_sum[abase + npix + k], c1 = acc_comp[abase + npix + k];
+            const float2 a3 = acc_sum[abase + 3 * npix + k], c3 = acc_comp[abase + 3 * npix + k];
+            s[1] = a1.x; s[2] = a1.y; s[3] = a3.x;
+            cc[1] = c1.x; cc[2] = c1.y; cc[3] = c3.x;
+        }
+    }
+    const float2 *f = field + static_cast<size_t>(c) * nt * NP * npix + k;
+    for (int t = 0; t < nt; ++t) {
+        float2 v[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) v[p] = f[(static_cast<size_t>(t) * NP + p) * npix];
+        float q[NQ];
+        products<NP>(v, q);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) two_sum_acc(s[i], cc[i], q[i]);
+    }
+    store_products<NP>(acc_sum + abase, npix, k, s);
+    store_products<NP>(acc_comp + abase, npix, k, cc);
+    if (finalize) {
+        float m[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) m[i] = (s[i] + cc[i]) * inv_n;
+        store_products<NP>(image + abase, npix, k, m);
+    }
+}
+
+epic_status launch_power(int n_pol, int npix, int n_chan, int nt, const float2 *field,
+                         float2 *acc_sum, float2 *acc_comp, int finalize_n_time, float2 *image,
+                         hipStream_t stream)
+{
+    const int64_t n = static_cast<int64_t>(n_chan) * npix;
+    const dim3 blocks(static_cast<unsigned>((n + 255) / 256)), threads(256);
+    const float inv = finalize_n_time > 0 ? static_cast<float>(1.0 / finalize_n_time) : 0.f;
+    KernelTimer timer("square_accumulate", stream);
+    if (n_pol == 2)
+        hipLaunchKernelGGL(k_power<2>, blocks, threads, 0, stream, npix, n_chan, nt, field, acc_sum,
+                           acc_comp, finalize_n_time > 0 ? 1 : 0, inv, image);
+    else
+        hipLaunchKernelGGL(k_power<1>, blocks, threads, 0, stream, npix, n_chan, nt, field, acc_sum,
+                           acc_comp, finalize_n_time > 0 ? 1 : 0, inv, image);
+    EPIC_HIP_TRY(hipGetLastError());
+    return EPIC_OK;
+}
+
+// Partial sums [n_chan][n_chunks][NQ][npix] -> mean products.  The chunks are
+// added in time order with the two-sum, so the result does not depend on how
+// work-groups were scheduled.
+template <int NP>
+__global__ __launch_bounds__(256) void k_reduce(int npix, int n_chan, int n_chunks,
+                                                const float *__restrict__ partials, float inv_n,
+                                                float2 *__restrict__ image)
+{
+    constexpr int NQ = NP == 2 ? 4 : 1;
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= static_cast<int64_t>(n_chan) * npix) return;
+    const int c = static_cast<int>(gid / npix);
+    const int k = static_cast<int>(gid - static_cast<int64_t>(c) * npix);
+    float s[NQ], cc[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) s[i] = cc[i] = 0.f;
+    const float *p = partials + static_cast<size_t>(c) * n_chunks * NQ * npix + k;
+    for (int ch = 0; ch < n_chunks; ++ch) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) two_sum_acc(s[i], cc[i], p[(static_cast<size_t>(ch) * NQ + i) * npix]);
+    }
+    float m[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) m[i] = (s[i] + cc[i]) * inv_n;
+    store_products<NP>(image + static_cast<size_t>(c) * NP * NP * npix, npix, k, m);
+}
+
+epic_status launch_reduce_partials(int n_pol, int npix, int n_chan, int n_chunks,
+                                   const float *partials, float inv_n_time, float2 *image,
+                                   hipStream_t stream)
+{
+    const int64_t n = static_cast<int64_t>(n_chan) * npix;
+    const dim3 blocks(static_cast<unsigned>((n + 255) / 256)), threads(256);
+    KernelTimer timer("reduce_chunks", stream);
+    if (n_pol == 2)
+        hipLaunchKernelGGL(k_reduce<2>, blocks, threads, 0, stream, npix, n_chan, n_chunks, partials,
+                           inv_n_time, image);
+    else
+        hipLaunchKernelGGL(k_reduce<1>, blocks, threads, 0, stream, npix, n_chan, n_chunks, partials,
+                           inv_n_time, image);
+    EPIC_HIP_TRY(hipGetLastError());
+    return EPIC_OK;
+}
+
+}  // namespace epic

@@ -1,0 +1,340 @@
+// plan.cpp -- host-side plan builder (FP64) and the library's device caches.
+//
+// For every (station, channel) the plan holds the kernel taps of Eq. 3's
+// gridding: each element a lands on the K x K cells around its nearest cell
+// with separable weights evaluated at its true sub-cell position (Sec. 5.2:
+// the kernel W~ is centred on r_a; the grid r_j is fixed in wavelengths so
+// the geometry is recomputed per channel).  Everything is computed in double
+// precision and rounded once to FP32 when stored.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+
+#include "internal.hpp"
+
+namespace epic {
+
+// ----------------------------------------------------------------- errors --
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+epic_status fail(epic_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+epic_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? EPIC_ERR_OUT_OF_MEMORY : EPIC_ERR_DEVICE;
+}
+
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+// Test hook: EPIC_TEST_FAIL_ALLOC=1 makes every library-owned allocation fail.
+static bool alloc_fail_forced()
+{
+    const char *e = std::getenv("EPIC_TEST_FAIL_ALLOC");
+    return e && e[0] == '1';
+}
+
+static epic_status dev_alloc(void **p, size_t bytes)
+{
+    if (alloc_fail_forced()) return fail(EPIC_ERR_OUT_OF_MEMORY, "allocation refused (EPIC_TEST_FAIL_ALLOC)");
+    hipError_t e = hipMalloc(p, bytes == 0 ? 16 : bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    return EPIC_OK;
+}
+
+// ------------------------------------------------------------------ plans --
+struct PlanEntry {
+    void *dev = nullptr;
+    PlanHandle h;
+};
+
+static std::mutex g_mu;
+static std::unordered_map<std::string, PlanEntry> g_plans;
+static std::map<std::pair<int, int>, void *> g_twiddles;
+static std::map<std::tuple<int, int, int>, void *> g_dft_tables;
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+static std::map<std::tuple<int, uintptr_t, int>, Workspace> g_ws;
+
+static void append(std::string &k, const void *p, size_t n)
+{
+    k.append(static_cast<const char *>(p), n);
+}
+
+// Geometry of one element at one channel: nearest cell and separable weights.
+// Returns false if the footprint leaves the grid.
+static bool element_taps(double x, double y, double delta, int nx, int ny, const epic_kernel &kn,
+                         int *ci, int *cj, double *wx, double *wy)
+{
+    const double u = x / delta + static_cast<double>(nx / 2);
+    const double v = y / delta + static_cast<double>(ny / 2);
+    const double fi = std::floor(u + 0.5);
+    const double fj = std::floor(v + 0.5);
+    const int K = kn.support;
+    const int h = (K - 1) / 2;
+    if (fi - h < 0 || fi + h > nx - 1 || fj - h < 0 || fj + h > ny - 1) return false;
+    *ci = static_cast<int>(fi);
+    *cj = static_cast<int>(fj);
+    if (kn.type == EPIC_KERNEL_NEAREST) {
+        wx[0] = wy[0] = 1.0;
+        return true;
+    }
+    const double du = u - fi, dv = v - fj;
+    double sx = 0.0, sy = 0.0;
+    for (int d = -h; d <= h; ++d) {
+        const double ex = (static_cast<double>(d) - du) / kn.sigma_cells;
+        const double ey = (static_cast<double>(d) - dv) / kn.sigma_cells;
+        wx[d + h] = std::exp(-0.5 * ex * ex);
+        wy[d + h] = std::exp(-0.5 * ey * ey);
+        sx += wx[d + h];
+        sy += wy[d + h];
+    }
+    for (int d = 0; d < K; ++d) {
+        wx[d] /= sx;
+        wy[d] /= sy;
+    }
+    return true;
+}
+
+epic_status check_geometry(const epic_common *common, const epic_station *st)
+{
+    const int K = st->kernel.support;
+    std::vector<double> wx(K), wy(K);
+    for (int c = 0; c < common->n_chan; ++c) {
+        const double delta = common->grid_spacing_wl * common->wavelength_m[c];
+        for (int a = 0; a < st->n_elem; ++a) {
+            int ci = 0, cj = 0;
+            if (!element_taps(st->pos_m[2 * a], st->pos_m[2 * a + 1], delta, st->nx, st->ny,
+                              st->kernel, &ci, &cj, wx.data(), wy.data()))
+                return fail(EPIC_ERR_INVALID_ARG,
+                            "element " + std::to_string(a) + " kernel footprint leaves the " +
+                                std::to_string(st->nx) + "x" + std::to_string(st->ny) +
+                                " grid at channel " + std::to_string(c));
+        }
+    }
+    return EPIC_OK;
+}
+
+epic_status get_plan(const epic_common *common, const epic_station *st, int device,
+                     PlanHandle *out)
+{
+    const int n_chan = common->n_chan;
+    const int n_elem = st->n_elem;
+    const int K = st->kernel.support;
+    std::string key;
+    key.reserve(64 + sizeof(double) * (2 * n_elem + n_chan));
+    append(key, &device, sizeof device);
+    append(key, &n_elem, sizeof n_elem);
+    append(key, &st->nx, sizeof st->nx);
+    append(key, &st->ny, sizeof st->ny);
+    append(key, &st->kernel.type, sizeof st->kernel.type);
+    append(key, &K, sizeof K);
+    append(key, &st->kernel.sigma_cells, sizeof st->kernel.sigma_cells);
+    append(key, &common->grid_spacing_wl, sizeof common->grid_spacing_wl);
+    append(key, &n_chan, sizeof n_chan);
+    append(key, common->wavelength_m, sizeof(double) * n_chan);
+    append(key, st->pos_m, sizeof(double) * 2 * n_elem);
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = it->second.h;
+        return EPIC_OK;
+    }
+
+    // Build on the host in FP64.
+    const int nx = st->nx, ny = st->ny, h = (K - 1) / 2;
+    std::vector<ChanPlan> chans(n_chan);
+    std::vector<int32_t> cell_start;
+    std::vector<Tap> taps;
+    std::vector<int> ci(n_elem), cj(n_elem);
+    std::vector<double> wx(static_cast<size_t>(n_elem) * K), wy(static_cast<size_t>(n_elem) * K);
+    PlanHandle hd;
+    for (int c = 0; c < n_chan; ++c) {
+        const double delta = common->grid_spacing_wl * common->wavelength_m[c];
+        int x_lo = nx, x_hi = -1, y_lo = ny, y_hi = -1;
+        for (int a = 0; a < n_elem; ++a) {
+            if (!element_taps(st->pos_m[2 * a], st->pos_m[2 * a + 1], delta, nx, ny, st->kernel,
+                              &ci[a], &cj[a], &wx[static_cast<size_t>(a) * K],
+                              &wy[static_cast<size_t>(a) * K])) {
+                return fail(EPIC_ERR_INVALID_ARG,
+                            "element " + std::to_string(a) + " kernel footprint leaves the " +
+                                std::to_string(nx) + "x" + std::to_string(ny) +
+                                " grid at channel " + std::to_string(c));
+            }
+            x_lo = std::min(x_lo, ci[a] - h);
+            x_hi = std::max(x_hi, ci[a] + h);
+            y_lo = std::min(y_lo, cj[a] - h);
+            y_hi = std::max(y_hi, cj[a] + h);
+        }
+        ChanPlan &cp = chans[c];
+        cp.x0 = x_lo;
+        cp.y0 = y_lo;
+        cp.bw = x_hi - x_lo + 1;
+        cp.bh = y_hi - y_lo + 1;
+        cp.cell_off = static_cast<int64_t>(cell_start.size());
+        cp.tap_off = static_cast<int64_t>(taps.size());
+        const int ncell = cp.bw * cp.bh;
+        hd.max_box = std::max(hd.max_box, ncell);
+        hd.max_bw = std::max(hd.max_bw, cp.bw);
+        hd.max_bh = std::max(hd.max_bh, cp.bh);
+        // counting sort of taps by cell; elements visited in ascending order
+        std::vector<int32_t> count(static_cast<size_t>(ncell) + 1, 0);
+        for (int a = 0; a < n_elem; ++a)
+            for (int dy = -h; dy <= h; ++dy)
+                for (int dx = -h; dx <= h; ++dx)
+                    ++count[static_cast<size_t>(cj[a] + dy - y_lo) * cp.bw + (ci[a] + dx - x_lo) + 1];
+        for (int i = 0; i < ncell; ++i) count[i + 1] += count[i];
+        const size_t base = taps.size();
+        taps.resize(base + static_cast<size_t>(count[ncell]));
+        std::vector<int32_t> fillp(count.begin(), count.end() - 1);
+        for (int a = 0; a < n_elem; ++a)
+            for (int dy = -h; dy <= h; ++dy)
+                for (int dx = -h; dx <= h; ++dx) {
+                    const size_t cell = static_cast<size_t>(cj[a] + dy - y_lo) * cp.bw + (ci[a] + dx - x_lo);
+                    const double w = wx[static_cast<size_t>(a) * K + dx + h] * wy[static_cast<size_t>(a) * K + dy + h];
+                    taps[base + fillp[cell]++] = Tap{a, static_cast<float>(w)};
+                }
+        cell_start.insert(cell_start.end(), count.begin(), count.end());
+    }
+    hd.n_taps_total = static_cast<int64_t>(taps.size());
+
+    // Upload: one allocation, three 256-byte aligned sections.
+    auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+    const size_t b_chan = up(sizeof(ChanPlan) * chans.size());
+    const size_t b_cell = up(sizeof(int32_t) * cell_start.size());
+    const size_t b_taps = up(sizeof(Tap) * taps.size());
+    void *dev = nullptr;
+    epic_status s = dev_alloc(&dev, b_chan + b_cell + b_taps);
+    if (s != EPIC_OK) return s;
+    char *p = static_cast<char *>(dev);
+    hipError_t e = hipMemcpy(p, chans.data(), sizeof(ChanPlan) * chans.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p + b_chan, cell_start.data(), sizeof(int32_t) * cell_start.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !taps.empty())
+        e = hipMemcpy(p + b_chan + b_cell, taps.data(), sizeof(Tap) * taps.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(e, "plan upload");
+    }
+    hd.chan = reinterpret_cast<const ChanPlan *>(p);
+    hd.cell_start = reinterpret_cast<const int32_t *>(p + b_chan);
+    hd.taps = reinterpret_cast<const Tap *>(p + b_chan + b_cell);
+    g_plans.emplace(std::move(key), PlanEntry{dev, hd});
+    *out = hd;
+    return EPIC_OK;
+}
+
+epic_status get_twiddles(int n, int device, const float2 **out)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto key = std::make_pair(device, n);
+    auto it = g_twiddles.find(key);
+    if (it != g_twiddles.end()) {
+        *out = static_cast<const float2 *>(it->second);
+        return EPIC_OK;
+    }
+    std::vector<float2> tw(n);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < n; ++k) {
+        const double a = two_pi * static_cast<double>(k) / static_cast<double>(n);
+        tw[k] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
+    }
+    void *dev = nullptr;
+    epic_status s = dev_alloc(&dev, sizeof(float2) * n);
+    if (s != EPIC_OK) return s;
+    hipError_t e = hipMemcpy(dev, tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(e, "twiddle upload");
+    }
+    g_twiddles[key] = dev;
+    *out = static_cast<const float2 *>(dev);
+    return EPIC_OK;
+}
+
+// Registry used by k_dft.hip: the table is built by the caller-supplied
+// function the first time (under the cache lock).
+epic_status cache_dft_table(int n, int precision, int device, size_t bytes,
+                            void (*fill)(int, int, void *), const void **out)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto key = std::make_tuple(device, n, precision);
+    auto it = g_dft_tables.find(key);
+    if (it != g_dft_tables.end()) {
+        *out = it->second;
+        return EPIC_OK;
+    }
+    std::vector<char> host(bytes);
+    fill(n, precision, host.data());
+    void *dev = nullptr;
+    epic_status s = dev_alloc(&dev, bytes);
+    if (s != EPIC_OK) return s;
+    hipError_t e = hipMemcpy(dev, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(e, "DFT table upload");
+    }
+    g_dft_tables[key] = dev;
+    *out = dev;
+    return EPIC_OK;
+}
+
+epic_status get_workspace(int device, hipStream_t stream, int slot, size_t bytes, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace &w = g_ws[std::make_tuple(device, reinterpret_cast<uintptr_t>(stream), slot)];
+    if (w.bytes >= bytes && w.ptr) {
+        *out = w.ptr;
+        return EPIC_OK;
+    }
+    if (w.ptr) {
+        // the old buffer may still be read by work queued on this stream
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        (void)hipFree(w.ptr);
+        w.ptr = nullptr;
+        w.bytes = 0;
+    }
+    const size_t want = bytes + bytes / 8;   // some headroom for growing workloads
+    epic_status s = dev_alloc(&w.ptr, want);
+    if (s != EPIC_OK) return s;
+    w.bytes = want;
+    *out = w.ptr;
+    return EPIC_OK;
+}
+
+void clear_all_caches()
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : g_plans) (void)hipFree(kv.second.dev);
+    g_plans.clear();
+    for (auto &kv : g_twiddles) (void)hipFree(kv.second);
+    g_twiddles.clear();
+    for (auto &kv : g_dft_tables) (void)hipFree(kv.second);
+    g_dft_tables.clear();
+    for (auto &kv : g_ws) (void)hipFree(kv.second.ptr);
+    g_ws.clear();
+}
+
+}  // namespace epic

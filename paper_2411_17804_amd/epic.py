@@ -1,0 +1,238 @@
+"""ctypes binding of the C ABI in include/epic.h (argument marshalling only).
+
+Every step of the imager runs in the gfx950 kernels of libepic.so; this module
+only turns Python objects into the ABI's structs and pointers.  Device buffers
+are torch tensors (used for their memory and for the current HIP stream);
+host arrays (positions, wavelengths) are numpy float64 arrays.  There is no
+fallback: if the library is not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libepic.so")
+
+# enums of epic.h
+EPIC_OK = 0
+EPIC_ERR_INVALID_ARG = -1
+EPIC_ERR_UNSUPPORTED = -2
+EPIC_ERR_OUT_OF_MEMORY = -3
+EPIC_ERR_DEVICE = -4
+EPIC_ERR_INTERNAL = -5
+CI8 = 0
+CF32 = 1
+FP32_FFT = 0
+FP16_SPLIT = 1
+BF16_SPLIT = 2
+KERNEL_NEAREST = 0
+KERNEL_GAUSSIAN = 1
+
+# every function the header declares
+ABI_FUNCTIONS = ("grid_voltages", "fft2_batched", "accumulate_power", "image_cadence",
+                 "epic_validate", "epic_timing_enable", "epic_timing_report",
+                 "epic_timing_reset", "epic_status_string", "epic_last_error",
+                 "epic_cache_clear")
+
+
+class _Kernel(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("support", ctypes.c_int32),
+                ("sigma_cells", ctypes.c_double)]
+
+
+class _Common(ctypes.Structure):
+    _fields_ = [("n_pol", ctypes.c_int32), ("n_chan", ctypes.c_int32),
+                ("wavelength_m", ctypes.c_void_p), ("grid_spacing_wl", ctypes.c_double),
+                ("n_time", ctypes.c_int32), ("volt_type", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+class _Station(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int32), ("pos_m", ctypes.c_void_p),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("kernel", _Kernel),
+                ("volts", ctypes.c_void_p), ("image", ctypes.c_void_p)]
+
+
+class EpicError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{status_name(status)}: {detail}")
+        self.status = status
+        self.detail = detail
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libepic.so.  Import torch first in GPU processes so that the
+    library binds to the same HIP runtime as torch's streams."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.grid_voltages.argtypes = [P, P, i32, i32, P, P]
+    lib.grid_voltages.restype = i32
+    lib.fft2_batched.argtypes = [i32, i32, i64, i32, P, P, P]
+    lib.fft2_batched.restype = i32
+    lib.accumulate_power.argtypes = [i32, i32, i32, i32, i32, P, P, P, i32, P, P]
+    lib.accumulate_power.restype = i32
+    lib.image_cadence.argtypes = [P, P, i32, P]
+    lib.image_cadence.restype = i32
+    lib.epic_validate.argtypes = [P, P, i32]
+    lib.epic_validate.restype = i32
+    lib.epic_status_string.argtypes = [i32]
+    lib.epic_status_string.restype = ctypes.c_char_p
+    lib.epic_last_error.argtypes = []
+    lib.epic_last_error.restype = ctypes.c_char_p
+    lib.epic_timing_enable.argtypes = [i32]
+    lib.epic_timing_enable.restype = None
+    lib.epic_timing_report.argtypes = [ctypes.c_char_p, i32]
+    lib.epic_timing_report.restype = i32
+    lib.epic_timing_reset.argtypes = []
+    lib.epic_timing_reset.restype = None
+    lib.epic_cache_clear.argtypes = []
+    lib.epic_cache_clear.restype = None
+    _lib = lib
+    return lib
+
+
+def status_name(status: int) -> str:
+    return load().epic_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return load().epic_last_error().decode()
+
+
+def cache_clear() -> None:
+    load().epic_cache_clear()
+
+
+def timing_enable(on: bool = True) -> None:
+    load().epic_timing_enable(1 if on else 0)
+
+
+def timing_reset() -> None:
+    load().epic_timing_reset()
+
+
+def timing_report() -> dict:
+    """{kernel name: (launch count, total ms)} of the launches recorded while
+    timing was enabled (waits for them to finish)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    load().epic_timing_report(buf, len(buf))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, count, ms = line.split()
+        out[name] = (int(count), float(ms))
+    return out
+
+
+def _check(status: int) -> None:
+    if status != EPIC_OK:
+        raise EpicError(status, last_error())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    """Device address of a torch tensor (or an int address, or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+@dataclasses.dataclass
+class Common:
+    """Parameters shared by the stations of a call (epic_common)."""
+    n_pol: int
+    wavelength_m: np.ndarray
+    grid_spacing_wl: float
+    n_time: int
+    volt_type: int
+    precision: int = FP32_FFT
+
+    def to_c(self):
+        lam = np.ascontiguousarray(self.wavelength_m, dtype=np.float64)
+        c = _Common(self.n_pol, lam.shape[0], lam.ctypes.data, float(self.grid_spacing_wl),
+                    self.n_time, self.volt_type, self.precision)
+        return c, lam
+
+
+@dataclasses.dataclass
+class Station:
+    """One station (epic_station): host positions, device voltages and image."""
+    pos_m: np.ndarray
+    nx: int
+    ny: int
+    kernel_type: int
+    support: int
+    sigma_cells: float
+    volts: object = None       # torch tensor on the GPU
+    image: object = None       # torch tensor on the GPU (complex64 or float32 pairs)
+
+    def to_c(self):
+        pos = np.ascontiguousarray(self.pos_m, dtype=np.float64)
+        s = _Station(pos.shape[0], pos.ctypes.data, self.nx, self.ny,
+                     _Kernel(self.kernel_type, self.support, float(self.sigma_cells)),
+                     _dptr(self.volts), _dptr(self.image))
+        return s, pos
+
+
+def grid_voltages(common: Common, station: Station, t0: int, nt: int, grid, stream=None):
+    lib = load()
+    c, keep1 = common.to_c()
+    s, keep2 = station.to_c()
+    _check(lib.grid_voltages(ctypes.byref(c), ctypes.byref(s), t0, nt, _dptr(grid),
+                             _stream(stream)))
+
+
+def fft2_batched(nx: int, ny: int, batch: int, precision: int, inp, out, stream=None):
+    lib = load()
+    _check(lib.fft2_batched(nx, ny, batch, precision, _dptr(inp), _dptr(out), _stream(stream)))
+
+
+def accumulate_power(n_pol: int, nx: int, ny: int, n_chan: int, nt: int, field, acc_sum,
+                     acc_comp, finalize_n_time: int = 0, image=None, stream=None):
+    lib = load()
+    _check(lib.accumulate_power(n_pol, nx, ny, n_chan, nt, _dptr(field), _dptr(acc_sum),
+                                _dptr(acc_comp), finalize_n_time, _dptr(image), _stream(stream)))
+
+
+def _stations_c(stations):
+    arr = (_Station * len(stations))()
+    keep = []
+    for i, st in enumerate(stations):
+        s, k = st.to_c()
+        arr[i] = s
+        keep.append(k)
+    return arr, keep
+
+
+def validate(common: Common, stations) -> None:
+    """Host-only validation of an image_cadence call (no device work)."""
+    lib = load()
+    c, keep1 = common.to_c()
+    arr, keep = _stations_c(stations)
+    _check(lib.epic_validate(ctypes.byref(c), arr, len(stations)))
+
+
+def image_cadence(common: Common, stations, stream=None):
+    lib = load()
+    c, keep1 = common.to_c()
+    arr, keep = _stations_c(stations)
+    _check(lib.image_cadence(ctypes.byref(c), arr, len(stations), _stream(stream)))

@@ -1,0 +1,198 @@
+"""GPU parity: every ABI call against the FP64 oracle on the same seeded inputs.
+
+Tolerances (per image, the max-abs error over pixels divided by the image
+scale: max |I^{aa}| for auto products, sqrt(max XX max YY) for cross products):
+FP32 transform path <= 1e-5.  Stage tests use max-abs error over the max
+magnitude of the oracle's result.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_util import (from_complex, say, station_objects, to_complex, to_device_volts,
+                            torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = torch_cuda()
+    from paper_2411_17804_amd import epic
+    epic.load()
+    return t
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+# ------------------------------------------------------------------ grid ----
+@pytest.mark.parametrize("case", ["C1", "C2", "C2-nearest-ci8", "C3", "C5"])
+def test_grid_voltages(torch, case):
+    from paper_2411_17804_amd import epic
+    say(f"grid_voltages {case}")
+    if case == "C1":
+        cfg = W.make_config(1, n_time=6)
+    elif case.startswith("C2"):
+        cfg = W.make_config(2, chan_subset=[0, 17, 1023], n_time=6)
+    elif case == "C3":
+        cfg = W.make_config(3, chan_subset=[5, 200], n_time=5)
+    else:
+        cfg = W.make_config(5, chan_subset=[127], n_time=4)
+    st = cfg.stations[0]
+    ktype, K, sig = st.kernel_type, st.support, st.sigma_cells
+    if case == "C2-nearest-ci8":
+        ktype, K, sig = W.KERNEL_NEAREST, 1, 0.0
+    v = W.station_volts(cfg, 0)
+    common, (station,) = station_objects(cfg, [to_device_volts(v)])
+    station.kernel_type, station.support, station.sigma_cells = ktype, K, sig
+    t0, nt = 2, cfg.n_time - 3
+    grid = torch.zeros((cfg.n_chan, nt, cfg.n_pol, st.ny, st.nx, 2), dtype=torch.float32,
+                       device="cuda")
+    epic.grid_voltages(common, station, t0, nt, grid)
+    torch.cuda.synchronize()
+    got = to_complex(grid)
+    for c in range(cfg.n_chan):
+        ref = oracle.grid(st.pos_m, cfg.wavelengths_m[c], W.GRID_SPACING_WL, st.nx, st.ny, ktype,
+                          K, sig, v[c], t0=t0, nt=nt)
+        if case == "C2-nearest-ci8":
+            assert np.array_equal(got[c], ref), "integer sums must be exact"
+        else:
+            assert _rel(got[c], ref) <= 1e-6, (case, c, _rel(got[c], ref))
+
+
+# ------------------------------------------------------------------- fft ----
+FFT_SHAPES = [(16, 16), (32, 32), (64, 64), (128, 128), (256, 256), (32, 16), (16, 64),
+              (128, 64), (64, 256), (256, 32), (256, 128)]
+
+
+@pytest.mark.parametrize("nx,ny", FFT_SHAPES)
+def test_fft2_batched_fp32(torch, nx, ny):
+    from paper_2411_17804_amd import epic
+    say(f"fft2_batched fp32 {nx}x{ny}")
+    rng = np.random.default_rng([17804, nx, ny])
+    batch = 3
+    x = (rng.standard_normal((batch, ny, nx)) + 1j * rng.standard_normal((batch, ny, nx)))
+    x = x.astype(np.complex64).astype(np.complex128)
+    xin = from_complex(x)
+    out = torch.empty_like(xin)
+    epic.fft2_batched(nx, ny, batch, epic.FP32_FFT, xin, out)
+    torch.cuda.synchronize()
+    ref = oracle.fft2(x)
+    err = _rel(to_complex(out), ref)
+    assert err <= 2e-6, err
+    # in place gives the same bits
+    epic.fft2_batched(nx, ny, batch, epic.FP32_FFT, xin, xin)
+    torch.cuda.synchronize()
+    assert torch.equal(xin, out)
+
+
+# ----------------------------------------------------------------- power ----
+@pytest.mark.parametrize("n_pol", [1, 2])
+def test_accumulate_power(torch, n_pol):
+    from paper_2411_17804_amd import epic
+    say(f"accumulate_power n_pol={n_pol}")
+    rng = np.random.default_rng([17804, 77, n_pol])
+    n_chan, nt, ny, nx = 3, 37, 32, 16
+    f = rng.standard_normal((n_chan, nt, n_pol, ny, nx)) + 1j * rng.standard_normal(
+        (n_chan, nt, n_pol, ny, nx))
+    f = (f * 50).astype(np.complex64).astype(np.complex128)
+    fd = from_complex(f)
+    shape = (n_chan, n_pol * n_pol, ny, nx, 2)
+    s1, c1, img1 = (torch.zeros(shape, device="cuda") for _ in range(3))
+    epic.accumulate_power(n_pol, nx, ny, n_chan, nt, fd, s1, c1, nt, img1)
+    # the same cadence split over two calls: bit-identical
+    s2, c2, img2 = (torch.zeros(shape, device="cuda") for _ in range(3))
+    a = 20
+    epic.accumulate_power(n_pol, nx, ny, n_chan, a, from_complex(f[:, :a]), s2, c2, 0, None)
+    epic.accumulate_power(n_pol, nx, ny, n_chan, nt - a, from_complex(f[:, a:]), s2, c2, nt, img2)
+    torch.cuda.synchronize()
+    assert torch.equal(img1, img2)
+    got = to_complex(img1)
+    for c in range(n_chan):
+        ref = oracle.power_mean(f[c])
+        err = oracle.image_error(got[c], ref, n_pol)
+        assert err.max() <= 1e-6, err
+    if n_pol == 2:
+        assert np.array_equal(got[:, 2], np.conj(got[:, 1]))
+        assert np.all(got[:, 0].imag == 0) and np.all(got[:, 3].imag == 0)
+
+
+# ---------------------------------------------------------- image_cadence ----
+def run_cadence(cfg, precision=None):
+    from paper_2411_17804_amd import epic
+    torch = torch_cuda()
+    volts = [W.station_volts(cfg, s) for s in range(len(cfg.stations))]
+    common, stations = station_objects(cfg, [to_device_volts(v) for v in volts], precision)
+    epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    return volts, [to_complex(s.image) for s in stations], (common, stations)
+
+
+def oracle_image(cfg, s, v):
+    st = cfg.stations[s]
+    return oracle.image(st.pos_m, cfg.wavelengths_m, W.GRID_SPACING_WL, st.nx, st.ny,
+                        st.kernel_type, st.support, st.sigma_cells, v)
+
+
+CADENCE_CASES = {
+    # name: (config, channel subset, n_time)
+    "C1-full": (1, None, None),
+    "C2-3ch": (2, [0, 600, 1023], 96),
+    "C2-ragged-time": (2, [3], 37),
+    "C3-2ch": (3, [0, 255], 12),
+    "C5-1ch": (5, [64], 3),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CADENCE_CASES))
+def test_image_cadence_fp32(torch, case):
+    idx, chans, nt = CADENCE_CASES[case]
+    say(f"image_cadence fp32 {case}")
+    cfg = W.make_config(idx, chan_subset=chans, n_time=nt, precision=W.FP32_FFT)
+    volts, imgs, _ = run_cadence(cfg)
+    for s in range(len(cfg.stations)):
+        ref = oracle_image(cfg, s, volts[s])
+        err = oracle.image_error(imgs[s], ref, cfg.n_pol)
+        say(f"  {case} station {s}: worst error {err.max():.2e}")
+        assert err.max() <= FP32_TOL, err
+        if cfg.n_pol == 2:
+            assert np.array_equal(imgs[s][:, 2], np.conj(imgs[s][:, 1]))
+            assert np.all(imgs[s][:, 0].imag == 0) and np.all(imgs[s][:, 3].imag == 0)
+
+
+def test_image_cadence_deterministic(torch):
+    say("image_cadence determinism C2")
+    cfg = W.make_config(2, chan_subset=[1, 2], n_time=64)
+    _, a, (common, stations) = run_cadence(cfg)
+    from paper_2411_17804_amd import epic
+    epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    assert np.array_equal(a[0], to_complex(stations[0].image))
+
+
+def test_point_source_through_the_gpu_path(torch):
+    # a plane wave from pixel (kx', ky') = (5, -3) must peak there (sign pin)
+    from paper_2411_17804_amd import epic
+    say("image_cadence point source")
+    cfg = W.make_config(2, chan_subset=[512], n_time=8)
+    st = cfg.stations[0]
+    lam = cfg.wavelengths_m[0]
+    l, m = 5 / (st.nx * W.GRID_SPACING_WL), -3 / (st.ny * W.GRID_SPACING_WL)
+    ph = np.exp(-2j * np.pi * (l * st.pos_m[:, 0] + m * st.pos_m[:, 1]) / lam)
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal(8) + 1j * rng.standard_normal(8)
+    v = (A[:, None, None] * ph[None, :, None] * np.ones((1, 1, 2))).astype(np.complex64)[None]
+    cfg.volt_type = W.CF32
+    common, (station,) = station_objects(cfg, [to_device_volts(v)])
+    epic.image_cadence(common, [station])
+    torch.cuda.synchronize()
+    img = to_complex(station.image)[0, 0].real
+    assert np.unravel_index(np.argmax(img), img.shape) == (-3 % st.ny, 5 % st.nx)
+    ref = oracle.image(st.pos_m, cfg.wavelengths_m, 0.5, st.nx, st.ny, st.kernel_type, st.support,
+                       st.sigma_cells, v)
+    assert oracle.image_error(to_complex(station.image), ref, 2).max() <= FP32_TOL
