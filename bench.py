@@ -44,6 +44,36 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# Sources of each timed kernel: a counter summary under profiles/ is only used
+# while the hash of these files matches the one recorded with the counters.
+KERNEL_SOURCES = {
+    "fused_fft_cadence": ["k_fused.hip", "fft_lds.hpp", "volts.hpp"],
+    "fused_dft_cadence": ["k_fused_dft.hip", "mfma_split.hpp", "volts.hpp"],
+}
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from profiles/<kernel>_<workload>_hbm_bytes.md, or
+    None if there is no summary or the kernel changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_bytes.md")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_b = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    m_h = re.search(r"source_sha256_16: ([0-9a-f]+)", text)
+    if not (m_b and m_h):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        p = os.path.join(ROOT, "paper_2411_17804_amd", "csrc", f)
+        if not os.path.exists(p):
+            return None
+        h.update(open(p, "rb").read())
+    return int(m_b.group(1)) if h.hexdigest()[:16] == m_h.group(1) else None
+
+
 def flops_per_pixel_sample(cfg, st):
     """Algorithmic FP32 work per grid pixel-sample of the FFT path.
 
@@ -70,7 +100,21 @@ def main():
     ap.add_argument("--cpu-channels", type=int, default=64,
                     help="channels of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (to scale the HBM "
+                         "byte counters of a profiler run)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = 1 << 28                       # 2^28 float32 = 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": 4 * n, "launches": 3}))
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the path shards by channel "
@@ -141,7 +185,9 @@ def main():
         achieved = work / (dom_avg_ms / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3),
                 "peak": round(PEAK_FP32_VALU_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
+                "traffic": measured_traffic(dom_name, f"C{cfg.index}")
+                if cfg.n_chan == W.make_config(cfg.index).n_chan and args.n_time is None else None,
                 "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4),
                 "flop_per_pixel_sample": round(flop_px, 2)}
     else:
