@@ -1,12 +1,239 @@
-// k_dft.hip -- split-precision DFT-matrix transform (placeholder until the
-// MFMA kernels land).
+// k_dft.hip -- the 2-D transform of Eq. 3 (outer sum) as dense DFT-matrix
+// products on gfx950 matrix cores, in split precision (EPIC_FP16_SPLIT /
+// EPIC_BF16_SPLIT): Z = F_y . X . F_x^T with F_n[k][j] = exp(+2 pi i k j / n).
+//
+// One pass computes, for every batch item, P = F_n . X (X: [n][m] complex,
+// transform along the first axis) and stores P transposed ([m][n]).  Two
+// passes, the second on the first's output, give the 2-D transform in natural
+// layout.  The DFT matrix is generated on the host in FP64 (angle reduced as
+// the integer (k j mod n) / n), split into hi + lo parts and stored in MFMA
+// A-fragment order.  Each work-group scales its block of input columns by a
+// power of two so the FP16 parts cannot overflow (exact, undone on store).
+#include <cmath>
+#include <vector>
+
 #include "internal.hpp"
+#include "mfma_split.hpp"
 
 namespace epic {
 
-epic_status launch_dft2_split(int, int, int64_t, int, const float2 *, float2 *, int, hipStream_t)
+epic_status cache_dft_table(int n, int precision, int device, size_t bytes,
+                            void (*fill)(int, int, void *), const void **out);
+
+namespace {
+
+// Host: complex DFT matrix of size n as the real 2x2-block A operand.
+// Row m of an M-tile holds output k = 8 mt + m/2, part m%2 (re, im); K entry
+// kk of a K-step holds input j = 16 ks + kk/2, part kk%2.
+template <typename T>
+void fill_tables(int n, void *dst)
 {
-    return fail(EPIC_ERR_UNSUPPORTED, "split-precision transform not built yet");
+    const int MT = 2 * n / 16, KS = n / 16;
+    T *hi = static_cast<T *>(dst);
+    T *lo = hi + static_cast<size_t>(MT) * KS * 64 * 8;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int mt = 0; mt < MT; ++mt)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int r = 0; r < 8; ++r) {
+                    const int m = lane % 16, kk = 8 * (lane / 16) + r;
+                    const long k = 8 * mt + m / 2, j = 16 * ks + kk / 2;
+                    const double ang = two_pi * static_cast<double>((k * j) % n) / n;
+                    const double fr = std::cos(ang), fi = std::sin(ang);
+                    const bool out_im = (m % 2) == 1, in_im = (kk % 2) == 1;
+                    const double v = !out_im ? (!in_im ? fr : -fi) : (!in_im ? fi : fr);
+                    const T h = static_cast<T>(v);
+                    const T l = static_cast<T>(v - static_cast<double>(h));
+                    const size_t idx = ((static_cast<size_t>(mt) * KS + ks) * 64 + lane) * 8 + r;
+                    hi[idx] = h;
+                    lo[idx] = l;
+                }
+}
+
+void fill_any(int n, int precision, void *dst)
+{
+    if (precision == EPIC_FP16_SPLIT)
+        fill_tables<_Float16>(n, dst);
+    else
+        fill_tables<__bf16>(n, dst);
+}
+
+}  // namespace
+
+epic_status get_dft_tables(int n, int precision, int device, const void **out)
+{
+    const size_t bytes = static_cast<size_t>(2 * n / 16) * (n / 16) * 64 * 8 * 2 * 2;
+    return cache_dft_table(n, precision, device, bytes, fill_any, out);
+}
+
+template <int N, int NTW, int PREC>
+__global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
+                                                  float2 *__restrict__ out, int M,
+                                                  const typename Split<PREC>::vec8 *__restrict__ tab)
+{
+    using S = Split<PREC>;
+    using vec8 = typename S::vec8;
+    using scalar = typename S::scalar;
+    constexpr int CB = 16 * NTW;          // input columns per work-group
+    constexpr int MT = 2 * N / 16;        // real M-tiles of P
+    constexpr int KS = N / 16;            // K-steps
+    constexpr int MTW = (MT + 3) / 4;     // M-tiles per wave
+    constexpr int JP = N + 4;             // LDS pitch (packed complex) per column
+    extern __shared__ uint32_t lds[];
+    uint32_t *lhi = lds;                  // [CB][JP] (re, im) hi parts
+    uint32_t *llo = lds + CB * JP;        // [CB][JP] lo parts
+    __shared__ float red[4];
+
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int g = lane / 16, r = lane % 16;
+    const size_t b = blockIdx.y;
+    const int c0 = blockIdx.x * CB;
+    const float2 *src = in + b * N * M;
+
+    float s = 1.f;
+    if constexpr (S::needs_scale) {
+        float mx = 0.f;
+        for (int i = threadIdx.x; i < N * CB; i += 256) {
+            const float2 v = src[(i / CB) * M + c0 + i % CB];
+            mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        if (lane == 0) red[wave] = mx;
+        __syncthreads();
+        mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        s = pow2_scale(mx);
+    }
+    for (int i = threadIdx.x; i < N * CB; i += 256) {
+        const int j = i / CB, c = i % CB;
+        const float2 v = src[j * M + c0 + c];
+        scalar hr, lr, hi_, li;
+        split<PREC>(v.x * s, hr, lr);
+        split<PREC>(v.y * s, hi_, li);
+        const uint32_t ph = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hr)) |
+                            (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hi_)) << 16);
+        const uint32_t pl = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, lr)) |
+                            (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, li)) << 16);
+        lhi[c * JP + j] = ph;
+        llo[c * JP + j] = pl;
+    }
+    __syncthreads();
+
+    floatx4_t acc[MTW][NTW];
+#pragma unroll
+    for (int w = 0; w < MTW; ++w)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) acc[w][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+
+    const vec8 *tab_lo = tab + static_cast<size_t>(MT) * KS * 64;
+    for (int ks = 0; ks < KS; ++ks) {
+        vec8 ah[MTW], al[MTW];
+#pragma unroll
+        for (int w = 0; w < MTW; ++w) {
+            const int mt = wave + 4 * w;
+            if (mt < MT) {
+                ah[w] = tab[(mt * KS + ks) * 64 + lane];
+                al[w] = tab_lo[(mt * KS + ks) * 64 + lane];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const int c = t * 16 + r, j0 = ks * 16 + 4 * g;
+            const vec8 bh = *reinterpret_cast<const vec8 *>(&lhi[c * JP + j0]);
+            const vec8 bl = *reinterpret_cast<const vec8 *>(&llo[c * JP + j0]);
+#pragma unroll
+            for (int w = 0; w < MTW; ++w)
+                if (wave + 4 * w < MT) acc[w][t] = mma3<PREC>(ah[w], al[w], bh, bl, acc[w][t]);
+        }
+    }
+
+    const float inv = 1.f / s;
+#pragma unroll
+    for (int w = 0; w < MTW; ++w) {
+        const int mt = wave + 4 * w;
+        if (mt >= MT) continue;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const int c = c0 + t * 16 + r;
+            const int k = mt * 8 + 2 * g;
+            const floatx4_t a = acc[w][t];
+            float4 v = make_float4(a[0] * inv, a[1] * inv, a[2] * inv, a[3] * inv);
+            *reinterpret_cast<float4 *>(&out[(b * M + c) * N + k]) = v;
+        }
+    }
+}
+
+namespace {
+
+template <int N, int NTW, int PREC>
+epic_status run_pass(int64_t batch, int m, const float2 *in, float2 *out, const void *tab,
+                     hipStream_t stream)
+{
+    constexpr int CB = 16 * NTW;
+    const size_t bytes = sizeof(uint32_t) * 2 * CB * (N + 4);
+    auto k = k_dft_pass<N, NTW, PREC>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(bytes));
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    KernelTimer timer("dft_gemm_pass", stream);
+    for (int64_t b0 = 0; b0 < batch; b0 += 65535) {
+        const int64_t nb = std::min<int64_t>(65535, batch - b0);
+        hipLaunchKernelGGL(k, dim3(m / CB, static_cast<unsigned>(nb)), dim3(256), bytes, stream,
+                           in + b0 * N * m, out + b0 * N * m, m,
+                           static_cast<const typename Split<PREC>::vec8 *>(tab));
+        EPIC_HIP_TRY(hipGetLastError());
+    }
+    return EPIC_OK;
+}
+
+template <int N, int PREC>
+epic_status pass_n(int64_t batch, int m, const float2 *in, float2 *out, const void *tab,
+                   hipStream_t stream)
+{
+    // columns per work-group: as many as the accumulators allow
+    constexpr int MAX_NTW = N >= 128 ? 2 : 4;
+    if (m >= 16 * MAX_NTW) return run_pass<N, MAX_NTW, PREC>(batch, m, in, out, tab, stream);
+    if (m >= 32) return run_pass<N, 2, PREC>(batch, m, in, out, tab, stream);
+    return run_pass<N, 1, PREC>(batch, m, in, out, tab, stream);
+}
+
+template <int PREC>
+epic_status pass_any(int n, int64_t batch, int m, const float2 *in, float2 *out, const void *tab,
+                     hipStream_t stream)
+{
+    switch (n) {
+    case 16: return pass_n<16, PREC>(batch, m, in, out, tab, stream);
+    case 32: return pass_n<32, PREC>(batch, m, in, out, tab, stream);
+    case 64: return pass_n<64, PREC>(batch, m, in, out, tab, stream);
+    case 128: return pass_n<128, PREC>(batch, m, in, out, tab, stream);
+    case 256: return pass_n<256, PREC>(batch, m, in, out, tab, stream);
+    }
+    return fail(EPIC_ERR_INTERNAL, "dft pass: unexpected size");
+}
+
+}  // namespace
+
+epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, const float2 *in,
+                              float2 *out, int device, hipStream_t stream)
+{
+    const void *tab_y = nullptr, *tab_x = nullptr;
+    epic_status s = get_dft_tables(ny, precision, device, &tab_y);
+    if (s != EPIC_OK) return s;
+    s = get_dft_tables(nx, precision, device, &tab_x);
+    if (s != EPIC_OK) return s;
+    void *ws = nullptr;
+    s = get_workspace(device, stream, 3, sizeof(float2) * static_cast<size_t>(batch) * nx * ny, &ws);
+    if (s != EPIC_OK) return s;
+    float2 *mid = static_cast<float2 *>(ws);
+    // pass 1: along y (input [ny][nx]) -> [nx][ny]; pass 2: along x -> [ny][nx]
+    if (precision == EPIC_FP16_SPLIT) {
+        s = pass_any<EPIC_FP16_SPLIT>(ny, batch, nx, in, mid, tab_y, stream);
+        if (s != EPIC_OK) return s;
+        return pass_any<EPIC_FP16_SPLIT>(nx, batch, ny, mid, out, tab_x, stream);
+    }
+    s = pass_any<EPIC_BF16_SPLIT>(ny, batch, nx, in, mid, tab_y, stream);
+    if (s != EPIC_OK) return s;
+    return pass_any<EPIC_BF16_SPLIT>(nx, batch, ny, mid, out, tab_x, stream);
 }
 
 }  // namespace epic

@@ -196,3 +196,59 @@ def test_point_source_through_the_gpu_path(torch):
     ref = oracle.image(st.pos_m, cfg.wavelengths_m, 0.5, st.nx, st.ny, st.kernel_type, st.support,
                        st.sigma_cells, v)
     assert oracle.image_error(to_complex(station.image), ref, 2).max() <= FP32_TOL
+
+
+# ------------------------------------------------- split-precision DFT-GEMM ----
+SPLIT_TOL = {"fp16": 1e-4, "bf16": 2e-3}   # fp16 is the gate; bf16 is reported with a bound
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("nx,ny", [(16, 16), (32, 64), (64, 64), (128, 128), (256, 256),
+                                   (256, 32), (16, 128)])
+def test_fft2_batched_split(torch, prec, nx, ny):
+    from paper_2411_17804_amd import epic
+    say(f"fft2_batched {prec} {nx}x{ny}")
+    p = epic.FP16_SPLIT if prec == "fp16" else epic.BF16_SPLIT
+    rng = np.random.default_rng([17804, nx, ny, 9])
+    batch = 3
+    x = rng.standard_normal((batch, ny, nx)) + 1j * rng.standard_normal((batch, ny, nx))
+    x[1] *= 3e6            # beyond FP16 range: the per-block power-of-two scale must handle it
+    x[2] *= 1e-6
+    x = x.astype(np.complex64).astype(np.complex128)
+    xin = from_complex(x)
+    out = torch.empty_like(xin)
+    epic.fft2_batched(nx, ny, batch, p, xin, out)
+    torch.cuda.synchronize()
+    got = to_complex(out)
+    ref = oracle.fft2(x)
+    errs = [_rel(got[b], ref[b]) for b in range(batch)]
+    say(f"  {prec} {nx}x{ny}: errors {['%.2e' % e for e in errs]}")
+    assert max(errs) <= SPLIT_TOL[prec], errs
+    # in place
+    epic.fft2_batched(nx, ny, batch, p, xin, xin)
+    torch.cuda.synchronize()
+    assert torch.equal(xin, out)
+
+
+SPLIT_CASES = {
+    "C2-fp16-2ch": (2, [0, 1023], 40, "fp16"),
+    "C3-fp16-2ch": (3, [0, 255], 12, "fp16"),
+    "C3-bf16-1ch": (3, [100], 8, "bf16"),
+    "C5-fp16-1ch": (5, [0], 3, "fp16"),
+    "C5-bf16-1ch": (5, [127], 3, "bf16"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SPLIT_CASES))
+def test_image_cadence_split(torch, case):
+    idx, chans, nt, prec = SPLIT_CASES[case]
+    say(f"image_cadence {case}")
+    p = W.FP16_SPLIT if prec == "fp16" else W.BF16_SPLIT
+    cfg = W.make_config(idx, chan_subset=chans, n_time=nt, precision=p)
+    volts, imgs, _ = run_cadence(cfg)
+    for s in range(len(cfg.stations)):
+        ref = oracle_image(cfg, s, volts[s])
+        err = oracle.image_error(imgs[s], ref, cfg.n_pol)
+        say(f"  {case} station {s}: worst error {err.max():.2e}")
+        assert err.max() <= SPLIT_TOL[prec], err
+        assert np.array_equal(imgs[s][:, 2], np.conj(imgs[s][:, 1]))
