@@ -79,12 +79,16 @@ StationDev make_station_dev(const epic_station *s, const PlanHandle &p)
     d.chan = p.chan;
     d.cell_start = p.cell_start;
     d.taps = p.taps;
+    d.cell_order = p.cell_order;
     d.volts = s->volts;
     d.image = static_cast<float2 *>(s->image);
     d.n_elem = s->n_elem;
     d.nx = s->nx;
     d.ny = s->ny;
     d.log2n = ilog2(s->nx);
+    d.ktaps = s->kernel.support * s->kernel.support;
+    d.max_cells = p.max_box;
+    d.max_cell_taps = p.max_cell_taps;
     return d;
 }
 

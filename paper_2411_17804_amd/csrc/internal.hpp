@@ -36,11 +36,15 @@ struct StationDev {
     const ChanPlan *chan;     // [n_chan]
     const int32_t *cell_start;// per channel: [bw*bh + 1] offsets relative to tap_off
     const Tap *taps;          // per channel: taps in cell order
+    const int32_t *cell_order;// per channel: box cells by descending tap count (cell_off based)
     const void *volts;        // [n_chan][n_time][n_elem][n_pol]
     float2 *image;            // [n_chan][n_pol^2][ny][nx]
     int32_t n_elem;
     int32_t nx, ny;
     int32_t log2n;            // log2(nx) (square grids in the fused kernels)
+    int32_t ktaps;            // taps per element (support^2): n_elem*ktaps taps per channel
+    int32_t max_cells;        // max footprint-box cells over channels
+    int32_t max_cell_taps;    // max taps landing on one cell over channels
 };
 
 // ---------------------------------------------------------------------------
@@ -79,8 +83,10 @@ struct PlanHandle {
     const ChanPlan *chan = nullptr;
     const int32_t *cell_start = nullptr;
     const Tap *taps = nullptr;
+    const int32_t *cell_order = nullptr;
     int32_t max_box = 0;       // max bw*bh over channels
     int32_t max_bw = 0, max_bh = 0;
+    int32_t max_cell_taps = 0; // max taps landing on one cell over channels
     int64_t n_taps_total = 0;
 };
 

@@ -114,7 +114,281 @@ __global__ __launch_bounds__(FusedShape<N>::BLOCK) void k_fused_fft(StationDev s
     }
 }
 
+// ---------------------------------------------------------------------------
+// 64 x 64 grids: the 8 x 8 decomposition of each 64-point transform is kept in
+// registers.  Per sample, in the Stockham notation of fft_lds.hpp:
+//   R1  thread (row y, j) grids cells x = j + 8m straight into registers and
+//       does the first radix-8 pass; outputs land at x = 8j + k1;
+//   R2  the same thread reads x = j + 8r, twiddles by exp(+2 pi i r j / 64),
+//       does the second pass in place (outputs at j + 8k);
+//   C1, C2  the same two passes along y for column kx (rows outside the
+//       footprint are zero), and C2 leaves pixel (ky = j + 8k, kx) of both
+//       pols in the registers of one thread, which squares and accumulates.
+// LDS holds one 64 x 64 plane per pol under an XOR swizzle of the low five bits
+// of x that keys on y, chosen so that every access pattern above spreads a
+// wave's 64 lanes evenly over the banks (row tasks of a wave are 8 rows
+// apart).  The next sample's voltages are prefetched into registers and
+// staged in a second LDS buffer while the current sample is transformed.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int sw64(int y, int x)
+{
+    const int t = (y ^ (y >> 3)) & 7;
+    return y * 64 + (x ^ (t | ((t & 3) << 3)));
+}
+
+constexpr int kFused64Block = 512;
+constexpr int kFused64Rounds = 8;     // gather rounds: box cells <= 8 * 512
+constexpr int kFused64Prefetch = 4;   // raw voltage words per thread per sample (<= 8 KB/sample)
+constexpr size_t kLdsBytes = 160 * 1024;
+
+// LDS of the 64 x 64 kernel: transform planes, the gathered footprint box,
+// two voltage buffers (as float), the channel's gather taps.
+inline size_t fused64_lds_bytes(int np, const StationDev &sd, int max_cells)
+{
+    return sizeof(float2) * np * 64 * 64 + sizeof(float2) * np * max_cells +
+           sizeof(float2) * 2 * np * static_cast<size_t>(sd.n_elem) +
+           sizeof(Tap) * static_cast<size_t>(sd.n_elem) * sd.ktaps;
+}
+
+template <int NP, int VT>
+__global__ __launch_bounds__(kFused64Block) void k_fused_fft64(StationDev sd, int n_time, int chunk,
+                                                               float *__restrict__ partials,
+                                                               const float2 *__restrict__ twg,
+                                                               int vwords, int max_cells)
+{
+    constexpr int PLANE = 64 * 64;
+    constexpr int NQ = NP == 2 ? 4 : 1;
+    constexpr int BLOCK = kFused64Block;
+    extern __shared__ float2 lds[];
+    float2 *buf = lds;                                   // [NP][PLANE], swizzled
+    float2 *gb = buf + NP * PLANE;                       // [NP][max_cells] gathered box
+    float2 *vf = gb + NP * max_cells;                    // [2][n_elem][NP] voltages
+    Tap *taps_l = reinterpret_cast<Tap *>(vf + 2 * NP * sd.n_elem);
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int j = lane & 7;                 // butterfly index in every pass
+    const int yl = wv + 8 * (lane >> 3);    // row task (rows of a wave are 8 apart)
+    const int kx = tid >> 3;                // column task
+    const int ck = blockIdx.x, c = blockIdx.y;
+    const int n_chunks = gridDim.x;
+    const int t_begin = ck * chunk;
+    const int t_end = min(n_time, t_begin + chunk);
+    const ChanPlan cp = sd.chan[c];
+    const bool row_active = yl < cp.bh;
+    const int y = cp.y0 + yl;
+    const int ncell = cp.bw * cp.bh;
+
+    // gather jobs of this thread: box cells in descending tap-count order,
+    // packed as cell << 20 | count << 16 | first tap
+    uint32_t job[kFused64Rounds];
+    {
+        const int32_t *cs = sd.cell_start + cp.cell_off;
+        const int32_t *ord = sd.cell_order + cp.cell_off;
+        const Tap *taps = sd.taps + cp.tap_off;
+        const int ntap = cs[ncell];
+        for (int i = tid; i < ntap; i += BLOCK) taps_l[i] = taps[i];
+#pragma unroll
+        for (int q = 0; q < kFused64Rounds; ++q) {
+            const int i = tid + q * BLOCK;
+            job[q] = 0xffffffffu;
+            if (i < ncell) {
+                const int cell = ord[i];
+                const int k0 = cs[cell];
+                job[q] = (static_cast<uint32_t>(cell) << 20) |
+                         (static_cast<uint32_t>(cs[cell + 1] - k0) << 16) | static_cast<uint32_t>(k0);
+            }
+        }
+    }
+
+    float2 tw[8];
+#pragma unroll
+    for (int r = 1; r < 8; ++r) tw[r] = twg[r * j];
+
+    // swizzled LDS addresses (see sw64): rows of this thread's row task ...
+    const int tr = (y ^ (y >> 3)) & 7;
+    const int sr = tr | ((tr & 3) << 3);
+    const int bt = y * 64 + ((8 * j) ^ (sr & 0x18)) + tr;   // x = 8j + k  -> bt ^ k
+    const int bj = y * 64 + (j ^ tr) + (sr & 0x18);          // x = j + 8r  -> bj ^ 8r
+    // ... and of this thread's column task: rows j + 8m -> cm[m] + 512 m,
+    // rows 8j + k -> cm[k] + 448 j + 64 k
+    int cm[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int t = (j ^ m) & 7;
+        cm[m] = j * 64 + (kx ^ (t | ((t & 3) << 3)));
+    }
+    const int dj = 448 * j;
+
+    // voltages of sample t as float pairs in vf[buffer]
+    auto stash = [&](int buffer, int i, uint32_t w) {
+        float2 *dst = vf + buffer * NP * sd.n_elem;
+        if constexpr (VT == EPIC_CI8) {
+            dst[2 * i] = make_float2(static_cast<float>(static_cast<int8_t>(w & 0xff)),
+                                     static_cast<float>(static_cast<int8_t>((w >> 8) & 0xff)));
+            dst[2 * i + 1] = make_float2(static_cast<float>(static_cast<int8_t>((w >> 16) & 0xff)),
+                                         static_cast<float>(static_cast<int8_t>((w >> 24) & 0xff)));
+        } else {
+            reinterpret_cast<uint32_t *>(dst)[i] = w;
+        }
+    };
+    const uint32_t *vsrc = reinterpret_cast<const uint32_t *>(sd.volts) +
+                           static_cast<size_t>(c) * n_time * vwords;
+    for (int i = tid; i < vwords; i += BLOCK) stash(0, i, vsrc[static_cast<size_t>(t_begin) * vwords + i]);
+
+    float acc[8][NQ];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[k][q] = 0.f;
+    __syncthreads();
+
+    int cur = 0;
+    for (int t = t_begin; t < t_end; ++t) {
+        const bool has_next = t + 1 < t_end;
+        uint32_t pre[kFused64Prefetch];
+        if (has_next) {
+#pragma unroll
+            for (int q = 0; q < kFused64Prefetch; ++q) {
+                const int i = tid + q * BLOCK;
+                if (i < vwords) pre[q] = vsrc[static_cast<size_t>(t + 1) * vwords + i];
+            }
+        }
+        // G: grid the footprint box (Eq. 3 inner bracket), one cell per job
+        {
+            const float2 *vcur = vf + cur * NP * sd.n_elem;
+#pragma unroll
+            for (int q = 0; q < kFused64Rounds; ++q) {
+                if (job[q] != 0xffffffffu) {
+                    const int cell = job[q] >> 20, kn = (job[q] >> 16) & 15, k0 = job[q] & 0xffff;
+                    float2 a[NP];
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) a[p] = make_float2(0.f, 0.f);
+                    for (int s = 0; s < kn; ++s) {
+                        const Tap tp = taps_l[k0 + s];
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) {
+                            const float2 e = vcur[tp.elem * NP + p];
+                            a[p].x = fmaf(tp.w, e.x, a[p].x);
+                            a[p].y = fmaf(tp.w, e.y, a[p].y);
+                        }
+                    }
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) gb[p * max_cells + cell] = a[p];
+                }
+            }
+        }
+        if (has_next) {
+#pragma unroll
+            for (int q = 0; q < kFused64Prefetch; ++q) {
+                const int i = tid + q * BLOCK;
+                if (i < vwords) stash(cur ^ 1, i, pre[q]);
+            }
+        }
+        __syncthreads();
+        // R1: first radix-8 pass along x on the box rows (cells outside the box are 0)
+        if (row_active) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                float2 v[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int bx = j + 8 * m - cp.x0;
+                    v[m] = (bx >= 0 && bx < cp.bw) ? gb[p * max_cells + yl * cp.bw + bx]
+                                                   : make_float2(0.f, 0.f);
+                }
+                Dft<8>::run(v);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) buf[p * PLANE + (bt ^ k)] = v[k];
+            }
+        }
+        __syncthreads();
+        // R2: second radix-8 pass along x, in place
+        if (row_active) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                float2 v[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) v[r] = buf[p * PLANE + (bj ^ (8 * r))];
+#pragma unroll
+                for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], tw[r]);
+                Dft<8>::run(v);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) buf[p * PLANE + (bj ^ (8 * r))] = v[r];
+            }
+        }
+        __syncthreads();
+        // C1: first radix-8 pass along y for column kx (rows outside the box are 0)
+        {
+            float2 v[NP][8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int yy = j + 8 * m;
+                const bool in = yy >= cp.y0 && yy < cp.y0 + cp.bh;
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    v[p][m] = in ? buf[p * PLANE + cm[m] + 512 * m] : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p) Dft<8>::run(v[p]);
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) buf[p * PLANE + cm[k] + dj + 64 * k] = v[p][k];
+        }
+        __syncthreads();
+        // C2: second pass along y; pixel (ky = j + 8k, kx) of both pols is here
+        {
+            float2 v[NP][8];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) v[p][r] = buf[p * PLANE + cm[r] + 512 * r];
+#pragma unroll
+                for (int r = 1; r < 8; ++r) v[p][r] = cmul(v[p][r], tw[r]);
+                Dft<8>::run(v[p]);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float2 fx = v[0][k];
+                acc[k][0] = fmaf(fx.x, fx.x, fmaf(fx.y, fx.y, acc[k][0]));
+                if constexpr (NP == 2) {
+                    const float2 fy = v[1][k];
+                    acc[k][1] = fmaf(fx.x, fy.x, fmaf(fx.y, fy.y, acc[k][1]));
+                    acc[k][2] = fmaf(fx.y, fy.x, fmaf(-fx.x, fy.y, acc[k][2]));
+                    acc[k][3] = fmaf(fy.x, fy.x, fmaf(fy.y, fy.y, acc[k][3]));
+                }
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    float *out = partials + (static_cast<size_t>(c) * n_chunks + ck) * NQ * PLANE;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q * PLANE + (j + 8 * k) * 64 + kx] = acc[k][q];
+}
+
 namespace {
+
+template <int NP, int VT>
+epic_status run_fused64(const StationDev &sd, int n_chan, int n_time, int chunk, float *partials,
+                        const float2 *tw, int vwords, int max_cells, hipStream_t stream)
+{
+    const size_t bytes = fused64_lds_bytes(NP, sd, max_cells);
+    auto k = k_fused_fft64<NP, VT>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(bytes));
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    const int n_chunks = (n_time + chunk - 1) / chunk;
+    KernelTimer timer("fused_fft_cadence", stream);
+    hipLaunchKernelGGL(k, dim3(n_chunks, n_chan), dim3(kFused64Block), bytes, stream, sd, n_time,
+                       chunk, partials, tw, vwords, max_cells);
+    EPIC_HIP_TRY(hipGetLastError());
+    return EPIC_OK;
+}
 
 template <int N, int NP, int VT>
 epic_status run_fused(const StationDev &sd, int n_chan, int n_time, int chunk, float *partials,
@@ -139,6 +413,25 @@ template <int N>
 epic_status dispatch(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
                      int chunk, float *partials, const float2 *tw, hipStream_t stream)
 {
+    if constexpr (N == 64) {
+        // register-resident variant when one sample's voltages fit the
+        // prefetch and are a whole number of 32-bit words
+        const int64_t vbytes = static_cast<int64_t>(sd.n_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8);
+        const int vwords = static_cast<int>(vbytes / 4);
+        const int64_t taps_per_chan = static_cast<int64_t>(sd.n_elem) * sd.ktaps;
+        if (vbytes % 4 == 0 && vbytes / 4 <= kFused64Prefetch * kFused64Block &&
+            sd.max_cells <= kFused64Rounds * kFused64Block && sd.max_cell_taps <= 15 &&
+            taps_per_chan <= 0xffff && fused64_lds_bytes(n_pol, sd, sd.max_cells) <= kLdsBytes) {
+            const int mc = sd.max_cells;
+            if (n_pol == 2 && volt_type == EPIC_CI8)
+                return run_fused64<2, EPIC_CI8>(sd, n_chan, n_time, chunk, partials, tw, vwords, mc, stream);
+            if (n_pol == 2)
+                return run_fused64<2, EPIC_CF32>(sd, n_chan, n_time, chunk, partials, tw, vwords, mc, stream);
+            if (volt_type == EPIC_CI8)
+                return run_fused64<1, EPIC_CI8>(sd, n_chan, n_time, chunk, partials, tw, vwords, mc, stream);
+            return run_fused64<1, EPIC_CF32>(sd, n_chan, n_time, chunk, partials, tw, vwords, mc, stream);
+        }
+    }
     if (n_pol == 2 && volt_type == EPIC_CI8)
         return run_fused<N, 2, EPIC_CI8>(sd, n_chan, n_time, chunk, partials, tw, stream);
     if (n_pol == 2)

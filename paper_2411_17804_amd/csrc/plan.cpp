@@ -6,6 +6,7 @@
 // the kernel W~ is centred on r_a; the grid r_j is fixed in wavelengths so
 // the geometry is recomputed per channel).  Everything is computed in double
 // precision and rounded once to FP32 when stored.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -163,6 +164,7 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     const int nx = st->nx, ny = st->ny, h = (K - 1) / 2;
     std::vector<ChanPlan> chans(n_chan);
     std::vector<int32_t> cell_start;
+    std::vector<int32_t> cell_order;   // per channel: box cells by descending tap count
     std::vector<Tap> taps;
     std::vector<int> ci(n_elem), cj(n_elem);
     std::vector<double> wx(static_cast<size_t>(n_elem) * K), wy(static_cast<size_t>(n_elem) * K);
@@ -212,7 +214,17 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
                     const double w = wx[static_cast<size_t>(a) * K + dx + h] * wy[static_cast<size_t>(a) * K + dy + h];
                     taps[base + fillp[cell]++] = Tap{a, static_cast<float>(w)};
                 }
+        for (int i = 0; i < ncell; ++i) hd.max_cell_taps = std::max(hd.max_cell_taps, count[i + 1] - count[i]);
         cell_start.insert(cell_start.end(), count.begin(), count.end());
+        // cells sorted by tap count (ties by index) so that neighbouring lanes of a
+        // gathering wave walk lists of about the same length
+        std::vector<int32_t> order(ncell);
+        for (int i = 0; i < ncell; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return count[a + 1] - count[a] > count[b + 1] - count[b];
+        });
+        cell_order.insert(cell_order.end(), order.begin(), order.end());
+        cell_order.push_back(-1);
     }
     hd.n_taps_total = static_cast<int64_t>(taps.size());
 
@@ -221,8 +233,9 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     const size_t b_chan = up(sizeof(ChanPlan) * chans.size());
     const size_t b_cell = up(sizeof(int32_t) * cell_start.size());
     const size_t b_taps = up(sizeof(Tap) * taps.size());
+    const size_t b_order = up(sizeof(int32_t) * cell_order.size());
     void *dev = nullptr;
-    epic_status s = dev_alloc(&dev, b_chan + b_cell + b_taps);
+    epic_status s = dev_alloc(&dev, b_chan + b_cell + b_taps + b_order);
     if (s != EPIC_OK) return s;
     char *p = static_cast<char *>(dev);
     hipError_t e = hipMemcpy(p, chans.data(), sizeof(ChanPlan) * chans.size(), hipMemcpyHostToDevice);
@@ -232,6 +245,9 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     if (e == hipSuccess && !taps.empty())
         e = hipMemcpy(p + b_chan + b_cell, taps.data(), sizeof(Tap) * taps.size(),
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p + b_chan + b_cell + b_taps, cell_order.data(),
+                      sizeof(int32_t) * cell_order.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(dev);
         return hip_fail(e, "plan upload");
@@ -239,6 +255,7 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     hd.chan = reinterpret_cast<const ChanPlan *>(p);
     hd.cell_start = reinterpret_cast<const int32_t *>(p + b_chan);
     hd.taps = reinterpret_cast<const Tap *>(p + b_chan + b_cell);
+    hd.cell_order = reinterpret_cast<const int32_t *>(p + b_chan + b_cell + b_taps);
     g_plans.emplace(std::move(key), PlanEntry{dev, hd});
     *out = hd;
     return EPIC_OK;
