@@ -89,6 +89,8 @@ StationDev make_station_dev(const epic_station *s, const PlanHandle &p)
     d.ktaps = s->kernel.support * s->kernel.support;
     d.max_cells = p.max_box;
     d.max_cell_taps = p.max_cell_taps;
+    d.max_bw = p.max_bw;
+    d.max_bh = p.max_bh;
     return d;
 }
 
@@ -156,6 +158,32 @@ epic_status cadence_fused_fft(const epic_common *c, const epic_station *s, const
     const StationDev sd = make_station_dev(s, p);
     st = launch_fused_fft_partials(sd, n_pol, n_chan, c->n_time, c->volt_type, chunk,
                                    static_cast<float *>(ws), tw, stream);
+    if (st != EPIC_OK) return st;
+    const float inv = static_cast<float>(1.0 / static_cast<double>(c->n_time));
+    return launch_reduce_partials(n_pol, npix, n_chan, n_chunks, static_cast<const float *>(ws),
+                                  inv, static_cast<float2 *>(s->image), stream);
+}
+
+// Fused split-precision path for square grids up to 64x64 (matrix cores),
+// with the same chunk partials and ordered reduction as the FP32 path.
+epic_status cadence_fused_dft(const epic_common *c, const epic_station *s, const PlanHandle &p,
+                              int device, hipStream_t stream)
+{
+    const int n_pol = c->n_pol, n_chan = c->n_chan;
+    const int npix = s->nx * s->ny;
+    const int chunk = 32;
+    const int n_chunks = (c->n_time + chunk - 1) / chunk;
+    const int nreal = n_pol == 2 ? 4 : 1;
+    const size_t bytes = sizeof(float) * static_cast<size_t>(n_chan) * n_chunks * nreal * npix;
+    void *ws = nullptr;
+    epic_status st = get_workspace(device, stream, 2, bytes, &ws);
+    if (st != EPIC_OK) return st;
+    const uint32_t *rows = nullptr;
+    st = get_dft_rows(s->nx, c->precision, device, &rows);
+    if (st != EPIC_OK) return st;
+    const StationDev sd = make_station_dev(s, p);
+    st = launch_fused_dft_partials(sd, n_pol, n_chan, c->n_time, c->volt_type, c->precision, chunk,
+                                   static_cast<float *>(ws), rows, stream);
     if (st != EPIC_OK) return st;
     const float inv = static_cast<float>(1.0 / static_cast<double>(c->n_time));
     return launch_reduce_partials(n_pol, npix, n_chan, n_chunks, static_cast<const float *>(ws),
@@ -281,9 +309,13 @@ epic_status image_cadence(const epic_common *common, const epic_station *station
     }
     for (int i = 0; i < n_stations; ++i) {
         const epic_station *s = &stations[i];
-        const bool fused = common->precision == EPIC_FP32_FFT && s->nx == s->ny && s->nx <= 64;
-        st = fused ? cadence_fused_fft(common, s, plans[i], dev, stream)
-                   : cadence_composed(common, s, plans[i], dev, stream);
+        if (common->precision == EPIC_FP32_FFT && s->nx == s->ny && s->nx <= 64)
+            st = cadence_fused_fft(common, s, plans[i], dev, stream);
+        else if (common->precision != EPIC_FP32_FFT &&
+                 fused_dft_supported(make_station_dev(s, plans[i]), common->n_pol, common->volt_type))
+            st = cadence_fused_dft(common, s, plans[i], dev, stream);
+        else
+            st = cadence_composed(common, s, plans[i], dev, stream);
         if (st != EPIC_OK) return st;
     }
     return EPIC_OK;

@@ -29,6 +29,8 @@ struct ChanPlan {
     int32_t x0, y0, bw, bh;   // footprint box of this channel
     int64_t cell_off;         // first entry of this channel in cell_start[]
     int64_t tap_off;          // first entry of this channel in taps[]
+    float wsum_max;           // max over cells of the sum of |weight| of its taps
+    int32_t pad_;
 };
 
 // Device-side view of one station's plan and buffers (kernel argument).
@@ -45,6 +47,7 @@ struct StationDev {
     int32_t ktaps;            // taps per element (support^2): n_elem*ktaps taps per channel
     int32_t max_cells;        // max footprint-box cells over channels
     int32_t max_cell_taps;    // max taps landing on one cell over channels
+    int32_t max_bw, max_bh;   // largest footprint box sides over channels
 };
 
 // ---------------------------------------------------------------------------
@@ -102,6 +105,18 @@ epic_status get_twiddles(int n, int device, const float2 **out);
 
 // Split-precision DFT tables in MFMA fragment order (k_dft.hip).
 epic_status get_dft_tables(int n, int precision, int device, const void **out);
+
+// DFT matrix rows [n][n] as packed (re, im) hi parts, then lo parts (k_dft.hip).
+epic_status get_dft_rows(int n, int precision, int device, const uint32_t **out);
+
+// Fused split-precision cadence for square grids n in {16, 32, 64} (partial sums
+// per (channel, time chunk), like launch_fused_fft_partials).
+epic_status launch_fused_dft_partials(const StationDev &sd, int n_pol, int n_chan, int n_time,
+                                      int volt_type, int precision, int chunk, float *partials,
+                                      const uint32_t *dft_rows, hipStream_t stream);
+
+// Whether launch_fused_dft_partials covers this station.
+bool fused_dft_supported(const StationDev &sd, int n_pol, int volt_type);
 
 // Library-owned device workspace, per (device, stream, slot); grows on demand.
 epic_status get_workspace(int device, hipStream_t stream, int slot, size_t bytes, void **out);

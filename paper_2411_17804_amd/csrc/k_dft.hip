@@ -60,6 +60,44 @@ void fill_any(int n, int precision, void *dst)
 
 }  // namespace
 
+// Host: rows of the DFT matrix as (re, im) pairs, [k][j] = exp(+2 pi i k j / n),
+// hi parts then lo parts, each pair packed into 32 bits (re low, im high).
+template <typename T>
+void fill_rows(int n, void *dst)
+{
+    T *hi = static_cast<T *>(dst);
+    T *lo = hi + static_cast<size_t>(n) * n * 2;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (long k = 0; k < n; ++k)
+        for (long j = 0; j < n; ++j) {
+            const double ang = two_pi * static_cast<double>((k * j) % n) / n;
+            const double v[2] = {std::cos(ang), std::sin(ang)};
+            for (int part = 0; part < 2; ++part) {
+                const T h = static_cast<T>(v[part]);
+                const T l = static_cast<T>(v[part] - static_cast<double>(h));
+                hi[(k * n + j) * 2 + part] = h;
+                lo[(k * n + j) * 2 + part] = l;
+            }
+        }
+}
+
+void fill_rows_any(int n, int precision, void *dst)
+{
+    if ((precision & 0xf) == EPIC_FP16_SPLIT)
+        fill_rows<_Float16>(n, dst);
+    else
+        fill_rows<__bf16>(n, dst);
+}
+
+epic_status get_dft_rows(int n, int precision, int device, const uint32_t **out)
+{
+    const size_t bytes = static_cast<size_t>(n) * n * 4 * 2;
+    const void *p = nullptr;
+    epic_status s = cache_dft_table(n, precision | 0x10, device, bytes, fill_rows_any, &p);
+    *out = static_cast<const uint32_t *>(p);
+    return s;
+}
+
 epic_status get_dft_tables(int n, int precision, int device, const void **out)
 {
     const size_t bytes = static_cast<size_t>(2 * n / 16) * (n / 16) * 64 * 8 * 2 * 2;

@@ -1,0 +1,444 @@
+// k_fused_dft.hip -- the whole cadence for square grids up to 64 x 64 with the
+// 2-D transform of Eq. 3 evaluated as split-precision DFT-matrix products on
+// gfx950 matrix cores (EPIC_FP16_SPLIT / EPIC_BF16_SPLIT), fused with the
+// gridding (Eq. 3 inner bracket) and the products and time average (Eq. 2).
+//
+// One work-group owns one (channel, time chunk) and has N/16 waves; wave w
+// owns output rows k_y in [16w, 16w + 16).  Per sample:
+//   1. grid the kernel-footprint box (both pols), scale by a power of two s1
+//      bounded from the sample's largest voltage component and the channel's
+//      largest per-cell weight sum, split into hi/lo and store G^T in LDS;
+//   2. stage 1 (transform along y, pruned to the footprint rows):
+//        Y^T[x][k_y] = sum_y G^T[x][y] F[k_y][y0 + y]
+//      with G^T as the A operand and the wave's 16 DFT rows as constant B
+//      fragments held in registers for the whole chunk; steps 2-4 run for one
+//      pol after the other, pol X's stage-2 tiles waiting in registers;
+//   3. each wave scales its Y rows by a power of two s2 and re-splits them;
+//      the stage-1 result tiles are already laid out as stage-2 A fragments
+//      (the K index of stage 2 is ordered to match), so nothing goes back
+//      through LDS;
+//   4. stage 2 (transform along x, pruned to the footprint columns):
+//        Z[k_y][k_x] = sum_x Y[k_y][x] F[k_x][x0 + x]
+//      with B fragments built from the channel's DFT rows in LDS (a sign flip
+//      and a half swap turn a packed (re, im) pair into the 2x2 real block);
+//   5. undo s1 s2 exactly, form XX, XY, YY and accumulate in registers.
+// Partial sums per chunk go to the same ordered compensated reduction as the
+// FP32 path.
+#include <algorithm>
+
+#include "internal.hpp"
+#include "mfma_split.hpp"
+
+namespace epic {
+
+namespace {
+
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+template <int PREC>
+__device__ __forceinline__ uint32_t pack2(typename Split<PREC>::scalar a, typename Split<PREC>::scalar b)
+{
+    return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, a)) |
+           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, b)) << 16);
+}
+
+// (re, im) packed -> (re, -im): 2x2 block column for the real output part
+__device__ __forceinline__ uint32_t neg_hi(uint32_t w) { return w ^ 0x80000000u; }
+// (re, im) packed -> (im, re): 2x2 block column for the imaginary output part
+__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
+
+}  // namespace
+
+template <int N, int T>
+struct FusedDftShape {
+    static constexpr int WAVES = N / 16;
+    static constexpr int BLOCK = 64 * WAVES;
+    static constexpr int PITCH = 16 * T + 4;      // LDS pitch of G^T rows and F_x rows (words)
+    static constexpr int ROUNDS = (16 * T * 16 * T + BLOCK - 1) / BLOCK;   // gather rounds
+};
+
+// Voltage words per (element, pol) in LDS: int8 voltages are held as an exact
+// FP16 pair (one word), float voltages as a float pair (two words).
+constexpr int volt_words(int vt) { return vt == EPIC_CI8 ? 1 : 2; }
+
+inline size_t fused_dft_lds_bytes(int N, int T, int np, int vt, int n_elem, int max_cells)
+{
+    const int pitch = 16 * T + 4;
+    return sizeof(uint32_t) * (2 * static_cast<size_t>(np) * 16 * T * pitch   // G^T hi, lo
+                               + 2 * static_cast<size_t>(N) * pitch           // F_x rows hi, lo
+                               + 2 * static_cast<size_t>(np) * n_elem * volt_words(vt)  // voltages x 2
+                               + static_cast<size_t>(max_cells));             // gather jobs
+}
+
+template <int N, int T, int NP, int VT, int PREC>
+__global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_dft(
+    StationDev sd, int n_time, int chunk, float *__restrict__ partials,
+    const uint32_t *__restrict__ rows, int vwords)
+{
+    using Sh = FusedDftShape<N, T>;
+    using S = Split<PREC>;
+    using vec8 = typename S::vec8;
+    using scalar = typename S::scalar;
+    constexpr int WAVES = Sh::WAVES, BLOCK = Sh::BLOCK, PITCH = Sh::PITCH, ROUNDS = Sh::ROUNDS;
+    constexpr int NQ = NP == 2 ? 4 : 1;
+    constexpr int NT = N / 16;                      // k_x tiles
+    constexpr int GPLANE = 16 * T * PITCH;          // words per pol of G^T
+    extern __shared__ uint32_t lds[];
+    uint32_t *gbh = lds;                            // [NP][16T][PITCH] G^T hi (re, im)
+    uint32_t *gbl = gbh + NP * GPLANE;              // lo
+    uint32_t *txh = gbl + NP * GPLANE;              // [N][PITCH] F[k_x][x0 + x] hi (re, im)
+    uint32_t *txl = txh + N * PITCH;                // lo
+    constexpr int VW = volt_words(VT);
+    uint32_t *vf = txl + N * PITCH;                 // [2][n_elem][NP][VW] voltages
+    uint32_t *jobs = vf + 2 * NP * VW * sd.n_elem;  // [ncell] gather jobs
+    __shared__ float vred[2][WAVES];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int ck = blockIdx.x, c = blockIdx.y;
+    const int n_chunks = gridDim.x;
+    const int t_begin = ck * chunk;
+    const int t_end = min(n_time, t_begin + chunk);
+    const ChanPlan cp = sd.chan[c];
+    const int ncell = cp.bw * cp.bh;
+    const int mx = (cp.bw + 15) >> 4, my = (cp.bh + 15) >> 4;   // footprint tiles (<= T)
+    const uint32_t *rows_lo = rows + N * N;
+
+    // ---- once per work-group -------------------------------------------
+    for (int i = tid; i < 2 * NP * GPLANE; i += BLOCK) gbh[i] = 0u;     // padding stays 0
+    for (int i = tid; i < N * 16 * T; i += BLOCK) {
+        const int k = i / (16 * T), x = i - k * (16 * T);
+        const int jj = (cp.x0 + x) & (N - 1);
+        txh[k * PITCH + x] = rows[k * N + jj];
+        txl[k * PITCH + x] = rows_lo[k * N + jj];
+    }
+    // gather jobs (cells in descending tap-count order): cell << 20 | count << 16 | first tap
+    {
+        const int32_t *cs = sd.cell_start + cp.cell_off;
+        const int32_t *ord = sd.cell_order + cp.cell_off;
+        for (int i = tid; i < ncell; i += BLOCK) {
+            const int cell = ord[i];
+            const int k0 = cs[cell];
+            jobs[i] = (static_cast<uint32_t>(cell) << 20) |
+                      (static_cast<uint32_t>(cs[cell + 1] - k0) << 16) | static_cast<uint32_t>(k0);
+        }
+    }
+    const Tap *taps = sd.taps + cp.tap_off;
+    // stage-1 B fragments: DFT rows k_y = 16 wave + r16 at y0 + 16 ks + 4 g + i,
+    // held in registers for the whole chunk
+    vec8 b1[T][4];   // [K-step][re hi, re lo, im hi, im lo]
+    {
+        const int ky_row = (16 * wave + r16) * N;
+#pragma unroll
+        for (int ks = 0; ks < T; ++ks) {
+            u32x4_t wr_h, wr_l, wi_h, wi_l;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int jj = (cp.y0 + 16 * ks + 4 * g + i) & (N - 1);
+                const uint32_t h = rows[ky_row + jj], l = rows_lo[ky_row + jj];
+                wr_h[i] = neg_hi(h);
+                wr_l[i] = neg_hi(l);
+                wi_h[i] = swap_halves(h);
+                wi_l[i] = swap_halves(l);
+            }
+            b1[ks][0] = __builtin_bit_cast(vec8, wr_h);
+            b1[ks][1] = __builtin_bit_cast(vec8, wr_l);
+            b1[ks][2] = __builtin_bit_cast(vec8, wi_h);
+            b1[ks][3] = __builtin_bit_cast(vec8, wi_l);
+        }
+    }
+
+    // voltages of a sample as float pairs in vf[buffer]; returns the largest
+    // |component| this thread stored
+    const uint32_t *vsrc = reinterpret_cast<const uint32_t *>(sd.volts) +
+                           static_cast<size_t>(c) * n_time * vwords;
+    auto stash = [&](int buffer, int i, uint32_t w) -> float {
+        uint32_t *dst = vf + buffer * NP * VW * sd.n_elem;
+        if constexpr (VT == EPIC_CI8) {
+            // four int8 components -> two exact FP16 pairs
+            const int8_t a = static_cast<int8_t>(w & 0xff), b = static_cast<int8_t>((w >> 8) & 0xff);
+            const int8_t cc = static_cast<int8_t>((w >> 16) & 0xff), d = static_cast<int8_t>((w >> 24) & 0xff);
+            dst[2 * i] = pack2<EPIC_FP16_SPLIT>(static_cast<_Float16>(a), static_cast<_Float16>(b));
+            dst[2 * i + 1] = pack2<EPIC_FP16_SPLIT>(static_cast<_Float16>(cc), static_cast<_Float16>(d));
+            const int m = max(max(abs(static_cast<int>(a)), abs(static_cast<int>(b))),
+                              max(abs(static_cast<int>(cc)), abs(static_cast<int>(d))));
+            return static_cast<float>(m);
+        } else {
+            dst[i] = w;
+            return fabsf(__builtin_bit_cast(float, w));
+        }
+    };
+    auto volt = [&](const uint32_t *vcur, int idx) -> float2 {
+        if constexpr (VT == EPIC_CI8) {
+            const uint32_t w = vcur[idx];
+            return make_float2(static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w & 0xffff))),
+                               static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w >> 16))));
+        } else {
+            return reinterpret_cast<const float2 *>(vcur)[idx];
+        }
+    };
+    auto reduce_max = [&](float m, int buffer) {
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if (lane == 0) vred[buffer][wave] = m;
+    };
+    {
+        float m = 0.f;
+        for (int i = tid; i < vwords; i += BLOCK)
+            m = fmaxf(m, stash(0, i, vsrc[static_cast<size_t>(t_begin) * vwords + i]));
+        reduce_max(m, 0);
+    }
+
+    float acc[NT][4][NQ];
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[a][i][q] = 0.f;
+    __syncthreads();
+
+    int cur = 0;
+    for (int t = t_begin; t < t_end; ++t) {
+        const bool has_next = t + 1 < t_end;
+        // ---- 1. grid the footprint box, scale, split -> G^T in LDS -------
+        float vmax = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) vmax = fmaxf(vmax, vred[cur][w]);
+        const float s1 = pow2_scale(vmax * cp.wsum_max);
+        {
+            const uint32_t *vcur = vf + cur * NP * VW * sd.n_elem;
+            for (int i = tid; i < ncell; i += BLOCK) {
+                {
+                    const uint32_t job = jobs[i];
+                    const int cell = job >> 20, kn = (job >> 16) & 15, k0 = job & 0xffff;
+                    float2 a[NP];
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) a[p] = make_float2(0.f, 0.f);
+                    for (int s = 0; s < kn; ++s) {
+                        const Tap tp = taps[k0 + s];
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) {
+                            const float2 e = volt(vcur, tp.elem * NP + p);
+                            a[p].x = fmaf(tp.w, e.x, a[p].x);
+                            a[p].y = fmaf(tp.w, e.y, a[p].y);
+                        }
+                    }
+                    const int by = cell / cp.bw, bx = cell - by * cp.bw;
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        scalar hr, lr, hi_, li;
+                        split<PREC>(a[p].x * s1, hr, lr);
+                        split<PREC>(a[p].y * s1, hi_, li);
+                        gbh[p * GPLANE + bx * PITCH + by] = pack2<PREC>(hr, hi_);
+                        gbl[p * GPLANE + bx * PITCH + by] = pack2<PREC>(lr, li);
+                    }
+                }
+            }
+        }
+        if (has_next) {
+            float m = 0.f;
+            for (int i = tid; i < vwords; i += BLOCK)
+                m = fmaxf(m, stash(cur ^ 1, i, vsrc[static_cast<size_t>(t + 1) * vwords + i]));
+            reduce_max(m, cur ^ 1);
+        }
+        __syncthreads();
+
+        // ---- 2.-5. per pol: stage 1, rescale, stage 2; products once both
+        // pols of a tile are known (pol X's stage-2 tiles wait in zx) ------
+        floatx4_t zx[NT][2];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            // 2. stage 1: Y^T[x][k_y] for this wave's 16 k_y
+            floatx4_t c1[T][2];   // [x tile][re, im]
+#pragma unroll
+            for (int mt = 0; mt < T; ++mt)
+#pragma unroll
+                for (int o = 0; o < 2; ++o) c1[mt][o] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < T; ++ks) {
+                if (ks >= my) break;
+#pragma unroll
+                for (int mt = 0; mt < T; ++mt) {
+                    if (mt >= mx) break;
+                    const int off = p * GPLANE + (16 * mt + r16) * PITCH + 16 * ks + 4 * g;
+                    const vec8 ah = __builtin_bit_cast(vec8, *reinterpret_cast<const u32x4_t *>(&gbh[off]));
+                    const vec8 al = __builtin_bit_cast(vec8, *reinterpret_cast<const u32x4_t *>(&gbl[off]));
+                    c1[mt][0] = mma3<PREC>(ah, al, b1[ks][0], b1[ks][1], c1[mt][0]);
+                    c1[mt][1] = mma3<PREC>(ah, al, b1[ks][2], b1[ks][3], c1[mt][1]);
+                }
+            }
+            if (p == NP - 1) __syncthreads();   // G^T is free for the next sample
+
+            // 3. per-wave power-of-two scale and re-split into stage-2 A fragments
+            float ymax = 0.f;
+#pragma unroll
+            for (int mt = 0; mt < T; ++mt)
+#pragma unroll
+                for (int o = 0; o < 2; ++o)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) ymax = fmaxf(ymax, fabsf(c1[mt][o][i]));
+            for (int o = 32; o > 0; o >>= 1) ymax = fmaxf(ymax, __shfl_xor(ymax, o));
+            const float s2 = pow2_scale(ymax);
+            vec8 a2[T][2];   // [x K-step][hi, lo]
+#pragma unroll
+            for (int mt = 0; mt < T; ++mt) {
+                u32x4_t wh, wl;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    scalar hr, lr, hi_, li;
+                    split<PREC>(c1[mt][0][i] * s2, hr, lr);
+                    split<PREC>(c1[mt][1][i] * s2, hi_, li);
+                    wh[i] = pack2<PREC>(hr, hi_);
+                    wl[i] = pack2<PREC>(lr, li);
+                }
+                a2[mt][0] = __builtin_bit_cast(vec8, wh);
+                a2[mt][1] = __builtin_bit_cast(vec8, wl);
+            }
+
+            // 4. stage 2 per k_x tile; 5. products
+            const float inv = 1.f / (s1 * s2);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                floatx4_t z0 = floatx4_t{0.f, 0.f, 0.f, 0.f}, z1 = z0;
+#pragma unroll
+                for (int ks = 0; ks < T; ++ks) {
+                    if (ks >= mx) break;
+                    const int off = (16 * nt + r16) * PITCH + 16 * ks + 4 * g;
+                    const u32x4_t wh = *reinterpret_cast<const u32x4_t *>(&txh[off]);
+                    const u32x4_t wl = *reinterpret_cast<const u32x4_t *>(&txl[off]);
+                    u32x4_t rh, rl, ih, il;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        rh[i] = neg_hi(wh[i]);
+                        rl[i] = neg_hi(wl[i]);
+                        ih[i] = swap_halves(wh[i]);
+                        il[i] = swap_halves(wl[i]);
+                    }
+                    z0 = mma3<PREC>(a2[ks][0], a2[ks][1], __builtin_bit_cast(vec8, rh),
+                                    __builtin_bit_cast(vec8, rl), z0);
+                    z1 = mma3<PREC>(a2[ks][0], a2[ks][1], __builtin_bit_cast(vec8, ih),
+                                    __builtin_bit_cast(vec8, il), z1);
+                }
+                // lane holds pixels (k_y = 16 wave + 4 g + i, k_x = 16 nt + r16)
+                if (p == 0) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        z0[i] *= inv;
+                        z1[i] *= inv;
+                    }
+                    if constexpr (NP == 1) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            acc[nt][i][0] = fmaf(z0[i], z0[i], fmaf(z1[i], z1[i], acc[nt][i][0]));
+                    } else {
+                        zx[nt][0] = z0;
+                        zx[nt][1] = z1;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float xr = zx[nt][0][i], xi = zx[nt][1][i];
+                        const float yr = z0[i] * inv, yi = z1[i] * inv;
+                        acc[nt][i][0] = fmaf(xr, xr, fmaf(xi, xi, acc[nt][i][0]));
+                        acc[nt][i][1] = fmaf(xr, yr, fmaf(xi, yi, acc[nt][i][1]));
+                        acc[nt][i][2] = fmaf(xi, yr, fmaf(-xr, yi, acc[nt][i][2]));
+                        acc[nt][i][3] = fmaf(yr, yr, fmaf(yi, yi, acc[nt][i][3]));
+                    }
+                }
+            }
+        }
+        cur ^= 1;
+    }
+    float *out = partials + (static_cast<size_t>(c) * n_chunks + ck) * NQ * N * N;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pix = (16 * wave + 4 * g + i) * N + 16 * nt + r16;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) out[q * N * N + pix] = acc[nt][i][q];
+        }
+}
+
+namespace {
+
+template <int N, int T, int NP, int VT, int PREC>
+epic_status run(const StationDev &sd, int n_chan, int n_time, int chunk, float *partials,
+                const uint32_t *rows, int vwords, hipStream_t stream)
+{
+    using Sh = FusedDftShape<N, T>;
+    const size_t bytes = fused_dft_lds_bytes(N, T, NP, VT, sd.n_elem, sd.max_cells);
+    auto k = k_fused_dft<N, T, NP, VT, PREC>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(bytes));
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    const int n_chunks = (n_time + chunk - 1) / chunk;
+    KernelTimer timer("fused_dft_cadence", stream);
+    hipLaunchKernelGGL(k, dim3(n_chunks, n_chan), dim3(Sh::BLOCK), bytes, stream, sd, n_time,
+                       chunk, partials, rows, vwords);
+    EPIC_HIP_TRY(hipGetLastError());
+    return EPIC_OK;
+}
+
+template <int N, int T, int PREC>
+epic_status by_type(const StationDev &sd, int n_pol, int volt_type, int n_chan, int n_time,
+                    int chunk, float *partials, const uint32_t *rows, int vwords,
+                    hipStream_t stream)
+{
+    if (n_pol == 2 && volt_type == EPIC_CI8)
+        return run<N, T, 2, EPIC_CI8, PREC>(sd, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    if (n_pol == 2)
+        return run<N, T, 2, EPIC_CF32, PREC>(sd, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    if (volt_type == EPIC_CI8)
+        return run<N, T, 1, EPIC_CI8, PREC>(sd, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    return run<N, T, 1, EPIC_CF32, PREC>(sd, n_chan, n_time, chunk, partials, rows, vwords, stream);
+}
+
+template <int PREC>
+epic_status by_size(const StationDev &sd, int t, int n_pol, int volt_type, int n_chan, int n_time,
+                    int chunk, float *partials, const uint32_t *rows, int vwords,
+                    hipStream_t stream)
+{
+    switch (sd.nx * 8 + t) {
+    case 16 * 8 + 1: return by_type<16, 1, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    case 32 * 8 + 1: return by_type<32, 1, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    case 32 * 8 + 2: return by_type<32, 2, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    case 64 * 8 + 2: return by_type<64, 2, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    case 64 * 8 + 3: return by_type<64, 3, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    case 64 * 8 + 4: return by_type<64, 4, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    }
+    return fail(EPIC_ERR_INTERNAL, "fused split path: unsupported grid/footprint");
+}
+
+}  // namespace
+
+epic_status launch_fused_dft_partials(const StationDev &sd, int n_pol, int n_chan, int n_time,
+                                      int volt_type, int precision, int chunk, float *partials,
+                                      const uint32_t *rows, hipStream_t stream)
+{
+    const int n = sd.nx;
+    // footprint tiles: the largest box side over channels, at least the
+    // smallest template size for this grid
+    int t = (std::max(sd.max_bw, sd.max_bh) + 15) / 16;
+    const int tmin = n == 64 ? 2 : 1;
+    t = std::max(t, tmin);
+    const int vwords = static_cast<int>(static_cast<int64_t>(sd.n_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8) / 4);
+    if (precision == EPIC_FP16_SPLIT)
+        return by_size<EPIC_FP16_SPLIT>(sd, t, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    return by_size<EPIC_BF16_SPLIT>(sd, t, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+}
+
+// Whether the fused split kernel covers this station (host-side check).
+bool fused_dft_supported(const StationDev &sd, int n_pol, int volt_type)
+{
+    if (sd.nx != sd.ny || (sd.nx != 16 && sd.nx != 32 && sd.nx != 64)) return false;
+    const int64_t vbytes = static_cast<int64_t>(sd.n_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8);
+    if (vbytes % 4 != 0) return false;
+    if (sd.max_cell_taps > 15 || static_cast<int64_t>(sd.n_elem) * sd.ktaps > 0xffff) return false;
+    const int t = std::max((std::max(sd.max_bw, sd.max_bh) + 15) / 16, sd.nx == 64 ? 2 : 1);
+    if (t > sd.nx / 16) return false;
+    return fused_dft_lds_bytes(sd.nx, t, n_pol, volt_type, sd.n_elem, sd.max_cells) <= 160 * 1024;
+}
+
+}  // namespace epic

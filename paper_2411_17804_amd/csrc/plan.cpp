@@ -215,6 +215,18 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
                     taps[base + fillp[cell]++] = Tap{a, static_cast<float>(w)};
                 }
         for (int i = 0; i < ncell; ++i) hd.max_cell_taps = std::max(hd.max_cell_taps, count[i + 1] - count[i]);
+        {
+            std::vector<double> wsum(ncell, 0.0);
+            for (int a = 0; a < n_elem; ++a)
+                for (int dy = -h; dy <= h; ++dy)
+                    for (int dx = -h; dx <= h; ++dx)
+                        wsum[static_cast<size_t>(cj[a] + dy - y_lo) * cp.bw + (ci[a] + dx - x_lo)] +=
+                            std::fabs(wx[static_cast<size_t>(a) * K + dx + h] * wy[static_cast<size_t>(a) * K + dy + h]);
+            double m = 0.0;
+            for (double v : wsum) m = std::max(m, v);
+            cp.wsum_max = static_cast<float>(m * (1.0 + 1e-6));   // rounded up
+            cp.pad_ = 0;
+        }
         cell_start.insert(cell_start.end(), count.begin(), count.end());
         // cells sorted by tap count (ties by index) so that neighbouring lanes of a
         // gathering wave walk lists of about the same length
