@@ -161,6 +161,23 @@ epic_status image_cadence(const epic_common *common, const epic_station *station
                           int32_t n_stations, hipStream_t stream);
 
 /*
+ * Tile tuning (auxiliary).  image_cadence runs every station whose grid is
+ * square and at most 64 x 64 in fused kernels that process one (station,
+ * channel, time chunk) item per work-group; the chunk length (16, 32 or 64
+ * samples) trades launch width against per-item setup and partial-sum
+ * traffic.  epic_autotune runs each fused kernel class of this call with each
+ * candidate on the caller's buffers (it overwrites station images), keeps the
+ * fastest for later image_cadence calls of the same class (grid size,
+ * footprint tiles, pols, voltage type, precision) and, if the environment
+ * variable EPIC_TUNE_CACHE names a file, stores the choices there and reads
+ * them back in later processes.  Synchronises the stream.  The chunk length
+ * changes only the summation grouping of the time average, never the set of
+ * samples summed.
+ */
+epic_status epic_autotune(const epic_common *common, const epic_station *stations,
+                          int32_t n_stations, hipStream_t stream);
+
+/*
  * Host-only check of everything image_cadence would check (arguments and
  * geometry: every element's kernel footprint inside its grid at every
  * channel), without touching a device.  Returns EPIC_OK or the error

@@ -13,6 +13,12 @@ const char *last_error_cstr();
 
 using namespace epic;
 
+namespace epic {
+StationDev make_station_dev(const epic_station *s, const PlanHandle &p);
+epic_status cadence_composed(const epic_common *c, const epic_station *s, const PlanHandle &p,
+                             int device, hipStream_t stream);
+}
+
 namespace {
 
 bool is_pow2_grid(int n) { return n >= 16 && n <= 256 && (n & (n - 1)) == 0; }
@@ -73,7 +79,9 @@ epic_status current_device(int *dev)
     return EPIC_OK;
 }
 
-StationDev make_station_dev(const epic_station *s, const PlanHandle &p)
+}  // namespace
+
+StationDev epic::make_station_dev(const epic_station *s, const PlanHandle &p)
 {
     StationDev d{};
     d.chan = p.chan;
@@ -94,13 +102,11 @@ StationDev make_station_dev(const epic_station *s, const PlanHandle &p)
     return d;
 }
 
-size_t volt_bytes(int type) { return type == EPIC_CI8 ? 2 : 8; }
-
 // The composed cadence path: grid -> transform -> square/accumulate through a
 // library-owned workspace, in time chunks.  Used for the grids and precisions
 // that the fused kernel does not cover.
-epic_status cadence_composed(const epic_common *c, const epic_station *s, const PlanHandle &p,
-                             int device, hipStream_t stream)
+epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
+                                   const PlanHandle &p, int device, hipStream_t stream)
 {
     const int n_pol = c->n_pol, n_chan = c->n_chan;
     const int64_t npix = static_cast<int64_t>(s->nx) * s->ny;
@@ -137,61 +143,6 @@ epic_status cadence_composed(const epic_common *c, const epic_station *s, const 
     return EPIC_OK;
 }
 
-// Fused FP32 path for square grids up to 64x64: one kernel grids, transforms,
-// squares and accumulates a time chunk per (channel, chunk) work-group; a
-// second kernel reduces the chunks in order with compensation.
-epic_status cadence_fused_fft(const epic_common *c, const epic_station *s, const PlanHandle &p,
-                              int device, hipStream_t stream)
-{
-    const int n_pol = c->n_pol, n_chan = c->n_chan;
-    const int npix = s->nx * s->ny;
-    const int chunk = 32;
-    const int n_chunks = (c->n_time + chunk - 1) / chunk;
-    const int nreal = n_pol == 2 ? 4 : 1;
-    const size_t bytes = sizeof(float) * static_cast<size_t>(n_chan) * n_chunks * nreal * npix;
-    void *ws = nullptr;
-    epic_status st = get_workspace(device, stream, 2, bytes, &ws);
-    if (st != EPIC_OK) return st;
-    const float2 *tw = nullptr;
-    st = get_twiddles(s->nx, device, &tw);
-    if (st != EPIC_OK) return st;
-    const StationDev sd = make_station_dev(s, p);
-    st = launch_fused_fft_partials(sd, n_pol, n_chan, c->n_time, c->volt_type, chunk,
-                                   static_cast<float *>(ws), tw, stream);
-    if (st != EPIC_OK) return st;
-    const float inv = static_cast<float>(1.0 / static_cast<double>(c->n_time));
-    return launch_reduce_partials(n_pol, npix, n_chan, n_chunks, static_cast<const float *>(ws),
-                                  inv, static_cast<float2 *>(s->image), stream);
-}
-
-// Fused split-precision path for square grids up to 64x64 (matrix cores),
-// with the same chunk partials and ordered reduction as the FP32 path.
-epic_status cadence_fused_dft(const epic_common *c, const epic_station *s, const PlanHandle &p,
-                              int device, hipStream_t stream)
-{
-    const int n_pol = c->n_pol, n_chan = c->n_chan;
-    const int npix = s->nx * s->ny;
-    const int chunk = 32;
-    const int n_chunks = (c->n_time + chunk - 1) / chunk;
-    const int nreal = n_pol == 2 ? 4 : 1;
-    const size_t bytes = sizeof(float) * static_cast<size_t>(n_chan) * n_chunks * nreal * npix;
-    void *ws = nullptr;
-    epic_status st = get_workspace(device, stream, 2, bytes, &ws);
-    if (st != EPIC_OK) return st;
-    const uint32_t *rows = nullptr;
-    st = get_dft_rows(s->nx, c->precision, device, &rows);
-    if (st != EPIC_OK) return st;
-    const StationDev sd = make_station_dev(s, p);
-    st = launch_fused_dft_partials(sd, n_pol, n_chan, c->n_time, c->volt_type, c->precision, chunk,
-                                   static_cast<float *>(ws), rows, stream);
-    if (st != EPIC_OK) return st;
-    const float inv = static_cast<float>(1.0 / static_cast<double>(c->n_time));
-    return launch_reduce_partials(n_pol, npix, n_chan, n_chunks, static_cast<const float *>(ws),
-                                  inv, static_cast<float2 *>(s->image), stream);
-}
-
-}  // namespace
-
 extern "C" {
 
 const char *epic_status_string(epic_status status)
@@ -209,7 +160,11 @@ const char *epic_status_string(epic_status status)
 
 const char *epic_last_error(void) { return last_error_cstr(); }
 
-void epic_cache_clear(void) { clear_all_caches(); }
+void epic_cache_clear(void)
+{
+    clear_cadence_cache();
+    clear_all_caches();
+}
 
 epic_status epic_validate(const epic_common *common, const epic_station *stations,
                           int32_t n_stations)
@@ -307,18 +262,30 @@ epic_status image_cadence(const epic_common *common, const epic_station *station
         st = get_plan(common, &stations[i], dev, &plans[i]);
         if (st != EPIC_OK) return fail(st, "station " + std::to_string(i) + ": " + last_error_cstr());
     }
+    return run_cadence(common, stations, n_stations, plans.data(), dev, stream);
+}
+
+epic_status epic_autotune(const epic_common *common, const epic_station *stations,
+                          int32_t n_stations, hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!stations || n_stations < 1) return fail(EPIC_ERR_INVALID_ARG, "need >= 1 station");
     for (int i = 0; i < n_stations; ++i) {
-        const epic_station *s = &stations[i];
-        if (common->precision == EPIC_FP32_FFT && s->nx == s->ny && s->nx <= 64)
-            st = cadence_fused_fft(common, s, plans[i], dev, stream);
-        else if (common->precision != EPIC_FP32_FFT &&
-                 fused_dft_supported(make_station_dev(s, plans[i]), common->n_pol, common->volt_type))
-            st = cadence_fused_dft(common, s, plans[i], dev, stream);
-        else
-            st = cadence_composed(common, s, plans[i], dev, stream);
+        st = check_station(&stations[i], i);
         if (st != EPIC_OK) return st;
+        if (!stations[i].image) return fail(EPIC_ERR_INVALID_ARG, "station image is NULL");
     }
-    return EPIC_OK;
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    std::vector<PlanHandle> plans(n_stations);
+    for (int i = 0; i < n_stations; ++i) {
+        st = get_plan(common, &stations[i], dev, &plans[i]);
+        if (st != EPIC_OK) return fail(st, "station " + std::to_string(i) + ": " + last_error_cstr());
+    }
+    return tune_cadence(common, stations, n_stations, plans.data(), dev, stream);
 }
 
 }  // extern "C"

@@ -48,6 +48,21 @@ struct StationDev {
     int32_t max_cells;        // max footprint-box cells over channels
     int32_t max_cell_taps;    // max taps landing on one cell over channels
     int32_t max_bw, max_bh;   // largest footprint box sides over channels
+    int64_t part_off;         // first float of this station's chunk partial sums
+};
+
+// A batch of fused work: items (station index, channel, time chunk, 0) over a
+// device table of stations, plus the class-wide maxima the LDS layout uses.
+struct FusedBatch {
+    const StationDev *sds = nullptr;   // device [n_stations]
+    const int4 *items = nullptr;       // device [n_items]
+    int n_items = 0;
+    int max_elem = 0;                  // max n_elem over the batch's stations
+    int max_cells = 0;                 // max footprint-box cells
+    int max_cell_taps = 0;
+    int max_ktaps = 0;                 // max kernel taps per element (support^2)
+    int max_side = 0;                  // max footprint-box side
+    int n = 0;                         // grid size (square) shared by the batch
 };
 
 // ---------------------------------------------------------------------------
@@ -111,17 +126,27 @@ epic_status get_dft_rows(int n, int precision, int device, const uint32_t **out)
 
 // Fused split-precision cadence for square grids n in {16, 32, 64} (partial sums
 // per (channel, time chunk), like launch_fused_fft_partials).
-epic_status launch_fused_dft_partials(const StationDev &sd, int n_pol, int n_chan, int n_time,
-                                      int volt_type, int precision, int chunk, float *partials,
+epic_status launch_fused_dft_partials(const FusedBatch &b, int n_pol, int n_time, int volt_type,
+                                      int precision, int chunk, float *partials,
                                       const uint32_t *dft_rows, hipStream_t stream);
 
-// Whether launch_fused_dft_partials covers this station.
-bool fused_dft_supported(const StationDev &sd, int n_pol, int volt_type);
+// Whether launch_fused_dft_partials covers a batch with these maxima.
+bool fused_dft_supported(const FusedBatch &b, int n_pol, int volt_type);
 
 // Library-owned device workspace, per (device, stream, slot); grows on demand.
 epic_status get_workspace(int device, hipStream_t stream, int slot, size_t bytes, void **out);
 
 void clear_all_caches();
+
+// The cadence driver (cadence.cpp): groups stations into fused kernel classes,
+// launches one kernel per class plus the ordered reductions, replays the whole
+// cadence as a hipGraph when it can, and tunes the time-chunk length.
+epic_status run_cadence(const epic_common *c, const epic_station *st, int n, const PlanHandle *plans,
+                        int device, hipStream_t stream);
+epic_status tune_cadence(const epic_common *c, const epic_station *st, int n,
+                         const PlanHandle *plans, int device, hipStream_t stream);
+void clear_cadence_cache();
+bool timing_on();
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (each .hip file).  All validate nothing: the ABI layer has
@@ -141,10 +166,12 @@ epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, cons
                               float2 *out, int device, hipStream_t stream);
 
 // Fused FP32 cadence for square grids n in {16, 32, 64}: partial sums of the
-// four real product components per (station-channel, time chunk).
-epic_status launch_fused_fft_partials(const StationDev &sd, int n_pol, int n_chan, int n_time,
-                                      int volt_type, int chunk, float *partials,
-                                      const float2 *twiddles, hipStream_t stream);
+// four real product components per (station, channel, time chunk) item.
+epic_status launch_fused_fft_partials(const FusedBatch &b, int n_pol, int n_time, int volt_type,
+                                      int chunk, float *partials, const float2 *twiddles,
+                                      hipStream_t stream);
+// Whether the fused FP32 kernels cover a batch with these maxima.
+bool fused_fft_supported(const FusedBatch &b, int n_pol, int volt_type);
 
 // Ordered, compensated reduction of the partial sums of every chunk, then the
 // mean, written as the n_pol^2 complex products.

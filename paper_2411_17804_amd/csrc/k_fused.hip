@@ -21,8 +21,9 @@ template <> struct FusedShape<32> { static constexpr int BLOCK = 256; };
 template <> struct FusedShape<64> { static constexpr int BLOCK = 512; };
 
 template <int N, int NP, int VT>
-__global__ __launch_bounds__(FusedShape<N>::BLOCK) void k_fused_fft(StationDev sd, int n_time,
-                                                                    int chunk,
+__global__ __launch_bounds__(FusedShape<N>::BLOCK) void k_fused_fft(const StationDev *__restrict__ sds,
+                                                                    const int4 *__restrict__ items,
+                                                                    int n_time, int chunk,
                                                                     float *__restrict__ partials,
                                                                     const float2 *__restrict__ twg)
 {
@@ -36,8 +37,10 @@ __global__ __launch_bounds__(FusedShape<N>::BLOCK) void k_fused_fft(StationDev s
     float2 *buf = lds;                       // [NP][N][P]
     float2 *tw = lds + NP * PLANE;           // [N]
 
-    const int ck = blockIdx.x, c = blockIdx.y;
-    const int n_chunks = gridDim.x;
+    const int4 item = items[blockIdx.x];
+    const StationDev sd = sds[item.x];
+    const int c = item.y, ck = item.z;
+    const int n_chunks = (n_time + chunk - 1) / chunk;
     const int t_begin = ck * chunk;
     const int t_end = min(n_time, t_begin + chunk);
     const ChanPlan cp = sd.chan[c];
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(FusedShape<N>::BLOCK) void k_fused_fft(StationDev s
         }
         __syncthreads();
     }
-    float *out = partials + (static_cast<size_t>(c) * n_chunks + ck) * NQ * NPIX;
+    float *out = partials + sd.part_off + (static_cast<size_t>(c) * n_chunks + ck) * NQ * NPIX;
 #pragma unroll
     for (int i = 0; i < PXT; ++i) {
         const int k = threadIdx.x + i * BLOCK;
@@ -143,18 +146,20 @@ constexpr size_t kLdsBytes = 160 * 1024;
 
 // LDS of the 64 x 64 kernel: transform planes, the gathered footprint box,
 // two voltage buffers (as float), the channel's gather taps.
-inline size_t fused64_lds_bytes(int np, const StationDev &sd, int max_cells)
+inline size_t fused64_lds_bytes(int np, int max_elem, int ktaps, int max_cells)
 {
     return sizeof(float2) * np * 64 * 64 + sizeof(float2) * np * max_cells +
-           sizeof(float2) * 2 * np * static_cast<size_t>(sd.n_elem) +
-           sizeof(Tap) * static_cast<size_t>(sd.n_elem) * sd.ktaps;
+           sizeof(float2) * 2 * np * static_cast<size_t>(max_elem) +
+           sizeof(Tap) * static_cast<size_t>(max_elem) * ktaps;
 }
 
 template <int NP, int VT>
-__global__ __launch_bounds__(kFused64Block) void k_fused_fft64(StationDev sd, int n_time, int chunk,
+__global__ __launch_bounds__(kFused64Block) void k_fused_fft64(const StationDev *__restrict__ sds,
+                                                               const int4 *__restrict__ items,
+                                                               int n_time, int chunk,
                                                                float *__restrict__ partials,
                                                                const float2 *__restrict__ twg,
-                                                               int vwords, int max_cells)
+                                                               int max_elem, int max_cells)
 {
     constexpr int PLANE = 64 * 64;
     constexpr int NQ = NP == 2 ? 4 : 1;
@@ -162,15 +167,18 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(StationDev sd, in
     extern __shared__ float2 lds[];
     float2 *buf = lds;                                   // [NP][PLANE], swizzled
     float2 *gb = buf + NP * PLANE;                       // [NP][max_cells] gathered box
-    float2 *vf = gb + NP * max_cells;                    // [2][n_elem][NP] voltages
-    Tap *taps_l = reinterpret_cast<Tap *>(vf + 2 * NP * sd.n_elem);
+    float2 *vf = gb + NP * max_cells;                    // [2][max_elem][NP] voltages
+    Tap *taps_l = reinterpret_cast<Tap *>(vf + 2 * NP * max_elem);
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int j = lane & 7;                 // butterfly index in every pass
     const int yl = wv + 8 * (lane >> 3);    // row task (rows of a wave are 8 apart)
     const int kx = tid >> 3;                // column task
-    const int ck = blockIdx.x, c = blockIdx.y;
-    const int n_chunks = gridDim.x;
+    const int4 item = items[blockIdx.x];
+    const StationDev sd = sds[item.x];
+    const int c = item.y, ck = item.z;
+    const int n_chunks = (n_time + chunk - 1) / chunk;
+    const int vwords = sd.n_elem * NP * (VT == EPIC_CI8 ? 2 : 8) / 4;
     const int t_begin = ck * chunk;
     const int t_end = min(n_time, t_begin + chunk);
     const ChanPlan cp = sd.chan[c];
@@ -221,7 +229,7 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(StationDev sd, in
 
     // voltages of sample t as float pairs in vf[buffer]
     auto stash = [&](int buffer, int i, uint32_t w) {
-        float2 *dst = vf + buffer * NP * sd.n_elem;
+        float2 *dst = vf + buffer * NP * max_elem;
         if constexpr (VT == EPIC_CI8) {
             dst[2 * i] = make_float2(static_cast<float>(static_cast<int8_t>(w & 0xff)),
                                      static_cast<float>(static_cast<int8_t>((w >> 8) & 0xff)));
@@ -255,7 +263,7 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(StationDev sd, in
         }
         // G: grid the footprint box (Eq. 3 inner bracket), one cell per job
         {
-            const float2 *vcur = vf + cur * NP * sd.n_elem;
+            const float2 *vcur = vf + cur * NP * max_elem;
 #pragma unroll
             for (int q = 0; q < kFused64Rounds; ++q) {
                 if (job[q] != 0xffffffffu) {
@@ -363,7 +371,7 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(StationDev sd, in
         __syncthreads();
         cur ^= 1;
     }
-    float *out = partials + (static_cast<size_t>(c) * n_chunks + ck) * NQ * PLANE;
+    float *out = partials + sd.part_off + (static_cast<size_t>(c) * n_chunks + ck) * NQ * PLANE;
 #pragma unroll
     for (int k = 0; k < 8; ++k)
 #pragma unroll
@@ -372,85 +380,83 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(StationDev sd, in
 
 namespace {
 
-template <int NP, int VT>
-epic_status run_fused64(const StationDev &sd, int n_chan, int n_time, int chunk, float *partials,
-                        const float2 *tw, int vwords, int max_cells, hipStream_t stream)
+// the 64 x 64 register-resident kernel needs its LDS layout to fit
+bool fft64_fits(const FusedBatch &b, int n_pol, int volt_type)
 {
-    const size_t bytes = fused64_lds_bytes(NP, sd, max_cells);
+    const int64_t vbytes = static_cast<int64_t>(b.max_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8);
+    return b.n == 64 && vbytes % 4 == 0 && vbytes / 4 <= kFused64Prefetch * kFused64Block &&
+           b.max_cells <= kFused64Rounds * kFused64Block && b.max_cell_taps <= 15 &&
+           static_cast<int64_t>(b.max_elem) * b.max_ktaps <= 0xffff &&
+           fused64_lds_bytes(n_pol, b.max_elem, b.max_ktaps, b.max_cells) <= kLdsBytes;
+}
+
+template <int NP, int VT>
+epic_status run64(const FusedBatch &b, int n_time, int chunk, float *partials, const float2 *tw,
+                  hipStream_t stream)
+{
     auto k = k_fused_fft64<NP, VT>;
+    const size_t bytes = fused64_lds_bytes(NP, b.max_elem, b.max_ktaps, b.max_cells);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(bytes));
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-    const int n_chunks = (n_time + chunk - 1) / chunk;
     KernelTimer timer("fused_fft_cadence", stream);
-    hipLaunchKernelGGL(k, dim3(n_chunks, n_chan), dim3(kFused64Block), bytes, stream, sd, n_time,
-                       chunk, partials, tw, vwords, max_cells);
+    hipLaunchKernelGGL(k, dim3(b.n_items), dim3(kFused64Block), bytes, stream, b.sds, b.items,
+                       n_time, chunk, partials, tw, b.max_elem, b.max_cells);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }
 
 template <int N, int NP, int VT>
-epic_status run_fused(const StationDev &sd, int n_chan, int n_time, int chunk, float *partials,
+epic_status run_small(const FusedBatch &b, int n_time, int chunk, float *partials,
                       const float2 *tw, hipStream_t stream)
 {
-    constexpr int BLOCK = FusedShape<N>::BLOCK;
-    const size_t bytes = sizeof(float2) * (NP * N * (N + 1) + N);
     auto k = k_fused_fft<N, NP, VT>;
+    const size_t bytes = sizeof(float2) * (NP * N * (N + 1) + N);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(bytes));
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-    const int n_chunks = (n_time + chunk - 1) / chunk;
     KernelTimer timer("fused_fft_cadence", stream);
-    hipLaunchKernelGGL(k, dim3(n_chunks, n_chan), dim3(BLOCK), bytes, stream, sd, n_time, chunk,
-                       partials, tw);
+    hipLaunchKernelGGL(k, dim3(b.n_items), dim3(FusedShape<N>::BLOCK), bytes, stream, b.sds,
+                       b.items, n_time, chunk, partials, tw);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }
 
 template <int N>
-epic_status dispatch(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
-                     int chunk, float *partials, const float2 *tw, hipStream_t stream)
+epic_status dispatch(const FusedBatch &b, int n_pol, int volt_type, int n_time, int chunk,
+                     float *partials, const float2 *tw, hipStream_t stream)
 {
     if constexpr (N == 64) {
-        // register-resident variant when one sample's voltages fit the
-        // prefetch and are a whole number of 32-bit words
-        const int64_t vbytes = static_cast<int64_t>(sd.n_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8);
-        const int vwords = static_cast<int>(vbytes / 4);
-        const int64_t taps_per_chan = static_cast<int64_t>(sd.n_elem) * sd.ktaps;
-        if (vbytes % 4 == 0 && vbytes / 4 <= kFused64Prefetch * kFused64Block &&
-            sd.max_cells <= kFused64Rounds * kFused64Block && sd.max_cell_taps <= 15 &&
-            taps_per_chan <= 0xffff && fused64_lds_bytes(n_pol, sd, sd.max_cells) <= kLdsBytes) {
-            const int mc = sd.max_cells;
-            if (n_pol == 2 && volt_type == EPIC_CI8)
-                return run_fused64<2, EPIC_CI8>(sd, n_chan, n_time, chunk, partials, tw, vwords, mc, stream);
-            if (n_pol == 2)
-                return run_fused64<2, EPIC_CF32>(sd, n_chan, n_time, chunk, partials, tw, vwords, mc, stream);
-            if (volt_type == EPIC_CI8)
-                return run_fused64<1, EPIC_CI8>(sd, n_chan, n_time, chunk, partials, tw, vwords, mc, stream);
-            return run_fused64<1, EPIC_CF32>(sd, n_chan, n_time, chunk, partials, tw, vwords, mc, stream);
+        if (fft64_fits(b, n_pol, volt_type)) {
+            if (n_pol == 2 && volt_type == EPIC_CI8) return run64<2, EPIC_CI8>(b, n_time, chunk, partials, tw, stream);
+            if (n_pol == 2) return run64<2, EPIC_CF32>(b, n_time, chunk, partials, tw, stream);
+            if (volt_type == EPIC_CI8) return run64<1, EPIC_CI8>(b, n_time, chunk, partials, tw, stream);
+            return run64<1, EPIC_CF32>(b, n_time, chunk, partials, tw, stream);
         }
     }
-    if (n_pol == 2 && volt_type == EPIC_CI8)
-        return run_fused<N, 2, EPIC_CI8>(sd, n_chan, n_time, chunk, partials, tw, stream);
-    if (n_pol == 2)
-        return run_fused<N, 2, EPIC_CF32>(sd, n_chan, n_time, chunk, partials, tw, stream);
-    if (volt_type == EPIC_CI8)
-        return run_fused<N, 1, EPIC_CI8>(sd, n_chan, n_time, chunk, partials, tw, stream);
-    return run_fused<N, 1, EPIC_CF32>(sd, n_chan, n_time, chunk, partials, tw, stream);
+    if (n_pol == 2 && volt_type == EPIC_CI8) return run_small<N, 2, EPIC_CI8>(b, n_time, chunk, partials, tw, stream);
+    if (n_pol == 2) return run_small<N, 2, EPIC_CF32>(b, n_time, chunk, partials, tw, stream);
+    if (volt_type == EPIC_CI8) return run_small<N, 1, EPIC_CI8>(b, n_time, chunk, partials, tw, stream);
+    return run_small<N, 1, EPIC_CF32>(b, n_time, chunk, partials, tw, stream);
 }
 
 }  // namespace
 
-epic_status launch_fused_fft_partials(const StationDev &sd, int n_pol, int n_chan, int n_time,
-                                      int volt_type, int chunk, float *partials,
-                                      const float2 *twiddles, hipStream_t stream)
+bool fused_fft_supported(const FusedBatch &b, int, int)
 {
-    switch (sd.nx) {
-    case 16: return dispatch<16>(sd, n_pol, n_chan, n_time, volt_type, chunk, partials, twiddles, stream);
-    case 32: return dispatch<32>(sd, n_pol, n_chan, n_time, volt_type, chunk, partials, twiddles, stream);
-    case 64: return dispatch<64>(sd, n_pol, n_chan, n_time, volt_type, chunk, partials, twiddles, stream);
+    return b.n == 16 || b.n == 32 || b.n == 64;
+}
+
+epic_status launch_fused_fft_partials(const FusedBatch &b, int n_pol, int n_time, int volt_type,
+                                      int chunk, float *partials, const float2 *twiddles,
+                                      hipStream_t stream)
+{
+    switch (b.n) {
+    case 16: return dispatch<16>(b, n_pol, volt_type, n_time, chunk, partials, twiddles, stream);
+    case 32: return dispatch<32>(b, n_pol, volt_type, n_time, chunk, partials, twiddles, stream);
+    case 64: return dispatch<64>(b, n_pol, volt_type, n_time, chunk, partials, twiddles, stream);
     }
     return fail(EPIC_ERR_INTERNAL, "fused FFT path: unsupported grid");
 }

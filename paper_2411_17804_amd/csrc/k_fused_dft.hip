@@ -72,14 +72,14 @@ inline size_t fused_dft_lds_bytes(int N, int T, int np, int vt, int n_elem, int 
 
 template <int N, int T, int NP, int VT, int PREC>
 __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_dft(
-    StationDev sd, int n_time, int chunk, float *__restrict__ partials,
-    const uint32_t *__restrict__ rows, int vwords)
+    const StationDev *__restrict__ sds, const int4 *__restrict__ items, int n_time, int chunk,
+    float *__restrict__ partials, const uint32_t *__restrict__ rows, int max_elem)
 {
     using Sh = FusedDftShape<N, T>;
     using S = Split<PREC>;
     using vec8 = typename S::vec8;
     using scalar = typename S::scalar;
-    constexpr int WAVES = Sh::WAVES, BLOCK = Sh::BLOCK, PITCH = Sh::PITCH, ROUNDS = Sh::ROUNDS;
+    constexpr int WAVES = Sh::WAVES, BLOCK = Sh::BLOCK, PITCH = Sh::PITCH;
     constexpr int NQ = NP == 2 ? 4 : 1;
     constexpr int NT = N / 16;                      // k_x tiles
     constexpr int GPLANE = 16 * T * PITCH;          // words per pol of G^T
@@ -89,14 +89,17 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
     uint32_t *txh = gbl + NP * GPLANE;              // [N][PITCH] F[k_x][x0 + x] hi (re, im)
     uint32_t *txl = txh + N * PITCH;                // lo
     constexpr int VW = volt_words(VT);
-    uint32_t *vf = txl + N * PITCH;                 // [2][n_elem][NP][VW] voltages
-    uint32_t *jobs = vf + 2 * NP * VW * sd.n_elem;  // [ncell] gather jobs
+    uint32_t *vf = txl + N * PITCH;                 // [2][max_elem][NP][VW] voltages
+    uint32_t *jobs = vf + 2 * NP * VW * max_elem;   // [ncell] gather jobs
     __shared__ float vred[2][WAVES];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    const int ck = blockIdx.x, c = blockIdx.y;
-    const int n_chunks = gridDim.x;
+    const int4 item = items[blockIdx.x];
+    const StationDev sd = sds[item.x];
+    const int c = item.y, ck = item.z;
+    const int n_chunks = (n_time + chunk - 1) / chunk;
+    const int vwords = sd.n_elem * NP * (VT == EPIC_CI8 ? 2 : 8) / 4;
     const int t_begin = ck * chunk;
     const int t_end = min(n_time, t_begin + chunk);
     const ChanPlan cp = sd.chan[c];
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
     const uint32_t *vsrc = reinterpret_cast<const uint32_t *>(sd.volts) +
                            static_cast<size_t>(c) * n_time * vwords;
     auto stash = [&](int buffer, int i, uint32_t w) -> float {
-        uint32_t *dst = vf + buffer * NP * VW * sd.n_elem;
+        uint32_t *dst = vf + buffer * NP * VW * max_elem;
         if constexpr (VT == EPIC_CI8) {
             // four int8 components -> two exact FP16 pairs
             const int8_t a = static_cast<int8_t>(w & 0xff), b = static_cast<int8_t>((w >> 8) & 0xff);
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
         for (int w = 0; w < WAVES; ++w) vmax = fmaxf(vmax, vred[cur][w]);
         const float s1 = pow2_scale(vmax * cp.wsum_max);
         {
-            const uint32_t *vcur = vf + cur * NP * VW * sd.n_elem;
+            const uint32_t *vcur = vf + cur * NP * VW * max_elem;
             for (int i = tid; i < ncell; i += BLOCK) {
                 {
                     const uint32_t job = jobs[i];
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
         }
         cur ^= 1;
     }
-    float *out = partials + (static_cast<size_t>(c) * n_chunks + ck) * NQ * N * N;
+    float *out = partials + sd.part_off + (static_cast<size_t>(c) * n_chunks + ck) * NQ * N * N;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
@@ -363,82 +366,72 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
 namespace {
 
 template <int N, int T, int NP, int VT, int PREC>
-epic_status run(const StationDev &sd, int n_chan, int n_time, int chunk, float *partials,
-                const uint32_t *rows, int vwords, hipStream_t stream)
+epic_status run(const FusedBatch &b, int n_time, int chunk, float *partials, const uint32_t *rows,
+                hipStream_t stream)
 {
     using Sh = FusedDftShape<N, T>;
-    const size_t bytes = fused_dft_lds_bytes(N, T, NP, VT, sd.n_elem, sd.max_cells);
+    const size_t bytes = fused_dft_lds_bytes(N, T, NP, VT, b.max_elem, b.max_cells);
     auto k = k_fused_dft<N, T, NP, VT, PREC>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(bytes));
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-    const int n_chunks = (n_time + chunk - 1) / chunk;
     KernelTimer timer("fused_dft_cadence", stream);
-    hipLaunchKernelGGL(k, dim3(n_chunks, n_chan), dim3(Sh::BLOCK), bytes, stream, sd, n_time,
-                       chunk, partials, rows, vwords);
+    hipLaunchKernelGGL(k, dim3(b.n_items), dim3(Sh::BLOCK), bytes, stream, b.sds, b.items, n_time,
+                       chunk, partials, rows, b.max_elem);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }
 
 template <int N, int T, int PREC>
-epic_status by_type(const StationDev &sd, int n_pol, int volt_type, int n_chan, int n_time,
-                    int chunk, float *partials, const uint32_t *rows, int vwords,
-                    hipStream_t stream)
+epic_status by_type(const FusedBatch &b, int n_pol, int volt_type, int n_time, int chunk,
+                    float *partials, const uint32_t *rows, hipStream_t stream)
 {
-    if (n_pol == 2 && volt_type == EPIC_CI8)
-        return run<N, T, 2, EPIC_CI8, PREC>(sd, n_chan, n_time, chunk, partials, rows, vwords, stream);
-    if (n_pol == 2)
-        return run<N, T, 2, EPIC_CF32, PREC>(sd, n_chan, n_time, chunk, partials, rows, vwords, stream);
-    if (volt_type == EPIC_CI8)
-        return run<N, T, 1, EPIC_CI8, PREC>(sd, n_chan, n_time, chunk, partials, rows, vwords, stream);
-    return run<N, T, 1, EPIC_CF32, PREC>(sd, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    if (n_pol == 2 && volt_type == EPIC_CI8) return run<N, T, 2, EPIC_CI8, PREC>(b, n_time, chunk, partials, rows, stream);
+    if (n_pol == 2) return run<N, T, 2, EPIC_CF32, PREC>(b, n_time, chunk, partials, rows, stream);
+    if (volt_type == EPIC_CI8) return run<N, T, 1, EPIC_CI8, PREC>(b, n_time, chunk, partials, rows, stream);
+    return run<N, T, 1, EPIC_CF32, PREC>(b, n_time, chunk, partials, rows, stream);
 }
 
+// footprint tiles of a batch: its largest box side, at least the smallest
+// template size for the grid
+int tiles_of(const FusedBatch &b) { return std::max((b.max_side + 15) / 16, b.n == 64 ? 2 : 1); }
+
 template <int PREC>
-epic_status by_size(const StationDev &sd, int t, int n_pol, int volt_type, int n_chan, int n_time,
-                    int chunk, float *partials, const uint32_t *rows, int vwords,
-                    hipStream_t stream)
+epic_status by_size(const FusedBatch &b, int n_pol, int volt_type, int n_time, int chunk,
+                    float *partials, const uint32_t *rows, hipStream_t stream)
 {
-    switch (sd.nx * 8 + t) {
-    case 16 * 8 + 1: return by_type<16, 1, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
-    case 32 * 8 + 1: return by_type<32, 1, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
-    case 32 * 8 + 2: return by_type<32, 2, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
-    case 64 * 8 + 2: return by_type<64, 2, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
-    case 64 * 8 + 3: return by_type<64, 3, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
-    case 64 * 8 + 4: return by_type<64, 4, PREC>(sd, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+    switch (b.n * 8 + tiles_of(b)) {
+    case 16 * 8 + 1: return by_type<16, 1, PREC>(b, n_pol, volt_type, n_time, chunk, partials, rows, stream);
+    case 32 * 8 + 1: return by_type<32, 1, PREC>(b, n_pol, volt_type, n_time, chunk, partials, rows, stream);
+    case 32 * 8 + 2: return by_type<32, 2, PREC>(b, n_pol, volt_type, n_time, chunk, partials, rows, stream);
+    case 64 * 8 + 2: return by_type<64, 2, PREC>(b, n_pol, volt_type, n_time, chunk, partials, rows, stream);
+    case 64 * 8 + 3: return by_type<64, 3, PREC>(b, n_pol, volt_type, n_time, chunk, partials, rows, stream);
+    case 64 * 8 + 4: return by_type<64, 4, PREC>(b, n_pol, volt_type, n_time, chunk, partials, rows, stream);
     }
     return fail(EPIC_ERR_INTERNAL, "fused split path: unsupported grid/footprint");
 }
 
 }  // namespace
 
-epic_status launch_fused_dft_partials(const StationDev &sd, int n_pol, int n_chan, int n_time,
-                                      int volt_type, int precision, int chunk, float *partials,
+epic_status launch_fused_dft_partials(const FusedBatch &b, int n_pol, int n_time, int volt_type,
+                                      int precision, int chunk, float *partials,
                                       const uint32_t *rows, hipStream_t stream)
 {
-    const int n = sd.nx;
-    // footprint tiles: the largest box side over channels, at least the
-    // smallest template size for this grid
-    int t = (std::max(sd.max_bw, sd.max_bh) + 15) / 16;
-    const int tmin = n == 64 ? 2 : 1;
-    t = std::max(t, tmin);
-    const int vwords = static_cast<int>(static_cast<int64_t>(sd.n_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8) / 4);
     if (precision == EPIC_FP16_SPLIT)
-        return by_size<EPIC_FP16_SPLIT>(sd, t, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
-    return by_size<EPIC_BF16_SPLIT>(sd, t, n_pol, volt_type, n_chan, n_time, chunk, partials, rows, vwords, stream);
+        return by_size<EPIC_FP16_SPLIT>(b, n_pol, volt_type, n_time, chunk, partials, rows, stream);
+    return by_size<EPIC_BF16_SPLIT>(b, n_pol, volt_type, n_time, chunk, partials, rows, stream);
 }
 
-// Whether the fused split kernel covers this station (host-side check).
-bool fused_dft_supported(const StationDev &sd, int n_pol, int volt_type)
+bool fused_dft_supported(const FusedBatch &b, int n_pol, int volt_type)
 {
-    if (sd.nx != sd.ny || (sd.nx != 16 && sd.nx != 32 && sd.nx != 64)) return false;
-    const int64_t vbytes = static_cast<int64_t>(sd.n_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8);
+    if (b.n != 16 && b.n != 32 && b.n != 64) return false;
+    const int64_t vbytes = static_cast<int64_t>(b.max_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8);
     if (vbytes % 4 != 0) return false;
-    if (sd.max_cell_taps > 15 || static_cast<int64_t>(sd.n_elem) * sd.ktaps > 0xffff) return false;
-    const int t = std::max((std::max(sd.max_bw, sd.max_bh) + 15) / 16, sd.nx == 64 ? 2 : 1);
-    if (t > sd.nx / 16) return false;
-    return fused_dft_lds_bytes(sd.nx, t, n_pol, volt_type, sd.n_elem, sd.max_cells) <= 160 * 1024;
+    if (b.max_cell_taps > 15 || static_cast<int64_t>(b.max_elem) * b.max_ktaps > 0xffff) return false;
+    const int t = tiles_of(b);
+    if (t > b.n / 16) return false;
+    return fused_dft_lds_bytes(b.n, t, n_pol, volt_type, b.max_elem, b.max_cells) <= 160 * 1024;
 }
 
 }  // namespace epic

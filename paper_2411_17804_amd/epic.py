@@ -34,7 +34,7 @@ KERNEL_GAUSSIAN = 1
 
 # every function the header declares
 ABI_FUNCTIONS = ("grid_voltages", "fft2_batched", "accumulate_power", "image_cadence",
-                 "epic_validate", "epic_timing_enable", "epic_timing_report",
+                 "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
                  "epic_timing_reset", "epic_status_string", "epic_last_error",
                  "epic_cache_clear")
 
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.accumulate_power.restype = i32
     lib.image_cadence.argtypes = [P, P, i32, P]
     lib.image_cadence.restype = i32
+    lib.epic_autotune.argtypes = [P, P, i32, P]
+    lib.epic_autotune.restype = i32
     lib.epic_validate.argtypes = [P, P, i32]
     lib.epic_validate.restype = i32
     lib.epic_status_string.argtypes = [i32]
@@ -236,3 +238,11 @@ def image_cadence(common: Common, stations, stream=None):
     c, keep1 = common.to_c()
     arr, keep = _stations_c(stations)
     _check(lib.image_cadence(ctypes.byref(c), arr, len(stations), _stream(stream)))
+
+
+def autotune(common: Common, stations, stream=None):
+    """Time the fused kernels' chunk lengths on these buffers and keep the best."""
+    lib = load()
+    c, keep1 = common.to_c()
+    arr, keep = _stations_c(stations)
+    _check(lib.epic_autotune(ctypes.byref(c), arr, len(stations), _stream(stream)))

@@ -252,3 +252,58 @@ def test_image_cadence_split(torch, case):
         say(f"  {case} station {s}: worst error {err.max():.2e}")
         assert err.max() <= SPLIT_TOL[prec], err
         assert np.array_equal(imgs[s][:, 2], np.conj(imgs[s][:, 1]))
+
+
+# ------------------------------------------- hierarchical batch, graphs, tuning ----
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_image_cadence_hierarchical_batch(torch, prec):
+    # 12 stations of uneven size (grids 32/64/128) in one call; ragged cadence
+    p = W.FP32_FFT if prec == "fp32" else W.FP16_SPLIT
+    cfg = W.make_config(4, chan_subset=[0, 63], n_time=40, n_stations=12, precision=p)
+    sizes = sorted({s.nx for s in cfg.stations})
+    say(f"image_cadence C4 {prec}: 12 stations, grids {sizes}")
+    assert len(sizes) >= 2
+    volts, imgs, _ = run_cadence(cfg)
+    tol = FP32_TOL if prec == "fp32" else SPLIT_TOL["fp16"]
+    worst = 0.0
+    for s in range(len(cfg.stations)):
+        err = oracle.image_error(imgs[s], oracle_image(cfg, s, volts[s]), cfg.n_pol)
+        worst = max(worst, float(err.max()))
+        assert err.max() <= tol, (s, cfg.stations[s].nx, err)
+    say(f"  worst error over stations {worst:.2e}")
+
+
+def test_graph_replays_match_eager(torch):
+    # the first call runs eagerly, later calls replay a captured graph; eager
+    # work and synchronisations sit between the replays
+    from paper_2411_17804_amd import epic
+    say("image_cadence graph replays")
+    cfg = W.make_config(4, chan_subset=[1, 2], n_time=33, n_stations=6, precision=W.FP16_SPLIT)
+    # keep only the stations the fused kernels cover (grids up to 64)
+    cfg.stations = [s for s in cfg.stations if s.nx <= 64][:4]
+    volts = [W.station_volts(cfg, s) for s in range(len(cfg.stations))]
+    common, stations = station_objects(cfg, [to_device_volts(v) for v in volts])
+    epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    ref = [s.image.clone() for s in stations]
+    for rep in range(4):
+        for s in stations:
+            s.image.fill_(float("nan"))          # eager work between replays
+        torch.cuda.synchronize()
+        epic.image_cadence(common, stations)
+        torch.cuda.synchronize()
+        for a, b in zip(ref, stations):
+            assert torch.equal(a, b.image), f"replay {rep} differs from the eager result"
+
+
+def test_autotune_then_cadence(torch, tmp_path, monkeypatch):
+    from paper_2411_17804_amd import epic
+    say("autotune + image_cadence")
+    cfg = W.make_config(2, chan_subset=[0, 700], n_time=96, precision=W.FP32_FFT)
+    volts = [W.station_volts(cfg, 0)]
+    common, stations = station_objects(cfg, [to_device_volts(volts[0])])
+    epic.autotune(common, stations)
+    epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    err = oracle.image_error(to_complex(stations[0].image), oracle_image(cfg, 0, volts[0]), 2)
+    assert err.max() <= FP32_TOL
