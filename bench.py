@@ -88,6 +88,31 @@ def flops_per_pixel_sample(cfg, st):
     return fft + grid + prod
 
 
+def split_mfma_flops(cfg):
+    """Matrix-core flops of the fused split-precision kernel for one cadence
+    (stations with square grids up to 64): per sample, pol and channel, each of
+    the n/16 waves (16 output rows each) runs my*mx stage-1 and (n/16)*mx
+    stage-2 16x16x32 tiles for the real and imaginary outputs, three split
+    products each, where mx, my are the footprint box sides in 16-cell tiles.
+    The box follows the element cells and kernel support exactly as the plan
+    places them."""
+    total = 0
+    for st in cfg.stations:
+        if st.nx != st.ny or st.nx > 64:
+            continue
+        h = (st.support - 1) // 2
+        for lam in cfg.wavelengths_m:
+            d = W.GRID_SPACING_WL * lam
+            ci = np.floor(st.pos_m[:, 0] / d + st.nx // 2 + 0.5)
+            cj = np.floor(st.pos_m[:, 1] / d + st.ny // 2 + 0.5)
+            bw = int(ci.max() - ci.min()) + 2 * h + 1
+            bh = int(cj.max() - cj.min()) + 2 * h + 1
+            mx, my = -(-bw // 16), -(-bh // 16)
+            tiles = (st.nx // 16) * 2 * 3 * (my * mx + (st.nx // 16) * mx)
+            total += tiles * 16 * 16 * 32 * 2 * cfg.n_time * cfg.n_pol
+    return total
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +127,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default time-chunk length of the fused kernels")
+    ap.add_argument("--no-stages", action="store_true",
+                    help="skip the per-stage (unfused) roofline measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to scale the HBM "
                          "byte counters of a profiler run)")
@@ -204,9 +231,15 @@ def main():
                 "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4),
                 "flop_per_pixel_sample": round(flop_px, 2)}
     else:
-        roof = {"bound": "mfma", "achieved": None, "peak": PEAK_FP16_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": None, "traffic": None, "kernel": dom_name,
-                "avg_launch_ms": round(dom_avg_ms, 4)}
+        fl = split_mfma_flops(cfg) if dom_name == "fused_dft_cadence" else None
+        achieved = fl / launches_per_step / (dom_avg_ms / 1e3) / 1e12 if fl else None
+        roof = {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
+                "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP16_MFMA_TFLOPS, 4) if achieved else None,
+                "traffic": measured_traffic(dom_name, f"C{cfg.index}")
+                if cfg.n_chan == W.make_config(cfg.index).n_chan and args.n_time is None else None,
+                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4),
+                "flop_per_step": fl}
 
     out = {
         "metric": "grid pixel-samples/s per GPU",
@@ -234,9 +267,77 @@ def main():
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
     }
 
+    if not args.no_stages:
+        c0 = epic.Common(cfg.n_pol, cfg.wavelengths_m, W.GRID_SPACING_WL, cfg.n_time,
+                         cfg.volt_type, cfg.precision)
+        out["stages"] = stage_rooflines(cfg, c0, stations[0])
+        log(f"stages: {out['stages']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, stations, host_volts, args.cpu_channels)
     print(json.dumps(out), flush=True)
+
+
+def stage_rooflines(cfg, common, station, nt=64, reps=3):
+    """Each unfused stage on a block of nt samples of every channel of the
+    first station, timed with events on the current stream, against the
+    roofline that bounds it (algorithmic bytes for HBM-bound stages,
+    algorithmic matrix-core flops for the DFT-matrix products)."""
+    import torch
+    from paper_2411_17804_amd import epic
+    st = cfg.stations[0]
+    npix = st.nx * st.ny
+    nt = min(nt, cfg.n_time)
+    batch = cfg.n_chan * nt * cfg.n_pol
+    field_bytes = batch * npix * 8
+    grid = torch.empty((cfg.n_chan, nt, cfg.n_pol, st.ny, st.nx, 2), dtype=torch.float32,
+                       device="cuda:0")
+    out = torch.empty_like(grid)
+    acc = torch.zeros((2, cfg.n_chan, cfg.n_pol ** 2, st.ny, st.nx, 2), dtype=torch.float32,
+                      device="cuda:0")
+    img = torch.empty_like(acc[0])
+    bv = 2 if cfg.volt_type == W.CI8 else 8
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = 1e30
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    res = {}
+    ms = timed(lambda: epic.grid_voltages(common, station, 0, nt, grid))
+    b = cfg.n_chan * nt * st.n_elem * cfg.n_pol * bv + field_bytes
+    res["grid_voltages"] = {"ms": round(ms, 3), "bound": "hbm", "bytes": b,
+                            "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
+                            "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    ms = timed(lambda: epic.fft2_batched(st.nx, st.ny, batch, epic.FP32_FFT, grid, out))
+    b = 2 * field_bytes
+    res["fft2_batched_fp32"] = {"ms": round(ms, 3), "bound": "hbm", "bytes": b,
+                                "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
+                                "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    for name, p in (("fp16", epic.FP16_SPLIT), ("bf16", epic.BF16_SPLIT)):
+        ms = timed(lambda: epic.fft2_batched(st.nx, st.ny, batch, p, grid, out))
+        fl = batch * 3 * 8 * (st.ny ** 2 * st.nx + st.nx ** 2 * st.ny)
+        res[f"fft2_batched_{name}_split"] = {
+            "ms": round(ms, 3), "bound": "mfma", "flops": fl,
+            "achieved": round(fl / ms / 1e9, 1), "unit": "TFLOP/s",
+            "frac": round(fl / ms / 1e9 / PEAK_FP16_MFMA_TFLOPS, 4)}
+    ms = timed(lambda: epic.accumulate_power(cfg.n_pol, st.nx, st.ny, cfg.n_chan, nt, out, acc[0],
+                                             acc[1], nt, img))
+    b = field_bytes + 5 * cfg.n_chan * cfg.n_pol ** 2 * npix * 8
+    res["accumulate_power"] = {"ms": round(ms, 3), "bound": "hbm", "bytes": b,
+                               "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
+                               "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    res["_block"] = f"{cfg.n_chan} channels x {nt} samples x {cfg.n_pol} pols of {st.nx}x{st.ny}"
+    del grid, out, acc, img
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(cfg, stations, host_volts, n_sample_chan):
