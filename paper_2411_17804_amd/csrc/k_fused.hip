@@ -378,6 +378,232 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(const StationDev 
         for (int q = 0; q < NQ; ++q) out[q * PLANE + (j + 8 * k) * 64 + kx] = acc[k][q];
 }
 
+// Two-pol form of the 64 x 64 kernel with 1024 threads: threads 0-511 carry
+// pol X and threads 512-1023 pol Y through the same passes as above (one
+// radix-8 butterfly of one pol per thread and pass).  That halves the
+// registers of a thread and doubles the waves that hide LDS latency.  After
+// the last column pass both halves leave their pixels in LDS and each picks up
+// the other pol's, so that each forms and accumulates two of the four
+// products.
+constexpr int kFused64x2Block = 1024;
+
+template <int VT>
+__global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const StationDev *__restrict__ sds,
+                                                                   const int4 *__restrict__ items,
+                                                                   int n_time, int chunk,
+                                                                   float *__restrict__ partials,
+                                                                   const float2 *__restrict__ twg,
+                                                                   int max_elem, int max_cells)
+{
+    constexpr int NP = 2;
+    constexpr int PLANE = 64 * 64;
+    constexpr int BLOCK = kFused64x2Block;
+    constexpr int ROUNDS = kFused64Rounds * kFused64Block / BLOCK;
+    constexpr int PREFETCH = kFused64Prefetch * kFused64Block / BLOCK;
+    extern __shared__ float2 lds[];
+    float2 *buf = lds;                                   // [2][PLANE], swizzled
+    float2 *gb = buf + NP * PLANE;                       // [2][max_cells] gathered box
+    float2 *vf = gb + NP * max_cells;                    // [2][max_elem][2] voltages
+    Tap *taps_l = reinterpret_cast<Tap *>(vf + 2 * NP * max_elem);
+
+    const int tid = threadIdx.x;
+    const int pol = tid >> 9, tp5 = tid & 511;          // pol of this thread, index within it
+    const int lane = tp5 & 63, wv = tp5 >> 6;
+    const int j = lane & 7;
+    const int yl = wv + 8 * (lane >> 3);
+    const int kx = tp5 >> 3;
+    const int4 item = items[blockIdx.x];
+    const StationDev sd = sds[item.x];
+    const int c = item.y, ck = item.z;
+    const int n_chunks = (n_time + chunk - 1) / chunk;
+    const int vwords = sd.n_elem * NP * (VT == EPIC_CI8 ? 2 : 8) / 4;
+    const int t_begin = ck * chunk;
+    const int t_end = min(n_time, t_begin + chunk);
+    const ChanPlan cp = sd.chan[c];
+    const bool row_active = yl < cp.bh;
+    const int y = cp.y0 + yl;
+    const int ncell = cp.bw * cp.bh;
+    float2 *plane = buf + pol * PLANE;
+    const float2 *gpl = gb + pol * max_cells;
+
+    // gather jobs: all 1024 threads grid both pols of one cell each round
+    uint32_t job[ROUNDS];
+    {
+        const int32_t *cs = sd.cell_start + cp.cell_off;
+        const int32_t *ord = sd.cell_order + cp.cell_off;
+        const Tap *taps = sd.taps + cp.tap_off;
+        const int ntap = cs[ncell];
+        for (int i = tid; i < ntap; i += BLOCK) taps_l[i] = taps[i];
+#pragma unroll
+        for (int q = 0; q < ROUNDS; ++q) {
+            const int i = tid + q * BLOCK;
+            job[q] = 0xffffffffu;
+            if (i < ncell) {
+                const int cell = ord[i];
+                const int k0 = cs[cell];
+                job[q] = (static_cast<uint32_t>(cell) << 20) |
+                         (static_cast<uint32_t>(cs[cell + 1] - k0) << 16) | static_cast<uint32_t>(k0);
+            }
+        }
+    }
+
+    float2 tw[8];
+#pragma unroll
+    for (int r = 1; r < 8; ++r) tw[r] = twg[r * j];
+    const int tr = (y ^ (y >> 3)) & 7;
+    const int sr = tr | ((tr & 3) << 3);
+    const int bt = y * 64 + ((8 * j) ^ (sr & 0x18)) + tr;
+    const int bj = y * 64 + (j ^ tr) + (sr & 0x18);
+    int cm[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int t = (j ^ m) & 7;
+        cm[m] = j * 64 + (kx ^ (t | ((t & 3) << 3)));
+    }
+    const int dj = 448 * j;
+
+    auto stash = [&](int buffer, int i, uint32_t w) {
+        float2 *dst = vf + buffer * NP * max_elem;
+        if constexpr (VT == EPIC_CI8) {
+            dst[2 * i] = make_float2(static_cast<float>(static_cast<int8_t>(w & 0xff)),
+                                     static_cast<float>(static_cast<int8_t>((w >> 8) & 0xff)));
+            dst[2 * i + 1] = make_float2(static_cast<float>(static_cast<int8_t>((w >> 16) & 0xff)),
+                                         static_cast<float>(static_cast<int8_t>((w >> 24) & 0xff)));
+        } else {
+            reinterpret_cast<uint32_t *>(dst)[i] = w;
+        }
+    };
+    const uint32_t *vsrc = reinterpret_cast<const uint32_t *>(sd.volts) +
+                           static_cast<size_t>(c) * n_time * vwords;
+    for (int i = tid; i < vwords; i += BLOCK) stash(0, i, vsrc[static_cast<size_t>(t_begin) * vwords + i]);
+
+    float acc[8][2];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[k][q] = 0.f;
+    __syncthreads();
+
+    int cur = 0;
+    for (int t = t_begin; t < t_end; ++t) {
+        const bool has_next = t + 1 < t_end;
+        uint32_t pre[PREFETCH];
+        if (has_next) {
+#pragma unroll
+            for (int q = 0; q < PREFETCH; ++q) {
+                const int i = tid + q * BLOCK;
+                if (i < vwords) pre[q] = vsrc[static_cast<size_t>(t + 1) * vwords + i];
+            }
+        }
+        // G: grid the footprint box (Eq. 3 inner bracket); a cell's taps serve both pols
+        {
+            const float2 *vcur = vf + cur * NP * max_elem;
+#pragma unroll
+            for (int q = 0; q < ROUNDS; ++q) {
+                if (job[q] != 0xffffffffu) {
+                    const int cell = job[q] >> 20, kn = (job[q] >> 16) & 15, k0 = job[q] & 0xffff;
+                    float2 a0 = make_float2(0.f, 0.f), a1 = a0;
+                    for (int s = 0; s < kn; ++s) {
+                        const Tap tp = taps_l[k0 + s];
+                        const float2 e0 = vcur[tp.elem * 2], e1 = vcur[tp.elem * 2 + 1];
+                        a0.x = fmaf(tp.w, e0.x, a0.x);
+                        a0.y = fmaf(tp.w, e0.y, a0.y);
+                        a1.x = fmaf(tp.w, e1.x, a1.x);
+                        a1.y = fmaf(tp.w, e1.y, a1.y);
+                    }
+                    gb[cell] = a0;
+                    gb[max_cells + cell] = a1;
+                }
+            }
+        }
+        if (has_next) {
+#pragma unroll
+            for (int q = 0; q < PREFETCH; ++q) {
+                const int i = tid + q * BLOCK;
+                if (i < vwords) stash(cur ^ 1, i, pre[q]);
+            }
+        }
+        __syncthreads();
+        // R1: first radix-8 pass along x of this thread's pol
+        if (row_active) {
+            float2 v[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int bx = j + 8 * m - cp.x0;
+                v[m] = (bx >= 0 && bx < cp.bw) ? gpl[yl * cp.bw + bx] : make_float2(0.f, 0.f);
+            }
+            Dft<8>::run(v);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) plane[bt ^ k] = v[k];
+        }
+        __syncthreads();
+        // R2: second pass along x, in place
+        if (row_active) {
+            float2 v[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) v[r] = plane[bj ^ (8 * r)];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], tw[r]);
+            Dft<8>::run(v);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) plane[bj ^ (8 * r)] = v[r];
+        }
+        __syncthreads();
+        // C1: first pass along y for column kx
+        {
+            float2 v[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int yy = j + 8 * m;
+                const bool in = yy >= cp.y0 && yy < cp.y0 + cp.bh;
+                v[m] = in ? plane[cm[m] + 512 * m] : make_float2(0.f, 0.f);
+            }
+            Dft<8>::run(v);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 8; ++k) plane[cm[k] + dj + 64 * k] = v[k];
+        }
+        __syncthreads();
+        // C2: second pass along y; pixel (ky = j + 8k, kx) of this thread's pol.
+        // A thread reads and rewrites only its own eight addresses, so the
+        // result goes back in place without a barrier in between.
+        float2 v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = plane[cm[r] + 512 * r];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], tw[r]);
+        Dft<8>::run(v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) plane[cm[k] + 512 * k] = v[k];
+        __syncthreads();
+        // products (Eq. 2): pol-X threads keep XX and Re XY, pol-Y threads
+        // Im XY and YY.  The next sample writes the planes only after the
+        // barrier that follows its gather, so the other pol's plane is stable.
+        {
+            const float2 *other = buf + (pol ^ 1) * PLANE;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float2 w = other[cm[k] + 512 * k];
+                const float2 fx = pol == 0 ? v[k] : w, fy = pol == 0 ? w : v[k];
+                if (pol == 0) {
+                    acc[k][0] = fmaf(fx.x, fx.x, fmaf(fx.y, fx.y, acc[k][0]));
+                    acc[k][1] = fmaf(fx.x, fy.x, fmaf(fx.y, fy.y, acc[k][1]));
+                } else {
+                    acc[k][0] = fmaf(fx.y, fy.x, fmaf(-fx.x, fy.y, acc[k][0]));
+                    acc[k][1] = fmaf(fy.x, fy.x, fmaf(fy.y, fy.y, acc[k][1]));
+                }
+            }
+        }
+        cur ^= 1;
+    }
+    float *out = partials + sd.part_off + (static_cast<size_t>(c) * n_chunks + ck) * 4 * PLANE +
+                 2 * pol * PLANE;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) out[q * PLANE + (j + 8 * k) * 64 + kx] = acc[k][q];
+}
+
 namespace {
 
 // the 64 x 64 register-resident kernel needs its LDS layout to fit
@@ -407,6 +633,23 @@ epic_status run64(const FusedBatch &b, int n_time, int chunk, float *partials, c
     return EPIC_OK;
 }
 
+template <int VT>
+epic_status run64x2(const FusedBatch &b, int n_time, int chunk, float *partials, const float2 *tw,
+                    hipStream_t stream)
+{
+    auto k = k_fused_fft64x2<VT>;
+    const size_t bytes = fused64_lds_bytes(2, b.max_elem, b.max_ktaps, b.max_cells);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(bytes));
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    KernelTimer timer("fused_fft_cadence", stream);
+    hipLaunchKernelGGL(k, dim3(b.n_items), dim3(kFused64x2Block), bytes, stream, b.sds, b.items,
+                       n_time, chunk, partials, tw, b.max_elem, b.max_cells);
+    EPIC_HIP_TRY(hipGetLastError());
+    return EPIC_OK;
+}
+
 template <int N, int NP, int VT>
 epic_status run_small(const FusedBatch &b, int n_time, int chunk, float *partials,
                       const float2 *tw, hipStream_t stream)
@@ -430,8 +673,8 @@ epic_status dispatch(const FusedBatch &b, int n_pol, int volt_type, int n_time, 
 {
     if constexpr (N == 64) {
         if (fft64_fits(b, n_pol, volt_type)) {
-            if (n_pol == 2 && volt_type == EPIC_CI8) return run64<2, EPIC_CI8>(b, n_time, chunk, partials, tw, stream);
-            if (n_pol == 2) return run64<2, EPIC_CF32>(b, n_time, chunk, partials, tw, stream);
+            if (n_pol == 2 && volt_type == EPIC_CI8) return run64x2<EPIC_CI8>(b, n_time, chunk, partials, tw, stream);
+            if (n_pol == 2) return run64x2<EPIC_CF32>(b, n_time, chunk, partials, tw, stream);
             if (volt_type == EPIC_CI8) return run64<1, EPIC_CI8>(b, n_time, chunk, partials, tw, stream);
             return run64<1, EPIC_CF32>(b, n_time, chunk, partials, tw, stream);
         }

@@ -337,7 +337,7 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
                         zx[nt][0] = z0;
                         zx[nt][1] = z1;
                     }
-                } else {
+                } else if constexpr (NP == 2) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const float xr = zx[nt][0][i], xi = zx[nt][1][i];
