@@ -116,13 +116,13 @@ def split_mfma_flops(cfg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--precision", choices=sorted(PREC_NAMES), default="fp32")
     ap.add_argument("--n-chan", type=int, default=None, help="shrink the band (testing)")
     ap.add_argument("--n-time", type=int, default=None, help="shrink the cadence (testing)")
-    ap.add_argument("--cpu-channels", type=int, default=64,
+    ap.add_argument("--cpu-channels", type=int, default=192,
                     help="channels of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",

@@ -384,7 +384,9 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(const StationDev 
 // registers of a thread and doubles the waves that hide LDS latency.  After
 // the last column pass both halves leave their pixels in LDS and each picks up
 // the other pol's, so that each forms and accumulates two of the four
-// products.
+// products.  A wave's row tasks are 8 adjacent rows aligned to 8 (the swizzle
+// keeps those conflict-free too), so waves whose rows miss the footprint box
+// skip the row passes.
 constexpr int kFused64x2Block = 1024;
 
 template <int VT>
@@ -410,7 +412,7 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
     const int pol = tid >> 9, tp5 = tid & 511;          // pol of this thread, index within it
     const int lane = tp5 & 63, wv = tp5 >> 6;
     const int j = lane & 7;
-    const int yl = wv + 8 * (lane >> 3);
+    const int y = 8 * wv + (lane >> 3);                  // row task: a wave owns 8 adjacent rows
     const int kx = tp5 >> 3;
     const int4 item = items[blockIdx.x];
     const StationDev sd = sds[item.x];
@@ -420,8 +422,8 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
     const int t_begin = ck * chunk;
     const int t_end = min(n_time, t_begin + chunk);
     const ChanPlan cp = sd.chan[c];
-    const bool row_active = yl < cp.bh;
-    const int y = cp.y0 + yl;
+    const int yl = y - cp.y0;
+    const bool row_active = yl >= 0 && yl < cp.bh;       // waves wholly outside the box skip R1, R2
     const int ncell = cp.bw * cp.bh;
     float2 *plane = buf + pol * PLANE;
     const float2 *gpl = gb + pol * max_cells;
