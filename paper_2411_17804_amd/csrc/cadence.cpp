@@ -1,14 +1,17 @@
 // cadence.cpp -- the image_cadence driver.
 //
 // Stations of one call are sorted into kernel classes: the fused FP32 kernel
-// (square grids up to 64, one class per grid size) and the fused
-// split-precision kernel (square grids up to 64, one class per grid size and
-// footprint tile count, split further if the LDS would overflow).  Each class
-// runs as ONE launch over its work items (station, channel, time chunk),
-// ordered largest station first so the longest items start first.  Each
-// fused station then gets its ordered, compensated chunk reduction.  Stations
-// outside every class take the composed path (grid -> transform -> square and
-// accumulate, in time chunks).
+// (square grids up to 64, one class per grid size), the fused split-precision
+// kernel (square grids up to 64, one class per grid size and footprint tile
+// count, split further if the LDS would overflow) and the FP32 path for
+// 128 x 128 grids.  Each of the first two runs as ONE launch over its work
+// items (station, channel, time chunk), ordered largest station first so the
+// longest items start first.  The 128 x 128 class runs per time block: a
+// gridding launch into footprint boxes, then the fused transform-and-square
+// launch, for each batch of (station, channel) pairs whose boxes fit the box
+// buffer.  Each fused station then gets its ordered, compensated chunk
+// reduction.  Stations outside every class take the composed path (grid ->
+// transform -> square and accumulate, in time chunks).
 //
 // The class tables, item lists and partial-sum buffers are built once per
 // distinct call (same geometry, buffers and stream) and kept; when every
@@ -39,7 +42,15 @@ epic_status cadence_composed(const epic_common *c, const epic_station *s, const 
 
 namespace {
 
-constexpr int kPathFft = 0, kPathDft = 1;
+constexpr int kPathFft = 0, kPathDft = 1, kPathFft128 = 2;
+// Bytes of footprint boxes per batch of the 128 x 128 class: 2 GiB, or
+// EPIC_BOX_BUDGET_MB megabytes (a smaller buffer means more, smaller batches).
+size_t box_budget()
+{
+    const char *e = std::getenv("EPIC_BOX_BUDGET_MB");
+    const long mb = e ? std::atol(e) : 0;
+    return mb > 0 ? static_cast<size_t>(mb) << 20 : size_t(2) << 30;
+}
 constexpr int kDefaultChunk = 32;
 const int kChunkCandidates[] = {16, 32, 64};
 
@@ -50,6 +61,7 @@ struct Group {
     int chunk = kDefaultChunk;
     std::vector<int> members;     // station indices of the call
     FusedBatch batch;             // device pointers set after upload
+    std::vector<std::pair<int, int>> pair_batches;   // 128 x 128 class: (first item, count)
     std::vector<StationDev> host_sds;
     std::vector<int4> host_items;
 };
@@ -61,6 +73,7 @@ struct CadencePlan {
     std::vector<int> chunk;          // per station chunk length (fused stations)
     void *dev_tables = nullptr;
     float *partials = nullptr;
+    float2 *boxes = nullptr;         // footprint boxes of one batch (128 x 128 class)
     const float2 *twiddles[257] = {};
     const uint32_t *rows[257] = {};
     hipGraph_t graph = nullptr;
@@ -80,7 +93,7 @@ int tiles_for_side(int side, int n) { return std::max((side + 15) / 16, n == 64 
 std::string class_key(int path, int n, int tiles, const epic_common *c)
 {
     std::ostringstream o;
-    o << (path == kPathFft ? "fft" : "dft") << "_n" << n << "_t" << tiles << "_p" << c->n_pol << "_v"
+    o << (path == kPathFft ? "fft" : path == kPathDft ? "dft" : "fft128") << "_n" << n << "_t" << tiles << "_p" << c->n_pol << "_v"
       << c->volt_type << "_q" << c->precision;
     return o.str();
 }
@@ -118,6 +131,7 @@ void free_plan(CadencePlan *p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->dev_tables) (void)hipFree(p->dev_tables);
     if (p->partials) (void)hipFree(p->partials);
+    if (p->boxes) (void)hipFree(p->boxes);
     delete p;
 }
 
@@ -152,7 +166,10 @@ void classify(const epic_common *c, const epic_station *st, int n, const PlanHan
         const StationDev sd = make_station_dev(&st[i], plans[i]);
         const bool square = st[i].nx == st[i].ny && st[i].nx <= 64;
         int path = -1, tiles = 0;
-        if (square && c->precision == EPIC_FP32_FFT) {
+        if (st[i].nx == st[i].ny && c->precision == EPIC_FP32_FFT &&
+            fused128_supported(st[i].nx, sd.max_bw, sd.max_bh, sd.n_elem, c->n_pol)) {
+            path = kPathFft128;
+        } else if (square && c->precision == EPIC_FP32_FFT) {
             path = kPathFft;
         } else if (square) {
             FusedBatch one;
@@ -204,7 +221,7 @@ void classify(const epic_common *c, const epic_station *st, int n, const PlanHan
             next.max_cell_taps = std::max(next.max_cell_taps, sd.max_cell_taps);
             next.max_ktaps = std::max(next.max_ktaps, sd.ktaps);
             next.max_side = std::max(next.max_side, std::max(sd.max_bw, sd.max_bh));
-            const bool fits = g.path == kPathFft || fused_dft_supported(next, c->n_pol, c->volt_type);
+            const bool fits = g.path != kPathDft || fused_dft_supported(next, c->n_pol, c->volt_type);
             if (!fits && !cur.members.empty()) {
                 out.push_back(cur);
                 cur.members.clear();
@@ -233,7 +250,7 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
     p->chunk.assign(n, 0);
     const int nq = c->n_pol == 2 ? 4 : 1;
     int64_t part = 0;
-    size_t n_sds = 0, n_items = 0;
+    size_t n_sds = 0, n_items = 0, box_floats = 0;
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         Group &g = p->groups[gi];
         if (gi < chunks_override.size() && chunks_override[gi] > 0) g.chunk = chunks_override[gi];
@@ -246,14 +263,36 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
             p->chunk[i] = g.chunk;
             part += static_cast<int64_t>(c->n_chan) * n_chunks * nq * sd.nx * sd.ny;
             g.host_sds.push_back(sd);
-            for (int ch = 0; ch < c->n_chan; ++ch)
-                for (int ck = 0; ck < n_chunks; ++ck)
-                    g.host_items.push_back(make_int4(static_cast<int>(k), ch, ck, 0));
+            if (g.path == kPathFft128) {
+                for (int ch = 0; ch < c->n_chan; ++ch) g.host_items.push_back(make_int4(static_cast<int>(k), ch, 0, 0));
+            } else {
+                for (int ch = 0; ch < c->n_chan; ++ch)
+                    for (int ck = 0; ck < n_chunks; ++ck)
+                        g.host_items.push_back(make_int4(static_cast<int>(k), ch, ck, 0));
+            }
         }
         g.batch.n_items = static_cast<int>(g.host_items.size());
+        if (g.path == kPathFft128) {
+            // batches of pairs whose boxes for one time block fit the budget;
+            // box offsets restart at 0 in every batch (one buffer serves all)
+            size_t pair_floats = 0;
+            for (const StationDev &sd : g.host_sds)
+                pair_floats = std::max(pair_floats, static_cast<size_t>(g.chunk) * c->n_pol * sd.max_bw * sd.max_bh);
+            const int n_pairs = static_cast<int>(g.host_items.size());
+            int per = static_cast<int>(std::max<size_t>(1, box_budget() / (sizeof(float2) * pair_floats)));
+            if (per > 256 && per < n_pairs) per = per / 256 * 256;   // whole waves of work-groups
+            per = std::min(per, n_pairs);
+            for (int first = 0; first < n_pairs; first += per) {
+                const int cnt = std::min(per, n_pairs - first);
+                for (int q = 0; q < cnt; ++q)
+                    g.host_items[first + q].w = static_cast<int>(static_cast<size_t>(q) * pair_floats);
+                g.pair_batches.emplace_back(first, cnt);
+            }
+            box_floats = std::max(box_floats, static_cast<size_t>(per) * pair_floats);
+        }
         n_sds += g.host_sds.size();
         n_items += g.host_items.size();
-        if (g.path == kPathFft && !p->twiddles[g.n]) {
+        if (g.path != kPathDft && !p->twiddles[g.n]) {
             epic_status s = get_twiddles(g.n, device, &p->twiddles[g.n]);
             if (s != EPIC_OK) return s;
         }
@@ -268,6 +307,10 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
     if (e != hipSuccess) return hip_fail(e, "hipMalloc (cadence tables)");
     e = hipMalloc(reinterpret_cast<void **>(&p->partials), sizeof(float) * std::max<int64_t>(part, 1));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc (chunk partial sums)");
+    if (box_floats) {
+        e = hipMalloc(reinterpret_cast<void **>(&p->boxes), sizeof(float2) * box_floats);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc (footprint boxes)");
+    }
     char *base = static_cast<char *>(p->dev_tables);
     StationDev *dsds = reinterpret_cast<StationDev *>(base);
     int4 *ditems = reinterpret_cast<int4 *>(base + sds_bytes);
@@ -291,6 +334,22 @@ epic_status launch_group(const epic_common *c, const CadencePlan *p, const Group
     if (g.path == kPathFft)
         return launch_fused_fft_partials(g.batch, c->n_pol, c->n_time, c->volt_type, g.chunk,
                                          p->partials, p->twiddles[g.n], stream);
+    if (g.path == kPathFft128) {
+        const int n_blocks = (c->n_time + g.chunk - 1) / g.chunk;
+        for (int blk = 0; blk < n_blocks; ++blk)
+            for (const auto &pb : g.pair_batches) {
+                FusedBatch sub = g.batch;
+                sub.items = g.batch.items + pb.first;
+                sub.n_items = pb.second;
+                epic_status s = launch_grid_box(sub, c->n_pol, c->n_time, c->volt_type, g.chunk, blk,
+                                                p->boxes, stream);
+                if (s != EPIC_OK) return s;
+                s = launch_fused_fft128_partials(sub, c->n_pol, c->n_time, g.chunk, blk, p->boxes,
+                                                 p->partials, p->twiddles[g.n], stream);
+                if (s != EPIC_OK) return s;
+            }
+        return EPIC_OK;
+    }
     return launch_fused_dft_partials(g.batch, c->n_pol, c->n_time, c->volt_type, c->precision,
                                      g.chunk, p->partials, p->rows[g.n], stream);
 }

@@ -173,6 +173,18 @@ epic_status launch_fused_fft_partials(const FusedBatch &b, int n_pol, int n_time
 // Whether the fused FP32 kernels cover a batch with these maxima.
 bool fused_fft_supported(const FusedBatch &b, int n_pol, int volt_type);
 
+// The FP32 cadence for 128 x 128 grids (k_fused128.hip), per time block:
+// launch_grid_box grids the block's samples of every (station, channel) pair
+// of the batch (items: station index, channel, 0, box offset in float2) into
+// footprint boxes [t][pol][max_bh][max_bw]; launch_fused_fft128_partials
+// transforms them and writes the block's partial sums (one item per pair).
+bool fused128_supported(int n, int max_bw, int max_bh, int n_elem, int n_pol);
+epic_status launch_grid_box(const FusedBatch &b, int n_pol, int n_time, int volt_type, int chunk,
+                            int block, float2 *boxes, hipStream_t stream);
+epic_status launch_fused_fft128_partials(const FusedBatch &b, int n_pol, int n_time, int chunk,
+                                         int block, const float2 *boxes, float *partials,
+                                         const float2 *twiddles, hipStream_t stream);
+
 // Ordered, compensated reduction of the partial sums of every chunk, then the
 // mean, written as the n_pol^2 complex products.
 epic_status launch_reduce_partials(int n_pol, int npix, int n_chan, int n_chunks,

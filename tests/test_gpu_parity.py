@@ -145,6 +145,7 @@ CADENCE_CASES = {
     "C2-3ch": (2, [0, 600, 1023], 96),
     "C2-ragged-time": (2, [3], 37),
     "C3-2ch": (3, [0, 255], 12),
+    "C3-ragged-blocks": (3, [5, 130, 250], 70),
     "C5-1ch": (5, [64], 3),
 }
 
@@ -273,14 +274,19 @@ def test_image_cadence_hierarchical_batch(torch, prec):
     say(f"  worst error over stations {worst:.2e}")
 
 
-def test_graph_replays_match_eager(torch):
+@pytest.mark.parametrize("prec", ["fp16", "fp32"])
+def test_graph_replays_match_eager(torch, prec):
     # the first call runs eagerly, later calls replay a captured graph; eager
     # work and synchronisations sit between the replays
     from paper_2411_17804_amd import epic
-    say("image_cadence graph replays")
-    cfg = W.make_config(4, chan_subset=[1, 2], n_time=33, n_stations=6, precision=W.FP16_SPLIT)
-    # keep only the stations the fused kernels cover (grids up to 64)
-    cfg.stations = [s for s in cfg.stations if s.nx <= 64][:4]
+    say(f"image_cadence graph replays {prec}")
+    p = W.FP16_SPLIT if prec == "fp16" else W.FP32_FFT
+    cfg = W.make_config(4, chan_subset=[1, 2], n_time=33, n_stations=8, precision=p)
+    # keep only stations the fused kernels cover: grids up to 64 for the split
+    # path, every grid size (32, 64 and 128) for FP32
+    cfg.stations = [s for s in cfg.stations if prec == "fp32" or s.nx <= 64][:4]
+    if prec == "fp32":
+        assert any(s.nx == 128 for s in cfg.stations)
     volts = [W.station_volts(cfg, s) for s in range(len(cfg.stations))]
     common, stations = station_objects(cfg, [to_device_volts(v) for v in volts])
     epic.image_cadence(common, stations)
@@ -294,6 +300,33 @@ def test_graph_replays_match_eager(torch):
         torch.cuda.synchronize()
         for a, b in zip(ref, stations):
             assert torch.equal(a, b.image), f"replay {rep} differs from the eager result"
+
+
+def test_fused128_box_batches(torch, monkeypatch):
+    # a box buffer of 3 MB holds one (station, channel) pair of 128 x 128
+    # footprint boxes per time block, so the three channels run as three
+    # batches per block; images must equal the one-batch run bit for bit
+    from paper_2411_17804_amd import epic
+    say("image_cadence fp32 C3, one pair per box batch")
+    cfg = W.make_config(3, chan_subset=[7, 100, 201], n_time=40, precision=W.FP32_FFT)
+    volts = [W.station_volts(cfg, 0)]
+    common, stations = station_objects(cfg, [to_device_volts(volts[0])])
+    epic.cache_clear()
+    epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    one = stations[0].image.clone()
+    err = oracle.image_error(to_complex(one), oracle_image(cfg, 0, volts[0]), 2)
+    say(f"  worst error {err.max():.2e}")
+    assert err.max() <= FP32_TOL
+    monkeypatch.setenv("EPIC_BOX_BUDGET_MB", "3")
+    epic.cache_clear()
+    stations[0].image.fill_(float("nan"))
+    for rep in range(3):                         # eager, then graph replays
+        epic.image_cadence(common, stations)
+        torch.cuda.synchronize()
+        assert torch.equal(one, stations[0].image), f"call {rep} differs"
+    monkeypatch.delenv("EPIC_BOX_BUDGET_MB")
+    epic.cache_clear()
 
 
 def test_autotune_then_cadence(torch, tmp_path, monkeypatch):
