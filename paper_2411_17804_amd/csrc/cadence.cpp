@@ -167,7 +167,8 @@ void classify(const epic_common *c, const epic_station *st, int n, const PlanHan
         const bool square = st[i].nx == st[i].ny && st[i].nx <= 64;
         int path = -1, tiles = 0;
         if (st[i].nx == st[i].ny && c->precision == EPIC_FP32_FFT &&
-            fused128_supported(st[i].nx, sd.max_bw, sd.max_bh, sd.n_elem, c->n_pol)) {
+            fused128_supported(st[i].nx, sd.max_bw, sd.max_bh, sd.n_elem, c->n_pol, c->volt_type,
+                               sd.ktaps, sd.max_cell_taps)) {
             path = kPathFft128;
         } else if (square && c->precision == EPIC_FP32_FFT) {
             path = kPathFft;

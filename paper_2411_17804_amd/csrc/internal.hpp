@@ -178,7 +178,8 @@ bool fused_fft_supported(const FusedBatch &b, int n_pol, int volt_type);
 // of the batch (items: station index, channel, 0, box offset in float2) into
 // footprint boxes [t][pol][max_bh][max_bw]; launch_fused_fft128_partials
 // transforms them and writes the block's partial sums (one item per pair).
-bool fused128_supported(int n, int max_bw, int max_bh, int n_elem, int n_pol);
+bool fused128_supported(int n, int max_bw, int max_bh, int n_elem, int n_pol, int volt_type,
+                        int ktaps, int max_cell_taps);
 epic_status launch_grid_box(const FusedBatch &b, int n_pol, int n_time, int volt_type, int chunk,
                             int block, float2 *boxes, hipStream_t stream);
 epic_status launch_fused_fft128_partials(const FusedBatch &b, int n_pol, int n_time, int chunk,

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(FusedShape<N>::BLOCK) void k_fused_fft(const Statio
     const int t_begin = ck * chunk;
     const int t_end = min(n_time, t_begin + chunk);
     const ChanPlan cp = sd.chan[c];
-    const int32_t *cs = sd.cell_start + cp.cell_off;
+    const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
     const Tap *taps = sd.taps + cp.tap_off;
 
     for (int i = threadIdx.x; i < N; i += BLOCK) tw[i] = twg[i];
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(FusedShape<N>::BLOCK) void k_fused_fft(const Statio
                 const int cell = ry * cp.bw + bx;
                 const int k1 = cs[cell + 1];
                 for (int k = cs[cell]; k < k1; ++k) {
-                    const Tap tp = taps[k];
+                    const Tap tp = gload<Tap>(taps, k);
                     float2 e[NP];
                     load_volt<NP, VT>(sd.volts, vrow + tp.elem, e);
 #pragma unroll
@@ -190,11 +190,11 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(const StationDev 
     // packed as cell << 20 | count << 16 | first tap
     uint32_t job[kFused64Rounds];
     {
-        const int32_t *cs = sd.cell_start + cp.cell_off;
-        const int32_t *ord = sd.cell_order + cp.cell_off;
+        const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
+        const gptr<int32_t> ord = global_ptr<int32_t>(sd.cell_order) + cp.cell_off;
         const Tap *taps = sd.taps + cp.tap_off;
         const int ntap = cs[ncell];
-        for (int i = tid; i < ntap; i += BLOCK) taps_l[i] = taps[i];
+        for (int i = tid; i < ntap; i += BLOCK) taps_l[i] = gload<Tap>(taps, i);
 #pragma unroll
         for (int q = 0; q < kFused64Rounds; ++q) {
             const int i = tid + q * BLOCK;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(const StationDev 
             reinterpret_cast<uint32_t *>(dst)[i] = w;
         }
     };
-    const uint32_t *vsrc = reinterpret_cast<const uint32_t *>(sd.volts) +
+    const gptr<uint32_t> vsrc = global_ptr<uint32_t>(sd.volts) +
                            static_cast<size_t>(c) * n_time * vwords;
     for (int i = tid; i < vwords; i += BLOCK) stash(0, i, vsrc[static_cast<size_t>(t_begin) * vwords + i]);
 
@@ -431,11 +431,11 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
     // gather jobs: all 1024 threads grid both pols of one cell each round
     uint32_t job[ROUNDS];
     {
-        const int32_t *cs = sd.cell_start + cp.cell_off;
-        const int32_t *ord = sd.cell_order + cp.cell_off;
+        const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
+        const gptr<int32_t> ord = global_ptr<int32_t>(sd.cell_order) + cp.cell_off;
         const Tap *taps = sd.taps + cp.tap_off;
         const int ntap = cs[ncell];
-        for (int i = tid; i < ntap; i += BLOCK) taps_l[i] = taps[i];
+        for (int i = tid; i < ntap; i += BLOCK) taps_l[i] = gload<Tap>(taps, i);
 #pragma unroll
         for (int q = 0; q < ROUNDS; ++q) {
             const int i = tid + q * BLOCK;
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
             reinterpret_cast<uint32_t *>(dst)[i] = w;
         }
     };
-    const uint32_t *vsrc = reinterpret_cast<const uint32_t *>(sd.volts) +
+    const gptr<uint32_t> vsrc = global_ptr<uint32_t>(sd.volts) +
                            static_cast<size_t>(c) * n_time * vwords;
     for (int i = tid; i < vwords; i += BLOCK) stash(0, i, vsrc[static_cast<size_t>(t_begin) * vwords + i]);
 

@@ -31,7 +31,8 @@ namespace epic {
 namespace {
 
 constexpr int kGridBoxBlock = 512;
-constexpr size_t kGridBoxLds = 64 * 1024;   // voltage staging of one gridding work-group
+constexpr int kGridBoxCells = 24;   // box cells per gridding thread (boxes up to 12288 cells)
+constexpr int kGridBoxPre = 16;     // raw voltage words per thread and sample
 constexpr int kF128Block = 512;
 constexpr size_t kF128Lds = sizeof(float2) * (128 * 128 + 8 * kF128Block);   // plane + pol X hold of CB task 3
 
@@ -46,120 +47,171 @@ __device__ __forceinline__ int pl(int y, int p)
     return y * 128 + (p ^ ((p >> 3) & 7) ^ ((y & 3) << 3));
 }
 
+// LDS slot of element e in the gridding kernel's voltage staging.
+__host__ __device__ __forceinline__ int gb_slot(int e) { return e + (e >> 5); }
+
+// LDS of the gridding kernel: one sample's voltages (FP32, padded slots) plus
+// a zero element, and the channel's taps as FP32 weights and 16-bit slots.
+size_t grid_box_lds(int max_elem, int max_ktaps, int n_pol)
+{
+    const size_t ntap = static_cast<size_t>(max_elem) * max_ktaps;
+    return sizeof(float2) * static_cast<size_t>(gb_slot(max_elem) + 1) * n_pol +
+           (sizeof(float) + sizeof(uint16_t)) * ntap;
+}
+
 }  // namespace
 
-// items: (station index, channel, 0, box offset in float2) per pair; grid:
-// 8 ceil(pairs / 8) ceil(chunk / TB) work-groups; block b covers samples
-// [b chunk, min(n_time, (b + 1) chunk)).  The TB samples' voltages are first
-// copied (coalesced, converted to FP32) into LDS; then every box cell, in
-// natural order so that the tap lists and the box rows are read and written
-// contiguously, sums weight * voltage over its taps for the TB samples.
-template <int NP, int VT, int TB>
+// One work-group per (station, channel) pair and time block (items: station
+// index, channel, 0, box offset in float2); block b covers samples
+// [b chunk, min(n_time, (b + 1) chunk)).  The channel's taps are compacted
+// into LDS once (16-bit element index, FP32 weight) and each thread keeps its
+// box cells' tap ranges in registers, so per sample the gather reads only
+// LDS: the voltages of the sample, staged in LDS as FP32 while the next
+// sample's are already on their way into registers.  Box cells are written in
+// natural order, so the stores are contiguous along the box rows.
+template <int NP, int VT>
 __global__ __launch_bounds__(kGridBoxBlock) void k_grid_box(const StationDev *__restrict__ sds,
-                                                            const int4 *__restrict__ items, int n_items,
-                                                            int n_time, int chunk, int block,
+                                                            const int4 *__restrict__ items, int n_time,
+                                                            int chunk, int block, int max_ntap,
                                                             float2 *__restrict__ boxes)
 {
-    extern __shared__ float2 vl[];                        // [TB][n_elem][NP]
-    // Work-groups are dealt to the 8 XCDs round-robin; pair x + 8 k runs all
-    // its sub-blocks on XCD x, back to back, so its tap lists stay in that
-    // XCD's L2 instead of every L2 streaming every channel's taps.
-    const int nsub = (chunk + TB - 1) / TB;
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int pair = xcd + 8 * (slot / nsub);
-    if (pair >= n_items) return;
-    const int4 item = items[pair];
-    const int sub = slot - (slot / nsub) * nsub;
+    constexpr int BLOCK = kGridBoxBlock;
+    constexpr int VW = VT == EPIC_CI8 ? 1 : 2 * NP;          // 32-bit words per element
+    extern __shared__ float2 lds[];
+    const int4 item = items[blockIdx.x];
     const StationDev sd = sds[item.x];
     const int c = item.y;
-    const int tb0 = block * chunk;
-    const int t_first = tb0 + sub * TB;
-    const int t_stop = min(min(n_time, tb0 + chunk), t_first + TB);
-    const int nts = t_stop - t_first;
-    if (nts <= 0) return;
     const int ne = sd.n_elem;
-    const size_t vrow0 = (static_cast<size_t>(c) * n_time + t_first) * ne;
-    {
-        // all loads first, then all LDS stores: the staging is one round trip
-        // to memory, not one per iteration (nts * ne * NP * 8 B <= the 64 KB
-        // staging bound, so MAXIT rounds of the work-group cover it)
-        constexpr int MAXIT = kGridBoxLds / (sizeof(float2) * NP * kGridBoxBlock);
-        float2 e[MAXIT][NP];
-#pragma unroll
-        for (int q = 0; q < MAXIT; ++q) {
-            const int i = threadIdx.x + q * kGridBoxBlock;
-            if (i < nts * ne) load_volt<NP, VT>(sd.volts, vrow0 + i, e[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < MAXIT; ++q) {
-            const int i = threadIdx.x + q * kGridBoxBlock;
-            if (i < nts * ne)
-#pragma unroll
-                for (int p = 0; p < NP; ++p) vl[i * NP + p] = e[q][p];
-        }
-    }
-    __syncthreads();
+    // element e's voltages sit at slot e + e / 32 (one pad slot every 32
+    // elements, so element strides that are multiples of 32, such as the
+    // rows of a lattice, do not all land on one LDS bank); slot(ne) is zero
+    float2 *vl = lds;                                          // [slot(ne) + 1][NP]
+    float *wl = reinterpret_cast<float *>(vl + static_cast<size_t>(gb_slot(ne) + 1) * NP);   // [ntap]
+    uint16_t *el = reinterpret_cast<uint16_t *>(wl + max_ntap);                 // [ntap]
     const ChanPlan cp = sd.chan[c];
-    const int32_t *cs = sd.cell_start + cp.cell_off;
+    const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
     const Tap *taps = sd.taps + cp.tap_off;
-    const size_t plane = static_cast<size_t>(sd.max_bh) * sd.max_bw;
-    float2 *out = boxes + item.w + static_cast<size_t>(t_first - tb0) * NP * plane;
     const int ncell = cp.bw * cp.bh;
-    // two cells per thread at a time and taps in groups of four, so that
-    // several independent tap loads are in flight (padding taps weigh 0)
-    for (int i0 = threadIdx.x; i0 < ncell; i0 += 2 * kGridBoxBlock) {
-        int kb[2], ke[2];
+    const int ntap = cs[ncell];
+    for (int i = threadIdx.x; i < ntap; i += BLOCK) {
+        const Tap tp = gload<Tap>(taps, i);
+        wl[i] = tp.w;
+        el[i] = static_cast<uint16_t>(gb_slot(tp.elem));
+    }
+    if (threadIdx.x < NP) vl[gb_slot(ne) * NP + threadIdx.x] = make_float2(0.f, 0.f);
+    // this thread's cells i = tid + BLOCK q (q < nq): first tap << 5 | tap
+    // count, and the cell's offset in the box plane, two 16-bit offsets a word
+    const int nq = ncell > static_cast<int>(threadIdx.x) ? (ncell - 1 - static_cast<int>(threadIdx.x)) / BLOCK + 1 : 0;
+    uint32_t job[kGridBoxCells];
+    uint32_t boff[kGridBoxCells / 2];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int i = i0 + u * kGridBoxBlock;
-            kb[u] = i < ncell ? cs[i] : 0;
-            ke[u] = i < ncell ? cs[i + 1] : 0;
+    for (int q = 0; q < kGridBoxCells; ++q) {
+        const int i = threadIdx.x + q * BLOCK;
+        uint32_t off = 0;
+        job[q] = 0;
+        if (q < nq) {
+            const int k0 = cs[i];
+            job[q] = (static_cast<uint32_t>(k0) << 5) | static_cast<uint32_t>(cs[i + 1] - k0);
+            const int by = i / cp.bw;
+            off = static_cast<uint32_t>(by * sd.max_bw + (i - by * cp.bw));
         }
-        float2 acc[2][TB][NP];
+        if (q % 2 == 0) boff[q / 2] = off;
+        else boff[q / 2] |= off << 16;
+    }
+    const int tb0 = block * chunk;
+    const int t_end = min(n_time, tb0 + chunk);
+    const int plane = sd.max_bh * sd.max_bw;
+    const int vwords = ne * VW;
+    const gptr<uint32_t> vbase = global_ptr<uint32_t>(sd.volts) +
+                            (static_cast<size_t>(c) * n_time + tb0) * vwords;
+    // the words of one sample are vwords <= kGridBoxPre * BLOCK
+    uint32_t pre[kGridBoxPre];
+    auto fetch = [&](int t, int tid) {
+        const gptr<uint32_t> src = vbase + static_cast<size_t>(t - tb0) * vwords;
+        // unconditional loads (clamped index): no branches between them, so
+        // they all go out together
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int q = 0; q < kGridBoxPre; ++q) pre[q] = src[min(tid + q * BLOCK, vwords - 1)];
+    };
+    auto stash = [&](int tid) {
 #pragma unroll
-            for (int t = 0; t < TB; ++t)
+        for (int q = 0; q < kGridBoxPre; ++q) {
+            const int i = tid + q * BLOCK;
+            if (i < vwords) {
+                const uint32_t w = pre[q];
+                if constexpr (VT == EPIC_CI8) {
+                    // one word = one element's two complex int8 values
+                    const int d = 2 * gb_slot(i);
+                    vl[d] = make_float2(static_cast<float>(static_cast<int8_t>(w & 0xff)),
+                                        static_cast<float>(static_cast<int8_t>((w >> 8) & 0xff)));
+                    vl[d + 1] = make_float2(static_cast<float>(static_cast<int8_t>((w >> 16) & 0xff)),
+                                            static_cast<float>(static_cast<int8_t>((w >> 24) & 0xff)));
+                } else {
+                    // VW words per element
+                    reinterpret_cast<uint32_t *>(vl)[gb_slot(i / VW) * VW + i % VW] = w;
+                }
+            }
+        }
+    };
+    if (tb0 < t_end) fetch(tb0, threadIdx.x);
+    for (int t = tb0; t < t_end; ++t) {
+        // an opaque copy of the thread index keeps the compiler from holding
+        // every unrolled address live across the sample loop
+        int tid;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(static_cast<int>(threadIdx.x)));
+        __syncthreads();          // previous sample's gather done (and taps written)
+        stash(tid);
+        __syncthreads();
+        if (t + 1 < t_end) fetch(t + 1, tid);
+        float2 *out = boxes + item.w + static_cast<size_t>(t - tb0) * NP * plane;
+        // cells in groups of G with the tap index outermost, so the G cells'
+        // LDS reads are independent of each other and overlap
+        constexpr int G = 4;
 #pragma unroll
-                for (int p = 0; p < NP; ++p) acc[u][t][p] = make_float2(0.f, 0.f);
-        const int rounds = max(ke[0] - kb[0], ke[1] - kb[1]);
-        for (int k = 0; k < rounds; k += 4) {
-            Tap tq[2][4];
+        for (int g0 = 0; g0 < kGridBoxCells; g0 += G) {
+            if (g0 < nq) {
+                int k0[G], kn[G], kmax = 0;
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+                for (int u = 0; u < G; ++u) {
+                    k0[u] = static_cast<int>(job[g0 + u] >> 5);
+                    kn[u] = g0 + u < nq ? static_cast<int>(job[g0 + u] & 31) : 0;
+                    kmax = max(kmax, kn[u]);
+                }
+                float2 a[G][NP];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int kk = kb[u] + k + q;
-                    tq[u][q] = kk < ke[u] ? taps[kk] : Tap{0, 0.f};
+                for (int u = 0; u < G; ++u)
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) a[u][p] = make_float2(0.f, 0.f);
+                // branch-free: a cell past its last tap reads tap 0 and the
+                // zero voltage slot (element ne), adding w * 0
+                for (int s = 0; s < kmax; ++s) {
+                    float w[G];
+                    int e[G];
+#pragma unroll
+                    for (int u = 0; u < G; ++u) {
+                        const bool ok = s < kn[u];
+                        const int kk = ok ? k0[u] + s : 0;
+                        w[u] = wl[kk];
+                        e[u] = ok ? static_cast<int>(el[kk]) : gb_slot(ne);
+                    }
+#pragma unroll
+                    for (int u = 0; u < G; ++u)
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) {
+                            const float2 v = vl[e[u] * NP + p];
+                            a[u][p].x = fmaf(w[u], v.x, a[u][p].x);
+                            a[u][p].y = fmaf(w[u], v.y, a[u][p].y);
+                        }
                 }
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+                for (int u = 0; u < G; ++u) {
+                    if (g0 + u < nq) {
+                        const int q = g0 + u;
+                        const int o = static_cast<int>((boff[q / 2] >> (16 * (q % 2))) & 0xffff);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int t = 0; t < TB; ++t) {
-                        if (t < nts) {
-#pragma unroll
-                            for (int p = 0; p < NP; ++p) {
-                                const float2 e = vl[(t * ne + tq[u][q].elem) * NP + p];
-                                acc[u][t][p].x = fmaf(tq[u][q].w, e.x, acc[u][t][p].x);
-                                acc[u][t][p].y = fmaf(tq[u][q].w, e.y, acc[u][t][p].y);
-                            }
-                        }
+                        for (int p = 0; p < NP; ++p) out[p * plane + o] = a[u][p];
                     }
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int i = i0 + u * kGridBoxBlock;
-            if (i < ncell) {
-                const int by = i / cp.bw, bx = i - by * cp.bw;
-                const size_t o = static_cast<size_t>(by) * sd.max_bw + bx;
-#pragma unroll
-                for (int t = 0; t < TB; ++t)
-                    if (t < nts)
-#pragma unroll
-                        for (int p = 0; p < NP; ++p)
-                            out[(static_cast<size_t>(t) * NP + p) * plane + o] = acc[u][t][p];
+                }
             }
         }
     }
@@ -328,54 +380,41 @@ __global__ __launch_bounds__(kF128Block) void k_fused_fft128(const StationDev *_
     }
 }
 
-bool fused128_supported(int n, int max_bw, int max_bh, int n_elem, int n_pol)
+bool fused128_supported(int n, int max_bw, int max_bh, int n_elem, int n_pol, int volt_type,
+                        int ktaps, int max_cell_taps)
 {
-    // one sample's voltages must fit the gridding kernel's LDS staging
-    return n == 128 && max_bw <= 128 && max_bh <= 128 &&
-           sizeof(float2) * static_cast<size_t>(n_elem) * n_pol <= kGridBoxLds;
-}
-
-// Samples per gridding work-group: as many (up to 8) as fit 64 KB of LDS.
-int grid_box_tb(int max_elem, int n_pol)
-{
-    const size_t per = sizeof(float2) * static_cast<size_t>(max_elem) * n_pol;
-    return per * 8 <= kGridBoxLds ? 8 : per * 4 <= kGridBoxLds ? 4 : per * 2 <= kGridBoxLds ? 2 : 1;
-}
-
-template <int NP, int VT>
-epic_status launch_grid_box_tb(const FusedBatch &b, int tb, int n_time, int chunk, int block,
-                               float2 *boxes, hipStream_t stream)
-{
-    auto pick = [&](auto k, int TB) -> epic_status {
-        const int nsub = (chunk + TB - 1) / TB;
-        const size_t lds = sizeof(float2) * static_cast<size_t>(TB) * b.max_elem * NP;
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           static_cast<int>(lds));
-        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-        const int per_xcd = (b.n_items + 7) / 8;
-        hipLaunchKernelGGL(k, dim3(8 * per_xcd * nsub), dim3(kGridBoxBlock), lds, stream, b.sds, b.items,
-                           b.n_items, n_time, chunk, block, boxes);
-        EPIC_HIP_TRY(hipGetLastError());
-        return EPIC_OK;
-    };
-    switch (tb) {
-    case 8: return pick(k_grid_box<NP, VT, 8>, 8);
-    case 4: return pick(k_grid_box<NP, VT, 4>, 4);
-    case 2: return pick(k_grid_box<NP, VT, 2>, 2);
-    default: return pick(k_grid_box<NP, VT, 1>, 1);
-    }
+    // the gridding kernel keeps a channel's taps and one sample's voltages in
+    // LDS, each thread's cells in registers and one sample's raw voltage
+    // words in registers
+    const int vw = volt_type == EPIC_CI8 ? 1 : 2 * n_pol;
+    const int64_t ntap = static_cast<int64_t>(n_elem) * ktaps;
+    return n == 128 && max_bw <= 128 && max_bh <= 128 && gb_slot(n_elem) < 65535 &&
+           max_bw * max_bh <= kGridBoxCells * kGridBoxBlock && max_cell_taps <= 31 &&
+           ntap < (1 << 26) && static_cast<int64_t>(n_elem) * vw <= kGridBoxPre * kGridBoxBlock &&
+           (volt_type != EPIC_CI8 || n_pol == 2) &&
+           grid_box_lds(n_elem, ktaps, n_pol) <= 160 * 1024;
 }
 
 epic_status launch_grid_box(const FusedBatch &b, int n_pol, int n_time, int volt_type, int chunk,
                             int block, float2 *boxes, hipStream_t stream)
 {
-    const int tb = grid_box_tb(b.max_elem, n_pol);
+    const int max_ntap = b.max_elem * b.max_ktaps;
+    const size_t lds = grid_box_lds(b.max_elem, b.max_ktaps, n_pol);
+    auto go = [&](auto k) -> epic_status {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(lds));
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+        hipLaunchKernelGGL(k, dim3(b.n_items), dim3(kGridBoxBlock), lds, stream, b.sds, b.items,
+                           n_time, chunk, block, max_ntap, boxes);
+        EPIC_HIP_TRY(hipGetLastError());
+        return EPIC_OK;
+    };
     KernelTimer timer("grid_box", stream);
-    if (n_pol == 2 && volt_type == EPIC_CI8) return launch_grid_box_tb<2, EPIC_CI8>(b, tb, n_time, chunk, block, boxes, stream);
-    if (n_pol == 2) return launch_grid_box_tb<2, EPIC_CF32>(b, tb, n_time, chunk, block, boxes, stream);
-    if (volt_type == EPIC_CI8) return launch_grid_box_tb<1, EPIC_CI8>(b, tb, n_time, chunk, block, boxes, stream);
-    return launch_grid_box_tb<1, EPIC_CF32>(b, tb, n_time, chunk, block, boxes, stream);
+    if (n_pol == 2 && volt_type == EPIC_CI8) return go(k_grid_box<2, EPIC_CI8>);
+    if (n_pol == 2) return go(k_grid_box<2, EPIC_CF32>);
+    if (volt_type == EPIC_CI8) return go(k_grid_box<1, EPIC_CI8>);
+    return go(k_grid_box<1, EPIC_CF32>);
 }
 
 epic_status launch_fused_fft128_partials(const FusedBatch &b, int n_pol, int n_time, int chunk,

@@ -27,6 +27,7 @@
 #include <algorithm>
 
 #include "internal.hpp"
+#include "volts.hpp"
 #include "mfma_split.hpp"
 
 namespace epic {
@@ -117,8 +118,8 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
     }
     // gather jobs (cells in descending tap-count order): cell << 20 | count << 16 | first tap
     {
-        const int32_t *cs = sd.cell_start + cp.cell_off;
-        const int32_t *ord = sd.cell_order + cp.cell_off;
+        const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
+        const gptr<int32_t> ord = global_ptr<int32_t>(sd.cell_order) + cp.cell_off;
         for (int i = tid; i < ncell; i += BLOCK) {
             const int cell = ord[i];
             const int k0 = cs[cell];
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
 
     // voltages of a sample as float pairs in vf[buffer]; returns the largest
     // |component| this thread stored
-    const uint32_t *vsrc = reinterpret_cast<const uint32_t *>(sd.volts) +
+    const gptr<uint32_t> vsrc = global_ptr<uint32_t>(sd.volts) +
                            static_cast<size_t>(c) * n_time * vwords;
     auto stash = [&](int buffer, int i, uint32_t w) -> float {
         uint32_t *dst = vf + buffer * NP * VW * max_elem;
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
                     for (int p = 0; p < NP; ++p) a[p] = make_float2(0.f, 0.f);
                     for (int s = 0; s < kn; ++s) {
-                        const Tap tp = taps[k0 + s];
+                        const Tap tp = gload<Tap>(taps, k0 + s);
 #pragma unroll
                         for (int p = 0; p < NP; ++p) {
                             const float2 e = volt(vcur, tp.elem * NP + p);

@@ -312,8 +312,13 @@ def test_fused128_box_batches(torch, monkeypatch):
     volts = [W.station_volts(cfg, 0)]
     common, stations = station_objects(cfg, [to_device_volts(volts[0])])
     epic.cache_clear()
+    epic.timing_reset()
+    epic.timing_enable(True)
     epic.image_cadence(common, stations)
     torch.cuda.synchronize()
+    epic.timing_enable(False)
+    used = epic.timing_report()
+    assert "fused_fft128_cadence" in used and "grid_box" in used, used   # the fused path ran
     one = stations[0].image.clone()
     err = oracle.image_error(to_complex(one), oracle_image(cfg, 0, volts[0]), 2)
     say(f"  worst error {err.max():.2e}")
