@@ -383,8 +383,8 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(const StationDev 
 // radix-8 butterfly of one pol per thread and pass).  That halves the
 // registers of a thread and doubles the waves that hide LDS latency.  After
 // the last column pass both halves leave their pixels in LDS and each picks up
-// the other pol's, so that each forms and accumulates two of the four
-// products.  A wave's row tasks are 8 adjacent rows aligned to 8 (the swizzle
+// the other pol's, so that each forms and accumulates two of the four real
+// product components.  A wave's row tasks are 8 adjacent rows aligned to 8 (the swizzle
 // keeps those conflict-free too), so waves whose rows miss the footprint box
 // skip the row passes.
 constexpr int kFused64x2Block = 1024;
@@ -409,7 +409,9 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
     Tap *taps_l = reinterpret_cast<Tap *>(vf + 2 * NP * max_elem);
 
     const int tid = threadIdx.x;
-    const int pol = tid >> 9, tp5 = tid & 511;          // pol of this thread, index within it
+    // pol of this thread (the same across a wave, which the compiler learns
+    // from readfirstlane: pol-dependent choices become scalar branches)
+    const int pol = __builtin_amdgcn_readfirstlane(tid >> 9), tp5 = tid & 511;
     const int lane = tp5 & 63, wv = tp5 >> 6;
     const int j = lane & 7;
     const int y = 8 * wv + (lane >> 3);                  // row task: a wave owns 8 adjacent rows
@@ -568,42 +570,46 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
         __syncthreads();
         // C2: second pass along y; pixel (ky = j + 8k, kx) of this thread's pol.
         // A thread reads and rewrites only its own eight addresses, so the
-        // result goes back in place without a barrier in between.
+        // result goes back in place without a barrier in between.  Pol X
+        // stores -i F^X = (Im, -Re), pol Y stores F^Y as it is, so that one
+        // formula, Re(F w*) with w the other pol's stored value, gives Re XY
+        // on the pol-X threads and Im XY on the pol-Y threads.
         float2 v[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) v[r] = plane[cm[r] + 512 * r];
 #pragma unroll
         for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], tw[r]);
         Dft<8>::run(v);
+        if (pol == 0) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) plane[cm[k] + 512 * k] = v[k];
+            for (int k = 0; k < 8; ++k) plane[cm[k] + 512 * k] = make_float2(v[k].y, -v[k].x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) plane[cm[k] + 512 * k] = v[k];
+        }
         __syncthreads();
-        // products (Eq. 2): pol-X threads keep XX and Re XY, pol-Y threads
-        // Im XY and YY.  The next sample writes the planes only after the
-        // barrier that follows its gather, so the other pol's plane is stable.
+        // products (Eq. 2): |F|^2 (XX or YY) and the cross term (Re XY or
+        // Im XY).  The next sample writes the planes only after the barrier
+        // that follows its gather, so the other pol's plane is stable here.
         {
             const float2 *other = buf + (pol ^ 1) * PLANE;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const float2 w = other[cm[k] + 512 * k];
-                const float2 fx = pol == 0 ? v[k] : w, fy = pol == 0 ? w : v[k];
-                if (pol == 0) {
-                    acc[k][0] = fmaf(fx.x, fx.x, fmaf(fx.y, fx.y, acc[k][0]));
-                    acc[k][1] = fmaf(fx.x, fy.x, fmaf(fx.y, fy.y, acc[k][1]));
-                } else {
-                    acc[k][0] = fmaf(fx.y, fy.x, fmaf(-fx.x, fy.y, acc[k][0]));
-                    acc[k][1] = fmaf(fy.x, fy.x, fmaf(fy.y, fy.y, acc[k][1]));
-                }
+                acc[k][0] = fmaf(v[k].x, v[k].x, fmaf(v[k].y, v[k].y, acc[k][0]));
+                acc[k][1] = fmaf(v[k].x, w.x, fmaf(v[k].y, w.y, acc[k][1]));
             }
         }
         cur ^= 1;
     }
-    float *out = partials + sd.part_off + (static_cast<size_t>(c) * n_chunks + ck) * 4 * PLANE +
-                 2 * pol * PLANE;
+    // components XX, Re XY, Im XY, YY: pol X holds (XX, Re XY), pol Y (YY, Im XY)
+    float *out = partials + sd.part_off + (static_cast<size_t>(c) * n_chunks + ck) * 4 * PLANE;
+    float *out_sq = out + (pol == 0 ? 0 : 3) * PLANE, *out_x = out + (pol == 0 ? 1 : 2) * PLANE;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) out[q * PLANE + (j + 8 * k) * 64 + kx] = acc[k][q];
+    for (int k = 0; k < 8; ++k) {
+        out_sq[(j + 8 * k) * 64 + kx] = acc[k][0];
+        out_x[(j + 8 * k) * 64 + kx] = acc[k][1];
+    }
 }
 
 namespace {
