@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
                                                                    int n_time, int chunk,
                                                                    float *__restrict__ partials,
                                                                    const float2 *__restrict__ twg,
-                                                                   int max_elem, int max_cells)
+                                                                   int max_elem, int gb_rows)
 {
     constexpr int NP = 2;
     constexpr int PLANE = 64 * 64;
@@ -404,8 +404,11 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
     constexpr int PREFETCH = kFused64Prefetch * kFused64Block / BLOCK;
     extern __shared__ float2 lds[];
     float2 *buf = lds;                                   // [2][PLANE], swizzled
-    float2 *gb = buf + NP * PLANE;                       // [2][max_cells] gathered box
-    float2 *vf = gb + NP * max_cells;                    // [2][max_elem][2] voltages
+    // gathered box rows at pitch 68 (the 4 pad words keep the row pass's
+    // reads of 8 adjacent rows on distinct banks), zero outside the box's columns
+    constexpr int GP = 68;
+    float2 *gb = buf + NP * PLANE;                       // [2][gb_rows][GP]
+    float2 *vf = gb + NP * gb_rows * GP;                 // [2][max_elem][2] voltages
     Tap *taps_l = reinterpret_cast<Tap *>(vf + 2 * NP * max_elem);
 
     const int tid = threadIdx.x;
@@ -428,7 +431,7 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
     const bool row_active = yl >= 0 && yl < cp.bh;       // waves wholly outside the box skip R1, R2
     const int ncell = cp.bw * cp.bh;
     float2 *plane = buf + pol * PLANE;
-    const float2 *gpl = gb + pol * max_cells;
+    const float2 *gpl = gb + pol * gb_rows * GP;
 
     // gather jobs: all 1024 threads grid both pols of one cell each round
     uint32_t job[ROUNDS];
@@ -445,10 +448,13 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
             if (i < ncell) {
                 const int cell = ord[i];
                 const int k0 = cs[cell];
-                job[q] = (static_cast<uint32_t>(cell) << 20) |
+                const int by = cell / cp.bw;
+                const int pos = by * 64 + cp.x0 + (cell - by * cp.bw);   // row by, column x (12 bits)
+                job[q] = (static_cast<uint32_t>(pos) << 20) |
                          (static_cast<uint32_t>(cs[cell + 1] - k0) << 16) | static_cast<uint32_t>(k0);
             }
         }
+        for (int i = tid; i < NP * gb_rows * GP; i += BLOCK) gb[i] = make_float2(0.f, 0.f);
     }
 
     float2 tw[8];
@@ -515,8 +521,9 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
                         a1.x = fmaf(tp.w, e1.x, a1.x);
                         a1.y = fmaf(tp.w, e1.y, a1.y);
                     }
-                    gb[cell] = a0;
-                    gb[max_cells + cell] = a1;
+                    const int at = cell + ((cell >> 6) << 2);   // row * GP + column
+                    gb[at] = a0;
+                    gb[gb_rows * GP + at] = a1;
                 }
             }
         }
@@ -532,10 +539,7 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
         if (row_active) {
             float2 v[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int bx = j + 8 * m - cp.x0;
-                v[m] = (bx >= 0 && bx < cp.bw) ? gpl[yl * cp.bw + bx] : make_float2(0.f, 0.f);
-            }
+            for (int m = 0; m < 8; ++m) v[m] = gpl[yl * GP + j + 8 * m];
             Dft<8>::run(v);
 #pragma unroll
             for (int k = 0; k < 8; ++k) plane[bt ^ k] = v[k];
@@ -615,8 +619,19 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
 namespace {
 
 // the 64 x 64 register-resident kernel needs its LDS layout to fit
+// LDS of the two-pol 64 x 64 kernel: the planes, the gathered box as
+// 64-wide rows at pitch 68, two voltage buffers, the channel's taps.
+size_t fused64x2_lds_bytes(int max_elem, int ktaps, int max_side)
+{
+    return sizeof(float2) * 2 * 64 * 64 + sizeof(float2) * 2 * 68 * static_cast<size_t>(max_side) +
+           sizeof(float2) * 2 * 2 * static_cast<size_t>(max_elem) +
+           sizeof(Tap) * static_cast<size_t>(max_elem) * ktaps;
+}
+
 bool fft64_fits(const FusedBatch &b, int n_pol, int volt_type)
 {
+    if (n_pol == 2 && (b.max_side > 64 || fused64x2_lds_bytes(b.max_elem, b.max_ktaps, b.max_side) > kLdsBytes))
+        return false;
     const int64_t vbytes = static_cast<int64_t>(b.max_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8);
     return b.n == 64 && vbytes % 4 == 0 && vbytes / 4 <= kFused64Prefetch * kFused64Block &&
            b.max_cells <= kFused64Rounds * kFused64Block && b.max_cell_taps <= 15 &&
@@ -646,14 +661,14 @@ epic_status run64x2(const FusedBatch &b, int n_time, int chunk, float *partials,
                     hipStream_t stream)
 {
     auto k = k_fused_fft64x2<VT>;
-    const size_t bytes = fused64_lds_bytes(2, b.max_elem, b.max_ktaps, b.max_cells);
+    const size_t bytes = fused64x2_lds_bytes(b.max_elem, b.max_ktaps, b.max_side);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(bytes));
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
     KernelTimer timer("fused_fft_cadence", stream);
     hipLaunchKernelGGL(k, dim3(b.n_items), dim3(kFused64x2Block), bytes, stream, b.sds, b.items,
-                       n_time, chunk, partials, tw, b.max_elem, b.max_cells);
+                       n_time, chunk, partials, tw, b.max_elem, b.max_side);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }
