@@ -52,9 +52,11 @@ KERNEL_SOURCES = {
 }
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, chunk):
     """HBM bytes per launch from profiles/<kernel>_<workload>_hbm_bytes.md, or
-    None if there is no summary or the kernel changed since it was taken."""
+    None if there is no summary, the kernel changed since it was taken, or it
+    was taken at another time-chunk length (the partial-sum writes scale with
+    1/chunk)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_bytes.md")
@@ -63,7 +65,8 @@ def measured_traffic(kernel: str, workload: str):
     text = open(path).read()
     m_b = re.search(r"traffic_bytes_per_launch: (\d+)", text)
     m_h = re.search(r"source_sha256_16: ([0-9a-f]+)", text)
-    if not (m_b and m_h):
+    m_c = re.search(r"chunk: (\d+)", text)
+    if not (m_b and m_h and m_c) or chunk is None or int(m_c.group(1)) != chunk:
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
@@ -183,10 +186,24 @@ def main():
     log(f"inputs generated and resident in HBM ({cfg.volt_bytes() / 1e9:.2f} GB) "
         f"in {time.time() - t_gen:.1f} s")
 
+    # the tuned chunk lengths come back through the library's tune-cache file
+    # ("class chunk" lines); without autotuning every class uses 32
+    tune_file = os.environ.get("EPIC_TUNE_CACHE")
+    if not tune_file:
+        import tempfile
+        tune_file = os.path.join(tempfile.mkdtemp(prefix="epic_bench_"), "tune.txt")
+        os.environ["EPIC_TUNE_CACHE"] = tune_file
+    chunks = {}
     if not args.no_autotune:
         t_tune = time.time()
         epic.autotune(common, stations)
         log(f"autotune done in {time.time() - t_tune:.1f} s")
+        if os.path.exists(tune_file):
+            for line in open(tune_file):
+                parts = line.split()
+                if len(parts) == 2:
+                    chunks[parts[0]] = int(parts[1])
+        log(f"tuned chunks {chunks}")
     for i in range(args.warmup):
         epic.image_cadence(common, stations)
     torch.cuda.synchronize()
@@ -216,6 +233,10 @@ def main():
 
     # dominant kernel and its roofline
     dom_name, (dom_count, dom_ms) = max(kern.items(), key=lambda kv: kv[1][1])
+    prefix = {"fused_fft_cadence": "fft_", "fused_dft_cadence": "dft_",
+              "fused_fft128_cadence": "fft128_"}.get(dom_name)
+    cls = sorted(v for k, v in chunks.items() if prefix and k.startswith(prefix))
+    dom_chunk = cls[0] if len(set(cls)) == 1 else (32 if args.no_autotune else None)
     dom_avg_ms = dom_ms / dom_count
     launches_per_step = dom_count / args.steps
     st0 = cfg.stations[0]
@@ -234,9 +255,9 @@ def main():
         roof = {"bound": "alu", "achieved": round(achieved, 3),
                 "peak": round(PEAK_FP32_VALU_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
-                "traffic": measured_traffic(dom_name, f"C{cfg.index}")
+                "traffic": measured_traffic(dom_name, f"C{cfg.index}", dom_chunk)
                 if cfg.n_chan == W.make_config(cfg.index).n_chan and args.n_time is None else None,
-                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4),
+                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": dom_chunk,
                 "flop_per_pixel_sample": round(flop_px, 2)}
     else:
         fl = split_mfma_flops(cfg) if dom_name == "fused_dft_cadence" else None
@@ -244,9 +265,9 @@ def main():
         roof = {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
                 "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP16_MFMA_TFLOPS, 4) if achieved else None,
-                "traffic": measured_traffic(dom_name, f"C{cfg.index}")
+                "traffic": measured_traffic(dom_name, f"C{cfg.index}", dom_chunk)
                 if cfg.n_chan == W.make_config(cfg.index).n_chan and args.n_time is None else None,
-                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4),
+                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": dom_chunk,
                 "flop_per_step": fl}
 
     out = {

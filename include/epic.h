@@ -162,10 +162,10 @@ epic_status image_cadence(const epic_common *common, const epic_station *station
 
 /*
  * Tile tuning (auxiliary).  image_cadence runs every station whose grid is
- * square and at most 64 x 64 in fused kernels that process one (station,
- * channel, time chunk) item per work-group; the chunk length (16, 32 or 64
- * samples) trades launch width against per-item setup and partial-sum
- * traffic.  epic_autotune runs each fused kernel class of this call with each
+ * square and at most 64 x 64 (and, in FP32, every 128 x 128 one) in fused
+ * kernels that process one (station, channel, time chunk) item per
+ * work-group; the chunk length (16, 32, 64 or 128 samples) trades launch
+ * width against per-item setup and partial-sum traffic.  epic_autotune runs each fused kernel class of this call with each
  * candidate on the caller's buffers (it overwrites station images), keeps the
  * fastest for later image_cadence calls of the same class (grid size,
  * footprint tiles, pols, voltage type, precision) and, if the environment

@@ -18,9 +18,10 @@
 // station is fused the whole cadence is captured into a hipGraph on first use
 // and replayed afterwards.
 //
-// The time-chunk length of each class is a tile parameter: epic_autotune times
-// the candidates on the caller's data and keeps the fastest, in memory and,
-// if EPIC_TUNE_CACHE names a file, on disk ("key chunk" lines).
+// The time-chunk length of each class (16, 32, 64 or 128 samples) is a tile
+// parameter: epic_autotune times the candidates on the caller's data and keeps
+// the fastest, in memory and, if EPIC_TUNE_CACHE names a file, on disk
+// ("key chunk" lines).
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -52,7 +53,10 @@ size_t box_budget()
     return mb > 0 ? static_cast<size_t>(mb) << 20 : size_t(2) << 30;
 }
 constexpr int kDefaultChunk = 32;
-const int kChunkCandidates[] = {16, 32, 64};
+// Chunk lengths the autotuner tries.  Each chunk is a plain FP32 sum (its
+// rounding error grows at most linearly, 128 * 2^-24 < 1e-5 relative), and
+// the chunks are then added with compensation.
+const int kChunkCandidates[] = {16, 32, 64, 128};
 
 struct Group {
     int path = kPathFft;
@@ -108,7 +112,7 @@ void load_tune_file()
     std::string key;
     int chunk = 0;
     while (f >> key >> chunk)
-        if (chunk == 16 || chunk == 32 || chunk == 64) g_tuned[key] = chunk;
+        if (chunk == 16 || chunk == 32 || chunk == 64 || chunk == 128) g_tuned[key] = chunk;
 }
 
 void save_tune_file()
