@@ -19,8 +19,9 @@
 //      through LDS;
 //   4. stage 2 (transform along x, pruned to the footprint columns):
 //        Z[k_y][k_x] = sum_x Y[k_y][x] F[k_x][x0 + x]
-//      with B fragments built from the channel's DFT rows in LDS (a sign flip
-//      and a half swap turn a packed (re, im) pair into the 2x2 real block);
+//      with B fragments from the channel's DFT rows in LDS; the 2x2 real
+//      block of the complex product is formed in the A fragments (up to 3
+//      footprint tiles) or, where registers are short, in the B fragments;
 //   5. undo s1 s2 exactly, form XX, XY, YY and accumulate in registers.
 // Partial sums per chunk go to the same ordered compensated reduction as the
 // FP32 path.
@@ -283,20 +284,41 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
                     for (int i = 0; i < 4; ++i) ymax = fmaxf(ymax, fabsf(c1[mt][o][i]));
             for (int o = 32; o > 0; o >>= 1) ymax = fmaxf(ymax, __shfl_xor(ymax, o));
             const float s2 = pow2_scale(ymax);
-            vec8 a2[T][2];   // [x K-step][hi, lo]
+            // The 2x2 real block of the complex product goes into whichever
+            // operand is cheaper to rebuild.  Up to 3 footprint tiles it sits
+            // in the A fragments (built once per sample and pol): with
+            // B = (Re F, Im F) pairs as stored, A = (Re Y, -Im Y) gives the
+            // real output and A = (Im Y, Re Y) the imaginary one.  With 4
+            // tiles the extra A registers would spill, so the A fragments stay
+            // (Re Y, Im Y) and each B fragment is turned into (Re F, -Im F)
+            // and (Im F, Re F) as it is loaded.
+            constexpr bool kBlockInA = T <= 3;
+            constexpr int NA = kBlockInA ? 4 : 2;
+            vec8 a2[T][NA];   // [x K-step][re hi, re lo(, im hi, im lo)]
 #pragma unroll
             for (int mt = 0; mt < T; ++mt) {
-                u32x4_t wh, wl;
+                u32x4_t rh, rl, ih, il;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     scalar hr, lr, hi_, li;
                     split<PREC>(c1[mt][0][i] * s2, hr, lr);
                     split<PREC>(c1[mt][1][i] * s2, hi_, li);
-                    wh[i] = pack2<PREC>(hr, hi_);
-                    wl[i] = pack2<PREC>(lr, li);
+                    if constexpr (kBlockInA) {
+                        rh[i] = pack2<PREC>(hr, -hi_);
+                        rl[i] = pack2<PREC>(lr, -li);
+                        ih[i] = pack2<PREC>(hi_, hr);
+                        il[i] = pack2<PREC>(li, lr);
+                    } else {
+                        rh[i] = pack2<PREC>(hr, hi_);
+                        rl[i] = pack2<PREC>(lr, li);
+                    }
                 }
-                a2[mt][0] = __builtin_bit_cast(vec8, wh);
-                a2[mt][1] = __builtin_bit_cast(vec8, wl);
+                a2[mt][0] = __builtin_bit_cast(vec8, rh);
+                a2[mt][1] = __builtin_bit_cast(vec8, rl);
+                if constexpr (kBlockInA) {
+                    a2[mt][NA > 2 ? 2 : 0] = __builtin_bit_cast(vec8, ih);
+                    a2[mt][NA > 3 ? 3 : 1] = __builtin_bit_cast(vec8, il);
+                }
             }
 
             // 4. stage 2 per k_x tile; 5. products
@@ -310,18 +332,24 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(2
                     const int off = (16 * nt + r16) * PITCH + 16 * ks + 4 * g;
                     const u32x4_t wh = *reinterpret_cast<const u32x4_t *>(&txh[off]);
                     const u32x4_t wl = *reinterpret_cast<const u32x4_t *>(&txl[off]);
-                    u32x4_t rh, rl, ih, il;
+                    if constexpr (kBlockInA) {
+                        const vec8 bh = __builtin_bit_cast(vec8, wh), bl = __builtin_bit_cast(vec8, wl);
+                        z0 = mma3<PREC>(a2[ks][0], a2[ks][1], bh, bl, z0);
+                        z1 = mma3<PREC>(a2[ks][NA > 2 ? 2 : 0], a2[ks][NA > 3 ? 3 : 1], bh, bl, z1);
+                    } else {
+                        u32x4_t rh, rl, ih, il;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        rh[i] = neg_hi(wh[i]);
-                        rl[i] = neg_hi(wl[i]);
-                        ih[i] = swap_halves(wh[i]);
-                        il[i] = swap_halves(wl[i]);
+                        for (int i = 0; i < 4; ++i) {
+                            rh[i] = neg_hi(wh[i]);
+                            rl[i] = neg_hi(wl[i]);
+                            ih[i] = swap_halves(wh[i]);
+                            il[i] = swap_halves(wl[i]);
+                        }
+                        z0 = mma3<PREC>(a2[ks][0], a2[ks][1], __builtin_bit_cast(vec8, rh),
+                                        __builtin_bit_cast(vec8, rl), z0);
+                        z1 = mma3<PREC>(a2[ks][0], a2[ks][1], __builtin_bit_cast(vec8, ih),
+                                        __builtin_bit_cast(vec8, il), z1);
                     }
-                    z0 = mma3<PREC>(a2[ks][0], a2[ks][1], __builtin_bit_cast(vec8, rh),
-                                    __builtin_bit_cast(vec8, rl), z0);
-                    z1 = mma3<PREC>(a2[ks][0], a2[ks][1], __builtin_bit_cast(vec8, ih),
-                                    __builtin_bit_cast(vec8, il), z1);
                 }
                 // lane holds pixels (k_y = 16 wave + 4 g + i, k_x = 16 nt + r16)
                 if (p == 0) {
