@@ -30,9 +30,9 @@ namespace epic {
 
 namespace {
 
-constexpr int kGridBoxBlock = 512;
-constexpr int kGridBoxCells = 24;   // box cells per gridding thread (boxes up to 12288 cells)
-constexpr int kGridBoxPre = 16;     // raw voltage words per thread and sample
+constexpr int kGridBoxBlock = 1024;
+constexpr int kGridBoxCells = 12;   // box cells per gridding thread (boxes up to 12288 cells)
+constexpr int kGridBoxPre = 8;      // raw voltage words per thread and sample
 constexpr int kF128Block = 512;
 constexpr size_t kF128Lds = sizeof(float2) * (128 * 128 + 8 * kF128Block);   // plane + pol X hold of CB task 3
 
