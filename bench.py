@@ -363,6 +363,13 @@ def stage_rooflines(cfg, common, station, nt=64, reps=3):
     res["accumulate_power"] = {"ms": round(ms, 3), "bound": "hbm", "bytes": b,
                                "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
                                "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    # the FFT-correlator output of the accumulated images (one inverse transform
+    # per channel and product, once per cadence)
+    ms = timed(lambda: epic.image_to_visibilities(cfg.n_pol, st.nx, st.ny, cfg.n_chan, img, acc[1]))
+    b = 2 * cfg.n_chan * cfg.n_pol ** 2 * npix * 8
+    res["image_to_visibilities"] = {"ms": round(ms, 3), "bound": "hbm", "bytes": b,
+                                    "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
+                                    "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
     res["_block"] = f"{cfg.n_chan} channels x {nt} samples x {cfg.n_pol} pols of {st.nx}x{st.ny}"
     del grid, out, acc, img
     torch.cuda.empty_cache()

@@ -161,6 +161,23 @@ epic_status image_cadence(const epic_common *common, const epic_station *station
                           int32_t n_stations, hipStream_t stream);
 
 /*
+ * FFT-correlator output (Sec. 6.2: an FFT correlator obtains the visibilities
+ * by one more, inverse, transform of the polarised intensities; Eq. 4 defines
+ * the visibilities and Eq. 6 their gridding with the cross-correlated element
+ * kernels).  For every channel and product of an image_cadence output:
+ *     vis[c][q][y][x] = 1/(nx ny) sum_{ky,kx} image[c][q][ky][kx]
+ *                                            exp(-2 pi i (kx x/nx + ky y/ny)),
+ * the inverse of the transform of Eq. 3, which returns the time-averaged
+ * visibilities (autocorrelations included) gridded at the baseline cells with
+ * the kernels' cross-correlation, on the circular grid.
+ * image, vis: device cf32 [n_chan][n_pol*n_pol][ny][nx] (image == vis is
+ * allowed); n_pol 1 or 2; nx, ny powers of two in 16..256; n_chan >= 1.
+ * FP32.  Errors: EPIC_ERR_INVALID_ARG for shapes or NULL pointers.
+ */
+epic_status image_to_visibilities(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_chan,
+                                  const void *image, void *vis, hipStream_t stream);
+
+/*
  * Tile tuning (auxiliary).  image_cadence runs every station whose grid is
  * square and at most 64 x 64 (and, in FP32, every 128 x 128 one) in fused
  * kernels that process one (station, channel, time chunk) item per

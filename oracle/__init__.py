@@ -207,6 +207,48 @@ def image(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K, sigma_c
     return out
 
 
+def grid_visibilities(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K,
+                      sigma_cells, volts, lib=None):
+    """FFT-correlator output of one station written out directly, per channel.
+
+    Eq. 4: the time-averaged visibilities, autocorrelations included,
+        V_ab^{pq} = mean_t E_a^p(t) conj(E_b^q(t));
+    Eq. 6 gridding: each is placed at its baseline cell c_a - c_b with the
+    cross-correlation of the two elements' kernels (extent 2K - 1 per axis),
+        G^{pq}[j] = sum_{a,b} sum_{d1,d2} w_a(d1) w_b(d2) V_ab^{pq}
+                    [j = (c_a + d1) - (c_b + d2) mod (nx, ny)].
+    No transform is involved; on the circular grid G is the inverse transform
+    of the EPIC image.  Cells and weights come from plan().  volts as for
+    image(); returns complex128 [n_chan, n_pol*n_pol, ny, nx]."""
+    lib = lib or load()
+    if volts.dtype == np.int8:
+        v = volts[..., 0].astype(np.float64) + 1j * volts[..., 1].astype(np.float64)
+    else:
+        v = volts.astype(np.complex128)
+    n_chan, n_time, n_elem, n_pol = v.shape[:4]
+    h = (K - 1) // 2
+    out = np.zeros((n_chan, n_pol * n_pol, ny, nx), np.complex128)
+    for c in range(n_chan):
+        ix, iy, wx, wy = plan(pos_m, wavelengths_m[c], grid_spacing_wl, nx, ny, kernel_type, K,
+                              sigma_cells, lib=lib)
+        ix = ix.astype(np.int64)
+        iy = iy.astype(np.int64)
+        V = np.einsum("tap,tbq->pqab", v[c], np.conj(v[c])) / n_time
+        for d1y in range(-h, h + 1):
+            for d1x in range(-h, h + 1):
+                wa = wx[:, d1x + h] * wy[:, d1y + h]
+                for d2y in range(-h, h + 1):
+                    for d2x in range(-h, h + 1):
+                        wb = wx[:, d2x + h] * wy[:, d2y + h]
+                        cx = ((ix + d1x)[:, None] - (ix + d2x)[None, :]) % nx
+                        cy = ((iy + d1y)[:, None] - (iy + d2y)[None, :]) % ny
+                        wab = wa[:, None] * wb[None, :]
+                        for p in range(n_pol):
+                            for q in range(n_pol):
+                                np.add.at(out[c, p * n_pol + q], (cy, cx), wab * V[p, q])
+    return out
+
+
 def max_threads(lib=None) -> int:
     return (lib or load()).eo_max_threads()
 

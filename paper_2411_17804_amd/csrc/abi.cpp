@@ -241,6 +241,23 @@ epic_status accumulate_power(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_ch
                         finalize_n_time, static_cast<float2 *>(image), stream);
 }
 
+epic_status image_to_visibilities(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_chan,
+                                  const void *image, void *vis, hipStream_t stream)
+{
+    set_error("");
+    if (n_pol != 1 && n_pol != 2) return fail(EPIC_ERR_INVALID_ARG, "n_pol must be 1 or 2");
+    if (!is_pow2_grid(nx) || !is_pow2_grid(ny))
+        return fail(EPIC_ERR_INVALID_ARG, "nx, ny must be powers of two in 16..256");
+    if (n_chan < 1) return fail(EPIC_ERR_INVALID_ARG, "n_chan must be >= 1");
+    if (!image || !vis) return fail(EPIC_ERR_INVALID_ARG, "image/vis is NULL");
+    int dev = 0;
+    epic_status st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    const int64_t batch = static_cast<int64_t>(n_chan) * n_pol * n_pol;
+    return launch_fft2_f32(nx, ny, batch, static_cast<const float2 *>(image), static_cast<float2 *>(vis),
+                           dev, stream, true);
+}
+
 epic_status image_cadence(const epic_common *common, const epic_station *stations,
                           int32_t n_stations, hipStream_t stream)
 {

@@ -155,8 +155,9 @@ bool timing_on();
 epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
                         int t0, int nt, float2 *grid, hipStream_t stream);
 
+// inverse: (1/(nx ny)) sum_k x[k] exp(-2 pi i k.j / N) instead of the + sign transform
 epic_status launch_fft2_f32(int nx, int ny, int64_t batch, const float2 *in, float2 *out,
-                            int device, hipStream_t stream);
+                            int device, hipStream_t stream, bool inverse = false);
 
 epic_status launch_power(int n_pol, int npix, int n_chan, int nt, const float2 *field,
                          float2 *acc_sum, float2 *acc_comp, int finalize_n_time, float2 *image,

@@ -2,13 +2,22 @@
 // unnormalised, natural order.  Grids up to 16384 cells are transformed in
 // one pass through LDS (one work-group per batch item); larger grids take a
 // row pass and a column pass through global memory.
+//
+// With INV the kernels compute the inverse, (1/(nx ny)) sum_k x[k]
+// exp(-2 pi i k.j / N), as conj(F(conj(x))) / (nx ny): the input is
+// conjugated as it is loaded and the result conjugated and scaled as it is
+// stored, so the inverse costs no extra pass.
+#include <type_traits>
+
 #include "fft_lds.hpp"
 #include "internal.hpp"
 
 namespace epic {
 
 // Load a 2-D item into LDS (row pitch P), transform rows then columns, store.
-template <int NX, int NY, int BLOCK>
+__device__ __forceinline__ float2 conj_scaled(float2 v, float s) { return make_float2(v.x * s, -v.y * s); }
+
+template <int NX, int NY, int BLOCK, bool INV>
 __global__ __launch_bounds__(BLOCK) void k_fft2_lds(const float2 *__restrict__ in,
                                                     float2 *__restrict__ out,
                                                     const float2 *__restrict__ twx,
@@ -23,17 +32,22 @@ __global__ __launch_bounds__(BLOCK) void k_fft2_lds(const float2 *__restrict__ i
     const float2 *src = in + item * (NX * NY);
     for (int i = threadIdx.x; i < NX; i += BLOCK) tx[i] = twx[i];
     for (int i = threadIdx.x; i < NY; i += BLOCK) ty[i] = twy[i];
-    for (int i = threadIdx.x; i < NX * NY; i += BLOCK) buf[(i / NX) * P + (i % NX)] = src[i];
+    for (int i = threadIdx.x; i < NX * NY; i += BLOCK)
+        buf[(i / NX) * P + (i % NX)] = INV ? conj_scaled(src[i], 1.f) : src[i];
     __syncthreads();
     constexpr int MAXL = NX > NY ? NX : NY;
     fft_lines<NX, BLOCK, MAXL, false>(buf, LineMap{NY, 0, 0, P, 1}, NY, tx);
     fft_lines<NY, BLOCK, MAXL, false>(buf, LineMap{NX, 0, 0, 1, P}, NX, ty);
     float2 *dst = out + item * (NX * NY);
-    for (int i = threadIdx.x; i < NX * NY; i += BLOCK) dst[i] = buf[(i / NX) * P + (i % NX)];
+    constexpr float kInv = 1.f / static_cast<float>(NX * NY);   // a power of two: exact
+    for (int i = threadIdx.x; i < NX * NY; i += BLOCK) {
+        const float2 v = buf[(i / NX) * P + (i % NX)];
+        dst[i] = INV ? conj_scaled(v, kInv) : v;
+    }
 }
 
 // Row pass for large grids: ROWS consecutive rows of length NX per block.
-template <int NX, int ROWS, int BLOCK>
+template <int NX, int ROWS, int BLOCK, bool INV>
 __global__ __launch_bounds__(BLOCK) void k_fft_rows(const float2 *__restrict__ in,
                                                     float2 *__restrict__ out,
                                                     const float2 *__restrict__ tw, int64_t n_rows)
@@ -45,14 +59,15 @@ __global__ __launch_bounds__(BLOCK) void k_fft_rows(const float2 *__restrict__ i
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * ROWS;
     const int nr = static_cast<int>(min<int64_t>(ROWS, n_rows - row0));
     for (int i = threadIdx.x; i < NX; i += BLOCK) t[i] = tw[i];
-    for (int i = threadIdx.x; i < nr * NX; i += BLOCK) buf[(i / NX) * P + (i % NX)] = in[row0 * NX + i];
+    for (int i = threadIdx.x; i < nr * NX; i += BLOCK)
+        buf[(i / NX) * P + (i % NX)] = INV ? conj_scaled(in[row0 * NX + i], 1.f) : in[row0 * NX + i];
     __syncthreads();
     fft_lines<NX, BLOCK, ROWS, false>(buf, LineMap{ROWS, 0, 0, P, 1}, nr, t);
     for (int i = threadIdx.x; i < nr * NX; i += BLOCK) out[row0 * NX + i] = buf[(i / NX) * P + (i % NX)];
 }
 
 // Column pass for large grids: COLS adjacent columns (length NY) per block.
-template <int NX, int NY, int COLS, int BLOCK>
+template <int NX, int NY, int COLS, int BLOCK, bool INV>
 __global__ __launch_bounds__(BLOCK) void k_fft_cols(float2 *__restrict__ data,
                                                     const float2 *__restrict__ tw)
 {
@@ -68,7 +83,11 @@ __global__ __launch_bounds__(BLOCK) void k_fft_cols(float2 *__restrict__ data,
     for (int i = threadIdx.x; i < NY * COLS; i += BLOCK) buf[(i / COLS) * P + (i % COLS)] = base[(i / COLS) * NX + (i % COLS)];
     __syncthreads();
     fft_lines<NY, BLOCK, COLS, false>(buf, LineMap{COLS, 0, 0, 1, P}, COLS, t);
-    for (int i = threadIdx.x; i < NY * COLS; i += BLOCK) base[(i / COLS) * NX + (i % COLS)] = buf[(i / COLS) * P + (i % COLS)];
+    constexpr float kInv = 1.f / static_cast<float>(NX * NY);
+    for (int i = threadIdx.x; i < NY * COLS; i += BLOCK) {
+        const float2 v = buf[(i / COLS) * P + (i % COLS)];
+        base[(i / COLS) * NX + (i % COLS)] = INV ? conj_scaled(v, kInv) : v;
+    }
 }
 
 namespace {
@@ -83,13 +102,13 @@ epic_status set_lds(K kernel, size_t bytes)
     return EPIC_OK;
 }
 
-template <int NX, int NY>
+template <int NX, int NY, bool INV>
 epic_status run_lds(int64_t batch, const float2 *in, float2 *out, const float2 *twx,
                     const float2 *twy, hipStream_t stream)
 {
     constexpr int BLOCK = NX * NY >= 8192 ? 512 : 256;
     const size_t bytes = sizeof(float2) * (NY * (NX + 1) + NX + NY);
-    auto k = k_fft2_lds<NX, NY, BLOCK>;
+    auto k = k_fft2_lds<NX, NY, BLOCK, INV>;
     epic_status s = set_lds(k, bytes);
     if (s != EPIC_OK) return s;
     // gridDim.x is limited to 2^31-1; batches beyond that are split
@@ -103,13 +122,13 @@ epic_status run_lds(int64_t batch, const float2 *in, float2 *out, const float2 *
     return EPIC_OK;
 }
 
-template <int NX>
+template <int NX, bool INV>
 epic_status run_rows(int64_t n_rows, const float2 *in, float2 *out, const float2 *tw,
                      hipStream_t stream)
 {
     constexpr int ROWS = 16, BLOCK = 256;
     const size_t bytes = sizeof(float2) * (ROWS * (NX + 1) + NX);
-    auto k = k_fft_rows<NX, ROWS, BLOCK>;
+    auto k = k_fft_rows<NX, ROWS, BLOCK, INV>;
     epic_status s = set_lds(k, bytes);
     if (s != EPIC_OK) return s;
     const int64_t blocks = (n_rows + ROWS - 1) / ROWS;
@@ -120,12 +139,12 @@ epic_status run_rows(int64_t n_rows, const float2 *in, float2 *out, const float2
     return EPIC_OK;
 }
 
-template <int NX, int NY>
+template <int NX, int NY, bool INV>
 epic_status run_cols(int64_t batch, float2 *data, const float2 *tw, hipStream_t stream)
 {
     constexpr int COLS = 16, BLOCK = 256;
     const size_t bytes = sizeof(float2) * (NY * (COLS + 1) + NY);
-    auto k = k_fft_cols<NX, NY, COLS, BLOCK>;
+    auto k = k_fft_cols<NX, NY, COLS, BLOCK, INV>;
     epic_status s = set_lds(k, bytes);
     if (s != EPIC_OK) return s;
     const int64_t blocks = batch * (NX / COLS);
@@ -135,35 +154,35 @@ epic_status run_cols(int64_t batch, float2 *data, const float2 *tw, hipStream_t 
     return EPIC_OK;
 }
 
-template <int NX>
+template <int NX, bool INV>
 epic_status dispatch_ny(int ny, int64_t batch, const float2 *in, float2 *out, const float2 *twx,
                         const float2 *twy, hipStream_t stream)
 {
     if constexpr (NX <= 128) {
         switch (ny) {
-        case 16: return run_lds<NX, 16>(batch, in, out, twx, twy, stream);
-        case 32: return run_lds<NX, 32>(batch, in, out, twx, twy, stream);
-        case 64: return run_lds<NX, 64>(batch, in, out, twx, twy, stream);
+        case 16: return run_lds<NX, 16, INV>(batch, in, out, twx, twy, stream);
+        case 32: return run_lds<NX, 32, INV>(batch, in, out, twx, twy, stream);
+        case 64: return run_lds<NX, 64, INV>(batch, in, out, twx, twy, stream);
         case 128:
-            if constexpr (NX <= 64) return run_lds<NX, 128>(batch, in, out, twx, twy, stream);
+            if constexpr (NX <= 64) return run_lds<NX, 128, INV>(batch, in, out, twx, twy, stream);
             break;
         default: break;
         }
     }
     if constexpr (NX == 256) {
-        if (ny == 16) return run_lds<NX, 16>(batch, in, out, twx, twy, stream);
-        if (ny == 32) return run_lds<NX, 32>(batch, in, out, twx, twy, stream);
-        if (ny == 64) return run_lds<NX, 64>(batch, in, out, twx, twy, stream);
+        if (ny == 16) return run_lds<NX, 16, INV>(batch, in, out, twx, twy, stream);
+        if (ny == 32) return run_lds<NX, 32, INV>(batch, in, out, twx, twy, stream);
+        if (ny == 64) return run_lds<NX, 64, INV>(batch, in, out, twx, twy, stream);
     }
     // two passes through global memory
-    epic_status s = run_rows<NX>(batch * ny, in, out, twx, stream);
+    epic_status s = run_rows<NX, INV>(batch * ny, in, out, twx, stream);
     if (s != EPIC_OK) return s;
     switch (ny) {
-    case 16: return run_cols<NX, 16>(batch, out, twy, stream);
-    case 32: return run_cols<NX, 32>(batch, out, twy, stream);
-    case 64: return run_cols<NX, 64>(batch, out, twy, stream);
-    case 128: return run_cols<NX, 128>(batch, out, twy, stream);
-    case 256: return run_cols<NX, 256>(batch, out, twy, stream);
+    case 16: return run_cols<NX, 16, INV>(batch, out, twy, stream);
+    case 32: return run_cols<NX, 32, INV>(batch, out, twy, stream);
+    case 64: return run_cols<NX, 64, INV>(batch, out, twy, stream);
+    case 128: return run_cols<NX, 128, INV>(batch, out, twy, stream);
+    case 256: return run_cols<NX, 256, INV>(batch, out, twy, stream);
     }
     return fail(EPIC_ERR_INTERNAL, "fft2: unexpected ny");
 }
@@ -171,21 +190,25 @@ epic_status dispatch_ny(int ny, int64_t batch, const float2 *in, float2 *out, co
 }  // namespace
 
 epic_status launch_fft2_f32(int nx, int ny, int64_t batch, const float2 *in, float2 *out,
-                            int device, hipStream_t stream)
+                            int device, hipStream_t stream, bool inverse)
 {
     const float2 *twx = nullptr, *twy = nullptr;
     epic_status s = get_twiddles(nx, device, &twx);
     if (s != EPIC_OK) return s;
     s = get_twiddles(ny, device, &twy);
     if (s != EPIC_OK) return s;
-    switch (nx) {
-    case 16: return dispatch_ny<16>(ny, batch, in, out, twx, twy, stream);
-    case 32: return dispatch_ny<32>(ny, batch, in, out, twx, twy, stream);
-    case 64: return dispatch_ny<64>(ny, batch, in, out, twx, twy, stream);
-    case 128: return dispatch_ny<128>(ny, batch, in, out, twx, twy, stream);
-    case 256: return dispatch_ny<256>(ny, batch, in, out, twx, twy, stream);
-    }
-    return fail(EPIC_ERR_INTERNAL, "fft2: unexpected nx");
+    auto go = [&](auto inv) -> epic_status {
+        constexpr bool INV = decltype(inv)::value;
+        switch (nx) {
+        case 16: return dispatch_ny<16, INV>(ny, batch, in, out, twx, twy, stream);
+        case 32: return dispatch_ny<32, INV>(ny, batch, in, out, twx, twy, stream);
+        case 64: return dispatch_ny<64, INV>(ny, batch, in, out, twx, twy, stream);
+        case 128: return dispatch_ny<128, INV>(ny, batch, in, out, twx, twy, stream);
+        case 256: return dispatch_ny<256, INV>(ny, batch, in, out, twx, twy, stream);
+        }
+        return fail(EPIC_ERR_INTERNAL, "fft2: unexpected nx");
+    };
+    return inverse ? go(std::true_type{}) : go(std::false_type{});
 }
 
 }  // namespace epic

@@ -34,7 +34,7 @@ KERNEL_GAUSSIAN = 1
 
 # every function the header declares
 ABI_FUNCTIONS = ("grid_voltages", "fft2_batched", "accumulate_power", "image_cadence",
-                 "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
+                 "image_to_visibilities", "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
                  "epic_timing_reset", "epic_status_string", "epic_last_error",
                  "epic_cache_clear")
 
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.accumulate_power.restype = i32
     lib.image_cadence.argtypes = [P, P, i32, P]
     lib.image_cadence.restype = i32
+    lib.image_to_visibilities.argtypes = [i32, i32, i32, i32, P, P, P]
+    lib.image_to_visibilities.restype = i32
     lib.epic_autotune.argtypes = [P, P, i32, P]
     lib.epic_autotune.restype = i32
     lib.epic_validate.argtypes = [P, P, i32]
@@ -213,6 +215,14 @@ def accumulate_power(n_pol: int, nx: int, ny: int, n_chan: int, nt: int, field, 
     lib = load()
     _check(lib.accumulate_power(n_pol, nx, ny, n_chan, nt, _dptr(field), _dptr(acc_sum),
                                 _dptr(acc_comp), finalize_n_time, _dptr(image), _stream(stream)))
+
+
+def image_to_visibilities(n_pol: int, nx: int, ny: int, n_chan: int, image, vis, stream=None):
+    """FFT-correlator output: the inverse transform of each product image
+    (image, vis: device cf32 [n_chan][n_pol^2][ny][nx]; image is vis allowed)."""
+    lib = load()
+    _check(lib.image_to_visibilities(n_pol, nx, ny, n_chan, _dptr(image), _dptr(vis),
+                                     _stream(stream)))
 
 
 def _stations_c(stations):

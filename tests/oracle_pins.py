@@ -20,6 +20,11 @@ What each pin is tied to:
                              included) gridded with the cross-correlated element
                              kernels and transformed equal the EPIC image
                              (Wiener-Khinchin on the circular grid).
+* pin_visibility_closed_forms -- the directly gridded visibilities (the
+                            FFT-correlator output, Eq. 4 then Eq. 6 without a
+                            transform): explicit values for elements on cell
+                            centres, the total equals the mean beam power at
+                            zero, Hermitian symmetry between XY and YX.
 * pin_translation         -- shifting every element by whole cells leaves the
                              power image unchanged.
 * pin_pol_symmetry        -- YX = conj(XY) and Im XX = 0 exactly, XX >= 0.
@@ -45,6 +50,7 @@ PIN_TOL = {
     "parseval": 1e-12,
     "point_source_centre": 1e-12,
     "point_source_offset": 1e-12,
+    "visibility_closed_forms": 1e-12,
     "xfft_equivalence": 1e-12,
     "translation": 1e-12,
     "pol_symmetry": 0.0,
@@ -164,6 +170,9 @@ def pin_point_source_offset(lib):
 
 
 def pin_xfft_equivalence(lib):
+    # the EPIC image (grid, + transform, square, mean) against the visibilities
+    # of Eq. 4 gridded as in Eq. 6 (oracle.grid_visibilities, no transform)
+    # and transformed with numpy: the two routes meet on the circular grid
     rng = _rng(6)
     nx, ny, lam, dwl, K, sig = 16, 16, 2.0, 0.5, 3, 0.5
     n_el, n_time, n_pol = 10, 9, 2
@@ -171,26 +180,43 @@ def pin_xfft_equivalence(lib):
     E = _cnormal(rng, (1, n_time, n_el, n_pol))
     img = oracle.image(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, E,
                        lib=lib)[0]
-    ix, iy, wx, wy = oracle.plan(pos, lam, dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, lib=lib)
-    # Eq. 4: visibilities including the a = b autocorrelations, averaged over time
-    V = np.einsum("tap,tbq->pqab", E[0], np.conj(E[0])) / n_time
-    h = (K - 1) // 2
-    ref = np.zeros((n_pol * n_pol, ny, nx), np.complex128)
-    for p in range(n_pol):
-        for q in range(n_pol):
-            Gv = np.zeros((ny, nx), np.complex128)
-            # Eq. 6 gridding with B_ab = w_a (cross-correlated with) w_b
-            for d1y in range(-h, h + 1):
-                for d1x in range(-h, h + 1):
-                    wa = wx[:, d1x + h] * wy[:, d1y + h]
-                    for d2y in range(-h, h + 1):
-                        for d2x in range(-h, h + 1):
-                            wb = wx[:, d2x + h] * wy[:, d2y + h]
-                            cx = ((ix + d1x)[:, None] - (ix + d2x)[None, :]) % nx
-                            cy = ((iy + d1y)[:, None] - (iy + d2y)[None, :]) % ny
-                            np.add.at(Gv, (cy, cx), wa[:, None] * wb[None, :] * V[p, q])
-            ref[p * n_pol + q] = np.fft.ifft2(Gv) * (nx * ny)
+    Gv = oracle.grid_visibilities(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_GAUSSIAN, K,
+                                  sig, E, lib=lib)[0]
+    ref = np.fft.ifft2(Gv, axes=(-2, -1)) * (nx * ny)
     return _rel(img, ref)
+
+
+def pin_visibility_closed_forms(lib):
+    # (a) nearest kernel, elements on cell centres, one sample: the grid holds
+    # E_a conj(E_b) at each baseline cell c_a - c_b and sum_a |E_a|^2 at 0;
+    # (b) Gaussian kernels: sum_j G^{pp}[j] = mean_t |sum_a E_a^p(t)|^2 (unit-sum
+    # kernels), and G^{pq}[j] = conj(G^{qp}[-j]) (Hermitian)
+    rng = _rng(12)
+    nx = ny = 16
+    lam, dwl = 2.0, 0.5
+    cells = np.array([[0, 0], [3, 1], [-2, 4]])
+    pos = cells * dwl * lam
+    E = _cnormal(rng, (1, 1, 3, 1))
+    G = oracle.grid_visibilities(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_NEAREST, 1, 1.0,
+                                 E, lib=lib)[0, 0]
+    want = np.zeros((ny, nx), np.complex128)
+    e = E[0, 0, :, 0]
+    for a in range(3):
+        for b in range(3):
+            d = cells[a] - cells[b]
+            want[d[1] % ny, d[0] % nx] += e[a] * np.conj(e[b])
+    err = _rel(G, want)
+    n_el, n_time, n_pol = 7, 5, 2
+    pos = rng.uniform(-3.0, 3.0, (n_el, 2))
+    E = _cnormal(rng, (1, n_time, n_el, n_pol))
+    G = oracle.grid_visibilities(pos, np.array([lam]), dwl, nx, ny, oracle.KERNEL_GAUSSIAN, 3, 0.5,
+                                 E, lib=lib)[0]
+    for p in range(n_pol):
+        tot = np.mean(np.abs(E[0, :, :, p].sum(axis=1)) ** 2)
+        err = max(err, abs(G[p * n_pol + p].sum() - tot) / tot)
+    flip = lambda g: np.roll(g[::-1, ::-1], 1, axis=(0, 1))   # j -> -j on the circular grid
+    err = max(err, _rel(G[1], np.conj(flip(G[2]))))
+    return err
 
 
 def pin_translation(lib):
@@ -282,6 +308,7 @@ ALL_PINS = {
     "point_source_centre": pin_point_source_centre,
     "point_source_offset": pin_point_source_offset,
     "xfft_equivalence": pin_xfft_equivalence,
+    "visibility_closed_forms": pin_visibility_closed_forms,
     "translation": pin_translation,
     "pol_symmetry": pin_pol_symmetry,
     "golden_two_element": pin_golden_two_element,

@@ -123,6 +123,12 @@ def test_unfused_calls_reject_bad_shapes_without_a_device():
     with pytest.raises(epic.EpicError):
         epic.accumulate_power(2, 64, 64, 1, 1, 0x1000, 0x1000, 0x1000, finalize_n_time=4,
                               image=None, stream=0)
+    for args in [(3, 64, 64, 1), (2, 48, 64, 1), (2, 64, 512, 1), (2, 64, 64, 0)]:
+        with pytest.raises(epic.EpicError) as e:
+            epic.image_to_visibilities(*args, 0x1000, 0x1000, stream=0)
+        assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    with pytest.raises(epic.EpicError):
+        epic.image_to_visibilities(2, 64, 64, 1, None, 0x1000, stream=0)
     common, station = _c2_like()
     with pytest.raises(epic.EpicError):
         epic.grid_voltages(common, station, 6, 4, 0x3000, stream=0)     # t0 + nt > n_time

@@ -91,6 +91,52 @@ def test_fft2_batched_fp32(torch, nx, ny):
     assert torch.equal(xin, out)
 
 
+# ---------------------------------------------- FFT-correlator output ----
+@pytest.mark.parametrize("nx,ny", [(16, 16), (64, 32), (64, 64), (128, 128), (256, 256), (256, 64)])
+def test_image_to_visibilities_transform(torch, nx, ny):
+    # the inverse transform: (1/N) sum_k x[k] exp(-2 pi i k.j/N) = conj(F(conj x)) / N
+    # with F the oracle's + sign transform
+    from paper_2411_17804_amd import epic
+    say(f"image_to_visibilities {nx}x{ny}")
+    rng = np.random.default_rng([17804, 91, nx, ny])
+    n_pol, n_chan = 2, 2
+    shape = (n_chan, n_pol * n_pol, ny, nx)
+    x = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    x = x.astype(np.complex128)
+    xin = from_complex(x)
+    out = torch.empty_like(xin)
+    epic.image_to_visibilities(n_pol, nx, ny, n_chan, xin, out)
+    torch.cuda.synchronize()
+    ref = np.conj(oracle.fft2(np.conj(x).reshape(-1, ny, nx))).reshape(shape) / (nx * ny)
+    err = _rel(to_complex(out), ref)
+    assert err <= 2e-6, err
+    epic.image_to_visibilities(n_pol, nx, ny, n_chan, xin, xin)      # in place: same bits
+    torch.cuda.synchronize()
+    assert torch.equal(xin, out)
+
+
+@pytest.mark.parametrize("case", ["C1-full", "C2-2ch"])
+def test_fft_correlator_output(torch, case):
+    # image_cadence then image_to_visibilities against the visibilities of
+    # Eq. 4 gridded directly as in Eq. 6 (no transform on the oracle side)
+    from paper_2411_17804_amd import epic
+    say(f"FFT-correlator output {case}")
+    if case == "C1-full":
+        cfg = W.make_config(1, precision=W.FP32_FFT)
+    else:
+        cfg = W.make_config(2, chan_subset=[5, 900], n_time=24, precision=W.FP32_FFT)
+    volts, _, (common, stations) = run_cadence(cfg)
+    st, s0 = cfg.stations[0], stations[0]
+    vis = torch.empty_like(s0.image)
+    epic.image_to_visibilities(cfg.n_pol, st.nx, st.ny, cfg.n_chan, s0.image, vis)
+    torch.cuda.synchronize()
+    ref = oracle.grid_visibilities(st.pos_m, cfg.wavelengths_m, W.GRID_SPACING_WL, st.nx, st.ny,
+                                   st.kernel_type, st.support, st.sigma_cells, volts[0])
+    err = oracle.image_error(to_complex(vis), ref, cfg.n_pol)
+    say(f"  worst error {err.max():.2e}")
+    assert err.max() <= FP32_TOL, err
+
+
 # ----------------------------------------------------------------- power ----
 @pytest.mark.parametrize("n_pol", [1, 2])
 def test_accumulate_power(torch, n_pol):
