@@ -370,6 +370,20 @@ def stage_rooflines(cfg, common, station, nt=64, reps=3):
     res["image_to_visibilities"] = {"ms": round(ms, 3), "bound": "hbm", "bytes": b,
                                     "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
                                     "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    # incoherent combination (Eq. 7) of 8 station images on this sky grid,
+    # with per-pixel weights (8 distinct copies of the image stand in for the
+    # stations, so that every byte comes from HBM)
+    n_st = 8
+    copies = img.unsqueeze(0).repeat(n_st, *([1] * img.dim()))
+    wts = torch.ones((n_st, cfg.n_pol ** 2, st.ny, st.nx), dtype=torch.float32, device="cuda:0")
+    ms = timed(lambda: epic.combine_incoherent(cfg.n_pol, st.nx, st.ny, cfg.n_chan,
+                                               [copies[m] for m in range(n_st)], acc[1], wts))
+    plane = cfg.n_pol ** 2 * npix
+    b = (n_st + 1) * cfg.n_chan * plane * 8 + n_st * plane * 4
+    res["combine_incoherent_8"] = {"ms": round(ms, 3), "bound": "hbm", "bytes": b,
+                                   "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
+                                   "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    del wts, copies
     res["_block"] = f"{cfg.n_chan} channels x {nt} samples x {cfg.n_pol} pols of {st.nx}x{st.ny}"
     del grid, out, acc, img
     torch.cuda.empty_cache()

@@ -178,6 +178,25 @@ epic_status image_to_visibilities(int32_t n_pol, int32_t nx, int32_t ny, int32_t
                                   const void *image, void *vis, hipStream_t stream);
 
 /*
+ * Incoherent combination of station images (Sec. 6.1, Eq. 7): the weighted
+ * mean of the stations' polarised intensities per sky pixel,
+ *     out[c][q][k] = sum_m w[m][q][k] images[m][c][q][k] / sum_m w[m][q][k],
+ * for stations imaged on one sky pixel grid (same nx, ny and grid spacing in
+ * wavelengths, hence the same directions per pixel).
+ * images: host array of n_stations device pointers, each cf32
+ *         [n_chan][n_pol*n_pol][ny][nx] (image_cadence outputs);
+ * weights: device float [n_stations][n_pol*n_pol][ny][nx], the same for every
+ *         channel (a station's beam weight towards each pixel), or NULL for
+ *         equal weights; pixels whose weights sum to 0 are written as 0;
+ * out: device cf32 [n_chan][n_pol*n_pol][ny][nx] (may be one of the images).
+ * 1 <= n_stations <= 128.  FP32 sums over the stations in order.
+ * Errors: EPIC_ERR_INVALID_ARG for shapes, counts or NULL pointers.
+ */
+epic_status combine_incoherent(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_chan,
+                               int32_t n_stations, const void *const *images,
+                               const float *weights, void *out, hipStream_t stream);
+
+/*
  * Tile tuning (auxiliary).  image_cadence runs every station whose grid is
  * square and at most 64 x 64 (and, in FP32, every 128 x 128 one) in fused
  * kernels that process one (station, channel, time chunk) item per

@@ -249,6 +249,25 @@ def grid_visibilities(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type
     return out
 
 
+def combine_incoherent(images, weights=None):
+    """Incoherent combination of station images (Sec. 6.1, Eq. 7), in FP64:
+    per pixel, product and channel, sum_m w_m I_m / sum_m w_m, for stations on
+    one sky pixel grid.  images: sequence of [n_chan, n_q, ny, nx] complex;
+    weights: [n_stations, n_q, ny, nx] real (the same for every channel) or
+    None for equal weights.  Pixels whose weights sum to 0 give 0."""
+    imgs = np.stack([np.asarray(i, np.complex128) for i in images])      # [m, c, q, y, x]
+    if weights is None:
+        w = np.ones((imgs.shape[0],) + imgs.shape[2:], np.float64)
+    else:
+        w = np.asarray(weights, np.float64)
+    num = np.einsum("mqyx,mcqyx->cqyx", w, imgs)
+    den = w.sum(axis=0)
+    out = np.zeros(num.shape, np.complex128)
+    nz = den != 0
+    out[:, nz] = num[:, nz] / den[nz]
+    return out
+
+
 def max_threads(lib=None) -> int:
     return (lib or load()).eo_max_threads()
 

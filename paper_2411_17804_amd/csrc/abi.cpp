@@ -258,6 +258,27 @@ epic_status image_to_visibilities(int32_t n_pol, int32_t nx, int32_t ny, int32_t
                            dev, stream, true);
 }
 
+epic_status combine_incoherent(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_chan,
+                               int32_t n_stations, const void *const *images,
+                               const float *weights, void *out, hipStream_t stream)
+{
+    set_error("");
+    if (n_pol != 1 && n_pol != 2) return fail(EPIC_ERR_INVALID_ARG, "n_pol must be 1 or 2");
+    if (!is_pow2_grid(nx) || !is_pow2_grid(ny))
+        return fail(EPIC_ERR_INVALID_ARG, "nx, ny must be powers of two in 16..256");
+    if (n_chan < 1 || n_chan > 65535) return fail(EPIC_ERR_INVALID_ARG, "n_chan must be in 1..65535");
+    if (n_stations < 1 || n_stations > kMaxCombine)
+        return fail(EPIC_ERR_INVALID_ARG, "n_stations must be in 1..128");
+    if (!images || !out) return fail(EPIC_ERR_INVALID_ARG, "images/out is NULL");
+    StationImages imgs{};
+    for (int m = 0; m < n_stations; ++m) {
+        if (!images[m]) return fail(EPIC_ERR_INVALID_ARG, "a station image pointer is NULL");
+        imgs.p[m] = static_cast<const float2 *>(images[m]);
+    }
+    return launch_combine(imgs, n_stations, n_pol * n_pol * nx * ny, n_chan, weights,
+                          static_cast<float2 *>(out), stream);
+}
+
 epic_status image_cadence(const epic_common *common, const epic_station *stations,
                           int32_t n_stations, hipStream_t stream)
 {

@@ -187,6 +187,15 @@ epic_status launch_fused_fft128_partials(const FusedBatch &b, int n_pol, int n_t
                                          int block, const float2 *boxes, float *partials,
                                          const float2 *twiddles, hipStream_t stream);
 
+// Incoherent combination of station images (k_combine.hip): device pointers
+// of up to kMaxCombine station images, passed by value as a kernel argument.
+constexpr int kMaxCombine = 128;
+struct StationImages {
+    const float2 *p[kMaxCombine];
+};
+epic_status launch_combine(const StationImages &imgs, int n_stations, int plane, int n_chan,
+                           const float *weights, float2 *out, hipStream_t stream);
+
 // Ordered, compensated reduction of the partial sums of every chunk, then the
 // mean, written as the n_pol^2 complex products.
 epic_status launch_reduce_partials(int n_pol, int npix, int n_chan, int n_chunks,

@@ -34,7 +34,7 @@ KERNEL_GAUSSIAN = 1
 
 # every function the header declares
 ABI_FUNCTIONS = ("grid_voltages", "fft2_batched", "accumulate_power", "image_cadence",
-                 "image_to_visibilities", "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
+                 "image_to_visibilities", "combine_incoherent", "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
                  "epic_timing_reset", "epic_status_string", "epic_last_error",
                  "epic_cache_clear")
 
@@ -87,6 +87,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.image_cadence.restype = i32
     lib.image_to_visibilities.argtypes = [i32, i32, i32, i32, P, P, P]
     lib.image_to_visibilities.restype = i32
+    lib.combine_incoherent.argtypes = [i32, i32, i32, i32, i32, P, P, P, P]
+    lib.combine_incoherent.restype = i32
     lib.epic_autotune.argtypes = [P, P, i32, P]
     lib.epic_autotune.restype = i32
     lib.epic_validate.argtypes = [P, P, i32]
@@ -223,6 +225,17 @@ def image_to_visibilities(n_pol: int, nx: int, ny: int, n_chan: int, image, vis,
     lib = load()
     _check(lib.image_to_visibilities(n_pol, nx, ny, n_chan, _dptr(image), _dptr(vis),
                                      _stream(stream)))
+
+
+def combine_incoherent(n_pol: int, nx: int, ny: int, n_chan: int, images, out, weights=None,
+                       stream=None):
+    """Weighted mean of station images on one sky grid (images: sequence of
+    device tensors cf32 [n_chan][n_pol^2][ny][nx]; weights: device float
+    [n_stations][n_pol^2][ny][nx] or None for equal weights)."""
+    lib = load()
+    ptrs = (ctypes.c_void_p * max(1, len(images)))(*[_dptr(t) for t in images])
+    _check(lib.combine_incoherent(n_pol, nx, ny, n_chan, len(images), ptrs if images else None,
+                                  _dptr(weights), _dptr(out), _stream(stream)))
 
 
 def _stations_c(stations):

@@ -25,6 +25,11 @@ What each pin is tied to:
                             transform): explicit values for elements on cell
                             centres, the total equals the mean beam power at
                             zero, Hermitian symmetry between XY and YX.
+* pin_incoherent_combination -- Eq. 7 as a weighted mean: invariant under a
+                            per-pixel rescaling of the weights, returns a lone
+                            weighted station or identical images unchanged,
+                            0 where all weights vanish, the plain mean for
+                            equal weights.
 * pin_translation         -- shifting every element by whole cells leaves the
                              power image unchanged.
 * pin_pol_symmetry        -- YX = conj(XY) and Im XX = 0 exactly, XX >= 0.
@@ -51,6 +56,7 @@ PIN_TOL = {
     "point_source_centre": 1e-12,
     "point_source_offset": 1e-12,
     "visibility_closed_forms": 1e-12,
+    "incoherent_combination": 1e-13,
     "xfft_equivalence": 1e-12,
     "translation": 1e-12,
     "pol_symmetry": 0.0,
@@ -219,6 +225,29 @@ def pin_visibility_closed_forms(lib):
     return err
 
 
+def pin_incoherent_combination(lib):
+    # Eq. 7 as weighted mean: invariant under a per-pixel rescaling of all
+    # weights; a single weighted station is returned as it is; identical
+    # images come back unchanged for any weights; all-zero weights give 0
+    rng = _rng(13)
+    n_st, n_chan, nq, ny, nx = 4, 2, 4, 8, 8
+    imgs = [_cnormal(rng, (n_chan, nq, ny, nx)) for _ in range(n_st)]
+    w = rng.uniform(0.1, 2.0, (n_st, nq, ny, nx))
+    base = oracle.combine_incoherent(imgs, w)
+    err = _rel(oracle.combine_incoherent(imgs, w * rng.uniform(0.5, 3.0, (1, nq, ny, nx))), base)
+    one = np.zeros_like(w)
+    one[2] = rng.uniform(0.5, 1.5, (nq, ny, nx))
+    err = max(err, _rel(oracle.combine_incoherent(imgs, one), imgs[2]))
+    same = [imgs[0]] * n_st
+    err = max(err, _rel(oracle.combine_incoherent(same, w), imgs[0]))
+    zero = w.copy()
+    zero[:, 1, 3, 5] = 0.0
+    z = oracle.combine_incoherent(imgs, zero)
+    err = max(err, float(np.abs(z[:, 1, 3, 5]).max()))
+    err = max(err, _rel(oracle.combine_incoherent(imgs), np.mean(np.stack(imgs), axis=0)))
+    return err
+
+
 def pin_translation(lib):
     rng = _rng(7)
     nx, ny, lam, dwl, K, sig = 32, 32, 2.0, 0.5, 3, 0.5
@@ -309,6 +338,7 @@ ALL_PINS = {
     "point_source_offset": pin_point_source_offset,
     "xfft_equivalence": pin_xfft_equivalence,
     "visibility_closed_forms": pin_visibility_closed_forms,
+    "incoherent_combination": pin_incoherent_combination,
     "translation": pin_translation,
     "pol_symmetry": pin_pol_symmetry,
     "golden_two_element": pin_golden_two_element,

@@ -129,6 +129,12 @@ def test_unfused_calls_reject_bad_shapes_without_a_device():
         assert e.value.status == epic.EPIC_ERR_INVALID_ARG
     with pytest.raises(epic.EpicError):
         epic.image_to_visibilities(2, 64, 64, 1, None, 0x1000, stream=0)
+    for n_pol, nx, n_chan, imgs in [(3, 64, 1, [0x1000]), (2, 40, 1, [0x1000]), (2, 64, 0, [0x1000]),
+                                    (2, 64, 1, []), (2, 64, 1, [0x1000] * 129),
+                                    (2, 64, 1, [0x1000, None])]:
+        with pytest.raises(epic.EpicError) as e:
+            epic.combine_incoherent(n_pol, nx, 64, n_chan, imgs, 0x2000, stream=0)
+        assert e.value.status == epic.EPIC_ERR_INVALID_ARG
     common, station = _c2_like()
     with pytest.raises(epic.EpicError):
         epic.grid_voltages(common, station, 6, 4, 0x3000, stream=0)     # t0 + nt > n_time
