@@ -125,9 +125,20 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
     EPIC_HIP_TRY(hipMemsetAsync(ws_acc, 0, 2 * acc_bytes, stream));
     const StationDev sd = make_station_dev(s, p);
     float2 *field = static_cast<float2 *>(ws_field);
+    // large stations: sample-blocked voltage copy for the gather (k_grid.hip)
+    float2 *tv = nullptr;
+    if (s->n_elem >= kGridTbMinElem) {
+        void *ws_tv = nullptr;
+        const size_t tv_bytes = sizeof(float2) * static_cast<size_t>(n_chan) * ((chunk + 7) / 8) * 8 *
+                                s->n_elem * n_pol;
+        st = get_workspace(device, stream, 2, tv_bytes, &ws_tv);
+        if (st != EPIC_OK) return st;
+        tv = static_cast<float2 *>(ws_tv);
+    }
     for (int t0 = 0; t0 < c->n_time; t0 += chunk) {
         const int nt = std::min(chunk, c->n_time - t0);
-        st = launch_grid(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, field, stream);
+        st = tv ? launch_grid_tb(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, tv, field, stream)
+                : launch_grid(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, field, stream);
         if (st != EPIC_OK) return st;
         const int64_t batch = static_cast<int64_t>(n_chan) * nt * n_pol;
         if (c->precision == EPIC_FP32_FFT)

@@ -155,6 +155,12 @@ bool timing_on();
 epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
                         int t0, int nt, float2 *grid, hipStream_t stream);
 
+// Gridding of large stations through a sample-blocked copy of the voltages:
+// tv is a device buffer of n_chan * ceil(nt / 8) * n_elem * 8 * n_pol float2.
+epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
+                           int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream);
+constexpr int kGridTbMinElem = 1024;   // stations at least this large take that route
+
 // inverse: (1/(nx ny)) sum_k x[k] exp(-2 pi i k.j / N) instead of the + sign transform
 epic_status launch_fft2_f32(int nx, int ny, int64_t batch, const float2 *in, float2 *out,
                             int device, hipStream_t stream, bool inverse = false);

@@ -7,26 +7,32 @@
 
 namespace epic {
 
-// One work-group per (channel, block of TB samples): every cell's tap list is
-// read once and applied to the TB samples, whose voltage loads are independent
-// of each other.  Writes all n_pol planes of each sample's ny x nx grid (zero
-// outside the footprint box).
+constexpr int kGridCellBlock = 1024;   // grid cells per work-group (4 per thread)
+constexpr int kGridTB = 8;             // samples per gridding work-group
+
+// One work-group per (channel, block of TB samples, block of CB cells): every
+// cell's tap list is read once and applied to the TB samples, whose voltage
+// loads are independent of each other.  Writes all n_pol planes of each
+// sample's ny x nx grid (zero outside the footprint box).  The cell blocks
+// keep the launch wide when a few samples of a large grid are gridded.
 template <int NP, int VT, int TB>
 __global__ __launch_bounds__(256) void k_grid(StationDev sd, int n_time, int t0, int nt,
                                               float2 *__restrict__ grid)
 {
+    constexpr int CB = kGridCellBlock;
     const int tb = blockIdx.x * TB;
     const int c = blockIdx.y;
     const int nts = min(TB, nt - tb);
     const ChanPlan cp = sd.chan[c];
-    const int32_t *cs = sd.cell_start + cp.cell_off;
+    const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
     const Tap *taps = sd.taps + cp.tap_off;
     const int nx = sd.nx, ny = sd.ny;
     const int npix = nx * ny;
     const size_t vrow0 = (static_cast<size_t>(c) * n_time + t0 + tb) * sd.n_elem;
     const size_t vstride = sd.n_elem;                      // elements per sample
     float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
-    for (int i = threadIdx.x; i < npix; i += blockDim.x) {
+    const int i_end = min(npix, static_cast<int>(blockIdx.z + 1) * CB);
+    for (int i = blockIdx.z * CB + threadIdx.x; i < i_end; i += blockDim.x) {
         const int y = i / nx, x = i - y * nx;
         const int bx = x - cp.x0, by = y - cp.y0;
         float2 acc[TB][NP];
@@ -38,7 +44,7 @@ __global__ __launch_bounds__(256) void k_grid(StationDev sd, int n_time, int t0,
             const int cell = by * cp.bw + bx;
             const int k1 = cs[cell + 1];
             for (int k = cs[cell]; k < k1; ++k) {
-                const Tap tp = taps[k];
+                const Tap tp = gload<Tap>(taps, k);
 #pragma unroll
                 for (int t = 0; t < TB; ++t) {
                     if (t < nts) {
@@ -62,11 +68,124 @@ __global__ __launch_bounds__(256) void k_grid(StationDev sd, int n_time, int t0,
     }
 }
 
+// Large stations: the TB samples of one element that a tap needs are first
+// made contiguous.  k_volts_tb copies samples t0 .. t0+nt-1 into
+// tv[c][block][elem][TB][NP] (FP32; samples past nt are 0), one thread per
+// (channel, block, element), reading unit-stride rows and writing one
+// contiguous run of TB * NP values; k_grid_tb then gathers each tap's TB
+// samples from one or two cache lines instead of TB separate rows.
+template <int NP, int VT, int TB>
+__global__ __launch_bounds__(256) void k_volts_tb(const void *__restrict__ volts, int n_elem,
+                                                  int n_time, int t0, int nt, int nblk,
+                                                  float2 *__restrict__ tv)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n_elem) return;
+    const int blk = blockIdx.y, c = blockIdx.z;
+    float2 v[TB][NP];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+        const int tt = blk * TB + t;
+        if (tt < nt) {
+            load_volt<NP, VT>(volts, (static_cast<size_t>(c) * n_time + t0 + tt) * n_elem + e, v[t]);
+        } else {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) v[t][p] = make_float2(0.f, 0.f);
+        }
+    }
+    float2 *dst = tv + ((static_cast<size_t>(c) * nblk + blk) * n_elem + e) * TB * NP;
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) dst[t * NP + p] = v[t][p];
+}
+
+template <int NP, int TB>
+__global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk,
+                                                 const float2 *__restrict__ tv,
+                                                 float2 *__restrict__ grid)
+{
+    constexpr int CB = kGridCellBlock;
+    const int blk = blockIdx.x, tb = blk * TB;
+    const int c = blockIdx.y;
+    const int nts = min(TB, nt - tb);
+    const ChanPlan cp = sd.chan[c];
+    const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
+    const Tap *taps = sd.taps + cp.tap_off;
+    const int nx = sd.nx, ny = sd.ny;
+    const int npix = nx * ny;
+    const float2 *src = tv + (static_cast<size_t>(c) * nblk + blk) * sd.n_elem * TB * NP;
+    float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
+    const int i_end = min(npix, static_cast<int>(blockIdx.z + 1) * CB);
+    for (int i = blockIdx.z * CB + threadIdx.x; i < i_end; i += blockDim.x) {
+        const int y = i / nx, x = i - y * nx;
+        const int bx = x - cp.x0, by = y - cp.y0;
+        float2 acc[TB][NP];
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) acc[t][p] = make_float2(0.f, 0.f);
+        if (bx >= 0 && bx < cp.bw && by >= 0 && by < cp.bh) {
+            const int cell = by * cp.bw + bx;
+            const int k1 = cs[cell + 1];
+            for (int k = cs[cell]; k < k1; ++k) {
+                const Tap tp = gload<Tap>(taps, k);
+                const float2 *e = src + static_cast<size_t>(tp.elem) * TB * NP;
+#pragma unroll
+                for (int t = 0; t < TB; ++t)
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const float2 v = gload<float2>(e, t * NP + p);
+                        acc[t][p].x = fmaf(tp.w, v.x, acc[t][p].x);
+                        acc[t][p].y = fmaf(tp.w, v.y, acc[t][p].y);
+                    }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+            if (t < nts)
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    out[(static_cast<size_t>(t) * NP + p) * npix + i] = acc[t][p];
+    }
+}
+
+epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
+                           int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream)
+{
+    constexpr int TB = kGridTB;
+    const int nblk = (nt + TB - 1) / TB;
+    const dim3 tblocks((sd.n_elem + 255) / 256, nblk, n_chan), threads(256);
+    {
+        KernelTimer timer("volts_tb", stream);
+        if (n_pol == 1 && volt_type == EPIC_CI8)
+            hipLaunchKernelGGL((k_volts_tb<1, EPIC_CI8, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
+        else if (n_pol == 1)
+            hipLaunchKernelGGL((k_volts_tb<1, EPIC_CF32, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
+        else if (volt_type == EPIC_CI8)
+            hipLaunchKernelGGL((k_volts_tb<2, EPIC_CI8, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
+        else
+            hipLaunchKernelGGL((k_volts_tb<2, EPIC_CF32, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
+        EPIC_HIP_TRY(hipGetLastError());
+    }
+    const int npix = sd.nx * sd.ny;
+    const dim3 blocks(nblk, n_chan, (npix + kGridCellBlock - 1) / kGridCellBlock);
+    KernelTimer timer("grid_gather", stream);
+    if (n_pol == 1)
+        hipLaunchKernelGGL((k_grid_tb<1, TB>), blocks, threads, 0, stream, sd, nt, nblk, tv, grid);
+    else
+        hipLaunchKernelGGL((k_grid_tb<2, TB>), blocks, threads, 0, stream, sd, nt, nblk, tv, grid);
+    EPIC_HIP_TRY(hipGetLastError());
+    return EPIC_OK;
+}
+
 epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
                         int t0, int nt, float2 *grid, hipStream_t stream)
 {
-    constexpr int TB = 8;
-    const dim3 blocks((nt + TB - 1) / TB, n_chan), threads(256);
+    constexpr int TB = kGridTB;
+    const int npix = sd.nx * sd.ny;
+    const dim3 blocks((nt + TB - 1) / TB, n_chan, (npix + kGridCellBlock - 1) / kGridCellBlock),
+        threads(256);
     KernelTimer timer("grid_gather", stream);
     if (n_pol == 1 && volt_type == EPIC_CI8)
         hipLaunchKernelGGL((k_grid<1, EPIC_CI8, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid);
