@@ -404,9 +404,9 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
     constexpr int PREFETCH = kFused64Prefetch * kFused64Block / BLOCK;
     extern __shared__ float2 lds[];
     float2 *buf = lds;                                   // [2][PLANE], swizzled
-    // gathered box rows at pitch 68 (the 4 pad words keep the row pass's
+    // gathered box rows at pitch 72 (the 8 pad entries keep the row pass's
     // reads of 8 adjacent rows on distinct banks), zero outside the box's columns
-    constexpr int GP = 68;
+    constexpr int GP = 72;
     float2 *gb = buf + NP * PLANE;                       // [2][gb_rows][GP]
     float2 *vf = gb + NP * gb_rows * GP;                 // [2][max_elem][2] voltages
     Tap *taps_l = reinterpret_cast<Tap *>(vf + 2 * NP * max_elem);
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
                         a1.x = fmaf(tp.w, e1.x, a1.x);
                         a1.y = fmaf(tp.w, e1.y, a1.y);
                     }
-                    const int at = cell + ((cell >> 6) << 2);   // row * GP + column
+                    const int at = cell + ((cell >> 6) << 3);   // row * GP + column
                     gb[at] = a0;
                     gb[gb_rows * GP + at] = a1;
                 }
@@ -541,8 +541,19 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
 #pragma unroll
             for (int m = 0; m < 8; ++m) v[m] = gpl[yl * GP + j + 8 * m];
             Dft<8>::run(v);
+            // lanes j >= 4 store their outputs in the order k ^ 4, so that
+            // the two lanes of a row whose positions differ by 32 never
+            // share a bank in one store
+            const bool hi = j >= 4;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) plane[bt ^ k] = v[k];
+            for (int k = 0; k < 4; ++k) {
+                const float2 a = v[k], b = v[k + 4];
+                v[k] = hi ? b : a;
+                v[k + 4] = hi ? a : b;
+            }
+            const int jr = hi ? 4 : 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) plane[bt ^ (k ^ jr)] = v[k];
         }
         __syncthreads();
         // R2: second pass along x, in place
@@ -620,10 +631,10 @@ namespace {
 
 // the 64 x 64 register-resident kernel needs its LDS layout to fit
 // LDS of the two-pol 64 x 64 kernel: the planes, the gathered box as
-// 64-wide rows at pitch 68, two voltage buffers, the channel's taps.
+// 64-wide rows at pitch 72, two voltage buffers, the channel's taps.
 size_t fused64x2_lds_bytes(int max_elem, int ktaps, int max_side)
 {
-    return sizeof(float2) * 2 * 64 * 64 + sizeof(float2) * 2 * 68 * static_cast<size_t>(max_side) +
+    return sizeof(float2) * 2 * 64 * 64 + sizeof(float2) * 2 * 72 * static_cast<size_t>(max_side) +
            sizeof(float2) * 2 * 2 * static_cast<size_t>(max_elem) +
            sizeof(Tap) * static_cast<size_t>(max_elem) * ktaps;
 }
