@@ -36,15 +36,18 @@ constexpr int kGridBoxPre = 8;      // raw voltage words per thread and sample
 constexpr int kF128Block = 512;
 constexpr size_t kF128Lds = sizeof(float2) * (128 * 128 + 8 * kF128Block);   // plane + pol X hold of CB task 3
 
-// LDS position of (row y, column position p) in the 128 x 128 plane.  The XOR
-// of the low 3 bits with bits 3-5 keeps the stride-8 reads of pass B on
-// distinct banks; the XOR of bits 3-4 with the row spreads the 4 to 8 rows a
-// wave touches in the row passes.  Both stay inside each aligned block of 64
-// positions, so the column passes (one row, 64 consecutive positions per
-// wave) are conflict-free as well.
+// LDS position of (row y, column position p) in the 128 x 128 plane.  The LDS
+// serves a 64-bit access a group of lanes at a time, and every group must
+// touch distinct banks: the XOR of the low 3 bits with bits 3-5 spreads the
+// stride-8 reads of pass B, the XOR of bit 0 with bit 6 separates positions
+// 64 apart, and a row-dependent XOR (25 (y mod 4), low 6 bits) spreads the
+// 2 to 8 rows a group touches in the row passes.  All of it stays inside
+// each aligned block of 64 positions, so the column passes (one row, 64
+// consecutive positions per wave) are conflict-free too; the choice was
+// checked exhaustively against every access pattern of this kernel.
 __device__ __forceinline__ int pl(int y, int p)
 {
-    return y * 128 + (p ^ ((p >> 3) & 7) ^ ((y & 3) << 3));
+    return y * 128 + (p ^ ((p >> 3) & 7) ^ (((y & 3) * 25) & 63) ^ ((p >> 6) & 1));
 }
 
 // LDS slot of element e in the gridding kernel's voltage staging.
