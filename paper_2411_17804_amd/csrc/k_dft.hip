@@ -104,10 +104,17 @@ epic_status get_dft_tables(int n, int precision, int device, const void **out)
     return cache_dft_table(n, precision, device, bytes, fill_any, out);
 }
 
+// With chan set (the composed cadence), item item0 + b belongs to channel
+// (item0 + b) / items_per_chan and only the K-steps that cover the channel's footprint
+// along the transformed axis are summed (the rest of the input is zero); on
+// the first axis (axis 0, along y) work-groups whose columns miss the
+// footprint write nothing, since the second pass sums only footprint rows.
 template <int N, int NTW, int PREC>
 __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
                                                   float2 *__restrict__ out, int M,
-                                                  const typename Split<PREC>::vec8 *__restrict__ tab)
+                                                  const typename Split<PREC>::vec8 *__restrict__ tab,
+                                                  const ChanPlan *__restrict__ chan,
+                                                  int64_t item0, int items_per_chan, int axis)
 {
     using S = Split<PREC>;
     using vec8 = typename S::vec8;
@@ -127,12 +134,21 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
     const size_t b = blockIdx.y;
     const int c0 = blockIdx.x * CB;
     const float2 *src = in + b * N * M;
+    int ks_lo = 0, ks_hi = KS - 1;
+    if (chan) {
+        const ChanPlan cp = chan[(item0 + static_cast<int64_t>(b)) / items_per_chan];
+        const int lo = axis == 0 ? cp.y0 : cp.x0, len = axis == 0 ? cp.bh : cp.bw;
+        ks_lo = lo >> 4;
+        ks_hi = (lo + len - 1) >> 4;
+        if (axis == 0 && (c0 + CB <= cp.x0 || c0 >= cp.x0 + cp.bw)) return;
+    }
+    const int j_lo = 16 * ks_lo, nrows = 16 * (ks_hi - ks_lo + 1);
 
     float s = 1.f;
     if constexpr (S::needs_scale) {
         float mx = 0.f;
-        for (int i = threadIdx.x; i < N * CB; i += 256) {
-            const float2 v = src[(i / CB) * M + c0 + i % CB];
+        for (int i = threadIdx.x; i < nrows * CB; i += 256) {
+            const float2 v = src[(j_lo + i / CB) * M + c0 + i % CB];
             mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
         }
         for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
@@ -141,8 +157,8 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
         mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
         s = pow2_scale(mx);
     }
-    for (int i = threadIdx.x; i < N * CB; i += 256) {
-        const int j = i / CB, c = i % CB;
+    for (int i = threadIdx.x; i < nrows * CB; i += 256) {
+        const int j = j_lo + i / CB, c = i % CB;
         const float2 v = src[j * M + c0 + c];
         scalar hr, lr, hi_, li;
         split<PREC>(v.x * s, hr, lr);
@@ -163,7 +179,7 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
         for (int t = 0; t < NTW; ++t) acc[w][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 
     const vec8 *tab_lo = tab + static_cast<size_t>(MT) * KS * 64;
-    for (int ks = 0; ks < KS; ++ks) {
+    for (int ks = ks_lo; ks <= ks_hi; ++ks) {
         vec8 ah[MTW], al[MTW];
 #pragma unroll
         for (int w = 0; w < MTW; ++w) {
@@ -202,9 +218,15 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
 
 namespace {
 
+struct Prune {
+    const ChanPlan *chan;   // null: dense
+    int items_per_chan;
+    int axis;
+};
+
 template <int N, int NTW, int PREC>
 epic_status run_pass(int64_t batch, int m, const float2 *in, float2 *out, const void *tab,
-                     hipStream_t stream)
+                     const Prune &pr, hipStream_t stream)
 {
     constexpr int CB = 16 * NTW;
     const size_t bytes = sizeof(uint32_t) * 2 * CB * (N + 4);
@@ -218,7 +240,8 @@ epic_status run_pass(int64_t batch, int m, const float2 *in, float2 *out, const 
         const int64_t nb = std::min<int64_t>(65535, batch - b0);
         hipLaunchKernelGGL(k, dim3(m / CB, static_cast<unsigned>(nb)), dim3(256), bytes, stream,
                            in + b0 * N * m, out + b0 * N * m, m,
-                           static_cast<const typename Split<PREC>::vec8 *>(tab));
+                           static_cast<const typename Split<PREC>::vec8 *>(tab), pr.chan, b0,
+                           pr.items_per_chan, pr.axis);
         EPIC_HIP_TRY(hipGetLastError());
     }
     return EPIC_OK;
@@ -226,25 +249,25 @@ epic_status run_pass(int64_t batch, int m, const float2 *in, float2 *out, const 
 
 template <int N, int PREC>
 epic_status pass_n(int64_t batch, int m, const float2 *in, float2 *out, const void *tab,
-                   hipStream_t stream)
+                   const Prune &pr, hipStream_t stream)
 {
     // columns per work-group: as many as the accumulators allow
     constexpr int MAX_NTW = N >= 128 ? 2 : 4;
-    if (m >= 16 * MAX_NTW) return run_pass<N, MAX_NTW, PREC>(batch, m, in, out, tab, stream);
-    if (m >= 32) return run_pass<N, 2, PREC>(batch, m, in, out, tab, stream);
-    return run_pass<N, 1, PREC>(batch, m, in, out, tab, stream);
+    if (m >= 16 * MAX_NTW) return run_pass<N, MAX_NTW, PREC>(batch, m, in, out, tab, pr, stream);
+    if (m >= 32) return run_pass<N, 2, PREC>(batch, m, in, out, tab, pr, stream);
+    return run_pass<N, 1, PREC>(batch, m, in, out, tab, pr, stream);
 }
 
 template <int PREC>
 epic_status pass_any(int n, int64_t batch, int m, const float2 *in, float2 *out, const void *tab,
-                     hipStream_t stream)
+                     const Prune &pr, hipStream_t stream)
 {
     switch (n) {
-    case 16: return pass_n<16, PREC>(batch, m, in, out, tab, stream);
-    case 32: return pass_n<32, PREC>(batch, m, in, out, tab, stream);
-    case 64: return pass_n<64, PREC>(batch, m, in, out, tab, stream);
-    case 128: return pass_n<128, PREC>(batch, m, in, out, tab, stream);
-    case 256: return pass_n<256, PREC>(batch, m, in, out, tab, stream);
+    case 16: return pass_n<16, PREC>(batch, m, in, out, tab, pr, stream);
+    case 32: return pass_n<32, PREC>(batch, m, in, out, tab, pr, stream);
+    case 64: return pass_n<64, PREC>(batch, m, in, out, tab, pr, stream);
+    case 128: return pass_n<128, PREC>(batch, m, in, out, tab, pr, stream);
+    case 256: return pass_n<256, PREC>(batch, m, in, out, tab, pr, stream);
     }
     return fail(EPIC_ERR_INTERNAL, "dft pass: unexpected size");
 }
@@ -252,8 +275,10 @@ epic_status pass_any(int n, int64_t batch, int m, const float2 *in, float2 *out,
 }  // namespace
 
 epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, const float2 *in,
-                              float2 *out, int device, hipStream_t stream)
+                              float2 *out, int device, hipStream_t stream, const ChanPlan *chan,
+                              int items_per_chan)
 {
+    const Prune p1{chan, items_per_chan, 0}, p2{chan, items_per_chan, 1};
     const void *tab_y = nullptr, *tab_x = nullptr;
     epic_status s = get_dft_tables(ny, precision, device, &tab_y);
     if (s != EPIC_OK) return s;
@@ -265,13 +290,13 @@ epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, cons
     float2 *mid = static_cast<float2 *>(ws);
     // pass 1: along y (input [ny][nx]) -> [nx][ny]; pass 2: along x -> [ny][nx]
     if (precision == EPIC_FP16_SPLIT) {
-        s = pass_any<EPIC_FP16_SPLIT>(ny, batch, nx, in, mid, tab_y, stream);
+        s = pass_any<EPIC_FP16_SPLIT>(ny, batch, nx, in, mid, tab_y, p1, stream);
         if (s != EPIC_OK) return s;
-        return pass_any<EPIC_FP16_SPLIT>(nx, batch, ny, mid, out, tab_x, stream);
+        return pass_any<EPIC_FP16_SPLIT>(nx, batch, ny, mid, out, tab_x, p2, stream);
     }
-    s = pass_any<EPIC_BF16_SPLIT>(ny, batch, nx, in, mid, tab_y, stream);
+    s = pass_any<EPIC_BF16_SPLIT>(ny, batch, nx, in, mid, tab_y, p1, stream);
     if (s != EPIC_OK) return s;
-    return pass_any<EPIC_BF16_SPLIT>(nx, batch, ny, mid, out, tab_x, stream);
+    return pass_any<EPIC_BF16_SPLIT>(nx, batch, ny, mid, out, tab_x, p2, stream);
 }
 
 }  // namespace epic
