@@ -207,25 +207,37 @@ def image(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K, sigma_c
     return out
 
 
-def grid_visibilities(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K,
-                      sigma_cells, volts, lib=None):
-    """FFT-correlator output of one station written out directly, per channel.
-
-    Eq. 4: the time-averaged visibilities, autocorrelations included,
-        V_ab^{pq} = mean_t E_a^p(t) conj(E_b^q(t));
-    Eq. 6 gridding: each is placed at its baseline cell c_a - c_b with the
-    cross-correlation of the two elements' kernels (extent 2K - 1 per axis),
-        G^{pq}[j] = sum_{a,b} sum_{d1,d2} w_a(d1) w_b(d2) V_ab^{pq}
-                    [j = (c_a + d1) - (c_b + d2) mod (nx, ny)].
-    No transform is involved; on the circular grid G is the inverse transform
-    of the EPIC image.  Cells and weights come from plan().  volts as for
-    image(); returns complex128 [n_chan, n_pol*n_pol, ny, nx]."""
-    lib = lib or load()
+def visibilities(volts):
+    """Eq. 4, the correlator of the XFFT architecture (Sec. 5.4): per channel the
+    mean over the cadence of E_a^p(t) conj(E_b^q(t)) for every ordered element
+    pair (autocorrelations included) and every pol pair, in FP64.  volts as for
+    image(); returns complex128 [n_chan, n_elem, n_pol, n_elem, n_pol] (row
+    (a, p), column (b, q)).  Each channel's matrix is X^T conj(X) / n_time for
+    X = the [n_time, n_elem * n_pol] voltage matrix (one library matmul)."""
     if volts.dtype == np.int8:
         v = volts[..., 0].astype(np.float64) + 1j * volts[..., 1].astype(np.float64)
     else:
         v = volts.astype(np.complex128)
     n_chan, n_time, n_elem, n_pol = v.shape[:4]
+    X = v.reshape(n_chan, n_time, n_elem * n_pol)
+    out = np.empty((n_chan, n_elem * n_pol, n_elem * n_pol), np.complex128)
+    for c in range(n_chan):
+        out[c] = (X[c].T @ np.conj(X[c])) / n_time
+    return out.reshape(n_chan, n_elem, n_pol, n_elem, n_pol)
+
+
+def grid_visibility_matrix(vis, pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K,
+                           sigma_cells, lib=None):
+    """Eq. 6 gridding (no transform) of given visibilities vis
+    [n_chan, n_elem, n_pol, n_elem, n_pol] (as visibilities() returns): each
+    V_ab^{pq} is placed at its baseline cell c_a - c_b with the
+    cross-correlation of the two elements' kernels (extent 2K - 1 per axis),
+        G^{pq}[j] = sum_{a,b} sum_{d1,d2} w_a(d1) w_b(d2) V_ab^{pq}
+                    [j = (c_a + d1) - (c_b + d2) mod (nx, ny)].
+    Cells and weights come from plan(); returns complex128
+    [n_chan, n_pol*n_pol, ny, nx]."""
+    lib = lib or load()
+    n_chan, n_elem, n_pol = vis.shape[0], vis.shape[1], vis.shape[2]
     h = (K - 1) // 2
     out = np.zeros((n_chan, n_pol * n_pol, ny, nx), np.complex128)
     for c in range(n_chan):
@@ -233,7 +245,6 @@ def grid_visibilities(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type
                               sigma_cells, lib=lib)
         ix = ix.astype(np.int64)
         iy = iy.astype(np.int64)
-        V = np.einsum("tap,tbq->pqab", v[c], np.conj(v[c])) / n_time
         for d1y in range(-h, h + 1):
             for d1x in range(-h, h + 1):
                 wa = wx[:, d1x + h] * wy[:, d1y + h]
@@ -245,8 +256,20 @@ def grid_visibilities(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type
                         wab = wa[:, None] * wb[None, :]
                         for p in range(n_pol):
                             for q in range(n_pol):
-                                np.add.at(out[c, p * n_pol + q], (cy, cx), wab * V[p, q])
+                                np.add.at(out[c, p * n_pol + q], (cy, cx),
+                                          wab * vis[c, :, p, :, q])
     return out
+
+
+def grid_visibilities(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K,
+                      sigma_cells, volts, lib=None):
+    """FFT-correlator output of one station written out directly, per channel:
+    the visibilities of Eq. 4 (visibilities()) gridded as in Eq. 6
+    (grid_visibility_matrix()).  No transform is involved; on the circular
+    grid the result is the inverse transform of the EPIC image.  volts as for
+    image(); returns complex128 [n_chan, n_pol*n_pol, ny, nx]."""
+    return grid_visibility_matrix(visibilities(volts), pos_m, wavelengths_m, grid_spacing_wl, nx,
+                                  ny, kernel_type, K, sigma_cells, lib=lib)
 
 
 def combine_incoherent(images, weights=None):

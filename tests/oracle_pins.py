@@ -25,6 +25,11 @@ What each pin is tied to:
                             transform): explicit values for elements on cell
                             centres, the total equals the mean beam power at
                             zero, Hermitian symmetry between XY and YX.
+* pin_visibility_correlator -- Eq. 4 on its own: element tones give
+                            V_ab^{pq} = A_a^p conj(A_b^q) exactly; orthogonal
+                            (Hadamard) codes give the identity matrix; random
+                            voltages give a Hermitian positive semi-definite
+                            matrix whose diagonal is the mean power.
 * pin_incoherent_combination -- Eq. 7 as a weighted mean: invariant under a
                             per-pixel rescaling of the weights, returns a lone
                             weighted station or identical images unchanged,
@@ -57,6 +62,7 @@ PIN_TOL = {
     "point_source_offset": 1e-12,
     "visibility_closed_forms": 1e-12,
     "incoherent_combination": 1e-13,
+    "visibility_correlator": 1e-12,
     "xfft_equivalence": 1e-12,
     "translation": 1e-12,
     "pol_symmetry": 0.0,
@@ -225,6 +231,38 @@ def pin_visibility_closed_forms(lib):
     return err
 
 
+def pin_visibility_correlator(lib, vis_fn=None):
+    # (a) a tone per element and pol, E_a^p(t) = A_a^p exp(i w t): the mean
+    # product is A_a^p conj(A_b^q) whatever w and n_time; (b) orthogonal +-1
+    # codes (rows of a Sylvester-Hadamard matrix) with per-element phases give
+    # the identity; (c) random voltages: Hermitian, PSD, diagonal = mean power
+    vis_fn = vis_fn or oracle.visibilities
+    rng = _rng(14)
+    n_el, n_pol, n_time = 5, 2, 7
+    A = _cnormal(rng, (n_el, n_pol))
+    t = np.arange(n_time)
+    E = A[None, :, :] * np.exp(1j * 0.7731 * t)[:, None, None]
+    V = vis_fn(E[None])[0]
+    want = A[:, :, None, None] * np.conj(A)[None, None, :, :]
+    err = _rel(V, want)
+    H = np.array([[1.0]])
+    while H.shape[0] < 8:
+        H = np.block([[H, H], [H, -H]])
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, 8))
+    E = (H.T * ph[None, :])[:, :, None]                       # [t, a, 1]
+    V = vis_fn(E[None])[0, :, 0, :, 0]
+    err = max(err, float(np.abs(V - np.eye(8)).max()))
+    E = _cnormal(rng, (2, 11, 4, 2))
+    V = vis_fn(E).reshape(2, 8, 8)
+    for c in range(2):
+        err = max(err, _rel(V[c], np.conj(V[c].T)))
+        ev = np.linalg.eigvalsh(0.5 * (V[c] + np.conj(V[c].T)))
+        err = max(err, max(0.0, -ev.min()) / ev.max())
+        power = np.mean(np.abs(E[c].reshape(11, 8)) ** 2, axis=0)
+        err = max(err, _rel(np.diag(V[c]), power))
+    return err
+
+
 def pin_incoherent_combination(lib):
     # Eq. 7 as weighted mean: invariant under a per-pixel rescaling of all
     # weights; a single weighted station is returned as it is; identical
@@ -339,6 +377,7 @@ ALL_PINS = {
     "xfft_equivalence": pin_xfft_equivalence,
     "visibility_closed_forms": pin_visibility_closed_forms,
     "incoherent_combination": pin_incoherent_combination,
+    "visibility_correlator": pin_visibility_correlator,
     "translation": pin_translation,
     "pol_symmetry": pin_pol_symmetry,
     "golden_two_element": pin_golden_two_element,

@@ -58,6 +58,44 @@ def test_ci8_conversion_is_exact(lib):
     assert np.array_equal(a, b)
 
 
+def _vis_mutants():
+    # plausible slips in the Python correlator (Eq. 4), planted on the CPU
+    def prep(volts):
+        if volts.dtype == np.int8:
+            return volts[..., 0].astype(np.float64) + 1j * volts[..., 1]
+        return volts.astype(np.complex128)
+
+    def no_conj(volts):
+        v = prep(volts)
+        X = v.reshape(v.shape[0], v.shape[1], -1)
+        return np.stack([x.T @ x / v.shape[1] for x in X]).reshape(
+            v.shape[0], v.shape[2], v.shape[3], v.shape[2], v.shape[3])
+
+    def conj_first(volts):
+        v = prep(volts)
+        X = v.reshape(v.shape[0], v.shape[1], -1)
+        return np.stack([np.conj(x.T) @ x / v.shape[1] for x in X]).reshape(
+            v.shape[0], v.shape[2], v.shape[3], v.shape[2], v.shape[3])
+
+    def sum_not_mean(volts):
+        return oracle.visibilities(volts) * prep(volts).shape[1]
+
+    def pol_major(volts):
+        v = prep(volts)
+        n_c, n_t, n_e, n_p = v.shape
+        X = np.transpose(v, (0, 1, 3, 2)).reshape(n_c, n_t, -1)     # rows (p, a), read as (a, p)
+        return np.stack([x.T @ np.conj(x) / n_t for x in X]).reshape(n_c, n_e, n_p, n_e, n_p)
+
+    return {"no_conj": no_conj, "conj_first": conj_first, "sum_not_mean": sum_not_mean,
+            "pol_major": pol_major}
+
+
+@pytest.mark.parametrize("mutant", sorted(_vis_mutants()))
+def test_correlator_pin_catches_mistakes(lib, mutant):
+    err = P.pin_visibility_correlator(lib, vis_fn=_vis_mutants()[mutant])
+    assert not err <= P.PIN_TOL["visibility_correlator"], mutant
+
+
 # (source fragment, replacement) -- each a plausible slip in the oracle
 MUTANTS = {
     "transform_sign": ("const double ang = EO_TWO_PI *", "const double ang = -EO_TWO_PI *"),
