@@ -197,6 +197,51 @@ epic_status combine_incoherent(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_
                                const float *weights, void *out, hipStream_t stream);
 
 /*
+ * Correlator of the XFFT architecture (Sec. 5.4, Eq. 4): the visibilities of
+ * one station, for every channel c, ordered element pair (a, b)
+ * (autocorrelations included) and pol pair (p, q),
+ *     vis[c][a][p][b][q] = (1/n_time) sum_t E_a^p(t) conj(E_b^q(t)),
+ * i.e. per channel the R x R matrix X X^H / n_time of the rows r = a*n_pol + p
+ * (R = n_elem*n_pol; Hermitian, both triangles written).
+ * common, station: as for image_cadence (station->volts is read; positions,
+ *         grid and image are not used);
+ * vis:    device, cf32 [n_chan][n_elem][n_pol][n_elem][n_pol], caller-owned.
+ * ci8 voltages are summed exactly in 32-bit integers on the int8 matrix cores
+ * (n_time of any length: longer cadences are summed in segments of 65472
+ * samples) and scaled by 1/n_time in FP32; cf32 voltages are summed in FP32
+ * on the FP32 matrix cores.  Deterministic.
+ * Errors: EPIC_ERR_INVALID_ARG for arguments as image_cadence (plus vis
+ * NULL); EPIC_ERR_UNSUPPORTED for n_elem > 65535.
+ */
+epic_status xfft_correlate(const epic_common *common, const epic_station *station, void *vis,
+                           hipStream_t stream);
+
+/*
+ * Imaging stage of the XFFT architecture (Sec. 5.4, Eq. 6): grids the
+ * visibilities of xfft_correlate at their baseline cells c_a - c_b with the
+ * cross-correlation of the two elements' kernels,
+ *     G[c][p*n_pol+q][j] = sum_{a,b} sum_{i,m} w_a(i) w_b(m) vis[c][a][p][b][q]
+ *                          over j = (c_a + i) - (c_b + m) mod (nx, ny),
+ * and transforms G as Eq. 3 does (+ sign, unnormalised, natural order) into
+ * station->image [n_chan][n_pol^2][ny][nx]: the same polarised intensities
+ * image_cadence returns (Wiener-Khinchin on the circular grid), up to FP32
+ * rounding.  Cells and weights are those of Eq. 3's gridding (the station's
+ * positions, kernel and grid, per channel's wavelength).
+ * vis:     device cf32 as xfft_correlate writes it;
+ * gridded: device cf32 [n_chan][n_pol^2][ny][nx] that receives G (the
+ *          gridded visibilities), or NULL (a library workspace is used);
+ * station->volts may be NULL.  The per-station plan (every element pair
+ * sorted by baseline cell, n_elem^2 * n_chan entries of 4 bytes) is built on
+ * the host once per geometry and cached like image_cadence's.  FP32 sums in a
+ * fixed order (deterministic).
+ * Errors: EPIC_ERR_INVALID_ARG as image_cadence (footprint off the grid
+ * included); EPIC_ERR_UNSUPPORTED for n_elem > 65535, n_elem^2 * n_chan >
+ * 2^31, or a visibility kernel (2K - 1 cells) wider than the grid.
+ */
+epic_status xfft_image(const epic_common *common, const epic_station *station, const void *vis,
+                       void *gridded, hipStream_t stream);
+
+/*
  * Tile tuning (auxiliary).  image_cadence runs every station whose grid is
  * square and at most 64 x 64 (and, in FP32, every 128 x 128 one) in fused
  * kernels that process one (station, channel, time chunk) item per

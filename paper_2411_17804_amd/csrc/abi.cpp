@@ -1,6 +1,7 @@
 // abi.cpp -- the C ABI of include/epic.h: argument validation, plan lookup
 // and dispatch to the HIP kernels.  No device work happens before every
 // argument has been checked.
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -50,7 +51,7 @@ epic_status check_common(const epic_common *c)
     return EPIC_OK;
 }
 
-epic_status check_station(const epic_station *s, int idx)
+epic_status check_station(const epic_station *s, int idx, bool need_volts = true)
 {
     const std::string who = "station " + std::to_string(idx) + ": ";
     if (s->n_elem < 1) return fail(EPIC_ERR_INVALID_ARG, who + "n_elem must be >= 1");
@@ -68,7 +69,7 @@ epic_status check_station(const epic_station *s, int idx)
         return fail(EPIC_ERR_INVALID_ARG, who + "NEAREST kernel needs support 1");
     if (k.type == EPIC_KERNEL_GAUSSIAN && (!std::isfinite(k.sigma_cells) || !(k.sigma_cells > 0.0)))
         return fail(EPIC_ERR_INVALID_ARG, who + "Gaussian sigma_cells must be finite and > 0");
-    if (!s->volts) return fail(EPIC_ERR_INVALID_ARG, who + "volts is NULL");
+    if (need_volts && !s->volts) return fail(EPIC_ERR_INVALID_ARG, who + "volts is NULL");
     return EPIC_OK;
 }
 
@@ -291,6 +292,63 @@ epic_status combine_incoherent(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_
     }
     return launch_combine(imgs, n_stations, n_pol * n_pol * nx * ny, n_chan, weights,
                           static_cast<float2 *>(out), stream);
+}
+
+epic_status xfft_correlate(const epic_common *common, const epic_station *station, void *vis,
+                           hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!station) return fail(EPIC_ERR_INVALID_ARG, "station is NULL");
+    st = check_station(station, 0);
+    if (st != EPIC_OK) return st;
+    if (!vis) return fail(EPIC_ERR_INVALID_ARG, "vis is NULL");
+    if (station->n_elem > 65535) return fail(EPIC_ERR_UNSUPPORTED, "correlator: more than 65535 elements");
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    return launch_xcorr(station->volts, common->volt_type, station->n_elem * common->n_pol,
+                        common->n_chan, common->n_time, static_cast<float2 *>(vis), stream);
+}
+
+epic_status xfft_image(const epic_common *common, const epic_station *station, const void *vis,
+                       void *gridded, hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!station) return fail(EPIC_ERR_INVALID_ARG, "station is NULL");
+    st = check_station(station, 0, false);
+    if (st != EPIC_OK) return st;
+    if (!vis) return fail(EPIC_ERR_INVALID_ARG, "vis is NULL");
+    if (!station->image) return fail(EPIC_ERR_INVALID_ARG, "station image is NULL");
+    if (2 * station->kernel.support - 1 > std::min(station->nx, station->ny))
+        return fail(EPIC_ERR_UNSUPPORTED, "visibility kernel wider than the grid");
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    XfftPlanHandle pl;
+    st = get_xfft_plan(common, station, dev, &pl);
+    if (st != EPIC_OK) return st;
+    const int n_pol = common->n_pol, nx = station->nx, ny = station->ny;
+    const int64_t batch = static_cast<int64_t>(common->n_chan) * n_pol * n_pol;
+    float2 *g = static_cast<float2 *>(gridded);
+    if (!g) {
+        void *ws = nullptr;
+        st = get_workspace(dev, stream, 4, sizeof(float2) * static_cast<size_t>(batch) * nx * ny, &ws);
+        if (st != EPIC_OK) return st;
+        g = static_cast<float2 *>(ws);
+    }
+    const int W = 2 * station->kernel.support - 1;
+    void *part = nullptr;
+    st = get_workspace(dev, stream, 5, sizeof(float2) * static_cast<size_t>(batch) * W * W * nx * ny,
+                       &part);
+    if (st != EPIC_OK) return st;
+    st = launch_vis_grid(static_cast<const float2 *>(vis), pl, n_pol, station->n_elem,
+                         common->n_chan, nx, ny, static_cast<float2 *>(part), g, stream);
+    if (st != EPIC_OK) return st;
+    return launch_fft2_f32(nx, ny, batch, g, static_cast<float2 *>(station->image), dev, stream);
 }
 
 epic_status image_cadence(const epic_common *common, const epic_station *stations,

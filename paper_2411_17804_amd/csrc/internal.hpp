@@ -108,6 +108,29 @@ struct PlanHandle {
     int64_t n_taps_total = 0;
 };
 
+// Plan of the XFFT route (Eq. 6 gridding of visibilities) of one station.
+// Per channel c (fixed strides): elem_w[c][a][2K] = (wx[0..K), wy[0..K)) of
+// element a; the non-empty baseline cells ("centres") cent_cell[c][i]
+// (x | y << 16) in raster order, their pair ranges
+// cent_start[c][i..i+1] (offsets into pairs[c][n_elem^2]); pairs are
+// (a | b << 16) with ascending (a, b) inside a centre.  cell_cent[c][cell] is
+// the centre index of a cell (-1 if no pair lands there) and cent_base[c] the
+// number of centres of the channels before c (cent_base[n_chan] =
+// n_cent_total).
+struct XfftPlanHandle {
+    const float *elem_w = nullptr;
+    const int32_t *cent_cell = nullptr;
+    const int32_t *cent_start = nullptr;
+    const uint32_t *pairs = nullptr;
+    const int32_t *cell_cent = nullptr;
+    const int64_t *cent_base = nullptr;
+    int64_t n_cent_total = 0;
+    int32_t K = 0;
+};
+
+epic_status get_xfft_plan(const epic_common *common, const epic_station *st, int device,
+                          XfftPlanHandle *out);
+
 // Host-only geometry check (no device needed).
 epic_status check_geometry(const epic_common *common, const epic_station *st);
 
@@ -154,6 +177,16 @@ bool timing_on();
 // ---------------------------------------------------------------------------
 epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
                         int t0, int nt, float2 *grid, hipStream_t stream);
+
+// XFFT route (k_xfft.hip).  Correlator (Eq. 4): vis[c][R][R] (R = n_elem *
+// n_pol rows in voltage order) = mean over n_time of X X^H.
+epic_status launch_xcorr(const void *volts, int volt_type, int R, int n_chan, int n_time,
+                         float2 *vis, hipStream_t stream);
+// Eq. 6 gridding of vis into grid[c][n_pol^2][ny][nx] (no transform);
+// part is a device buffer of n_chan * (2K-1)^2 * n_pol^2 * nx * ny float2.
+epic_status launch_vis_grid(const float2 *vis, const XfftPlanHandle &pl, int n_pol, int n_elem,
+                            int n_chan, int nx, int ny, float2 *part, float2 *grid,
+                            hipStream_t stream);
 
 // Gridding of large stations through a sample-blocked copy of the voltages:
 // tv is a device buffer of n_chan * ceil(nt / 8) * n_elem * 8 * n_pol float2.

@@ -73,6 +73,11 @@ struct Workspace {
     size_t bytes = 0;
 };
 static std::map<std::tuple<int, uintptr_t, int>, Workspace> g_ws;
+struct XfftEntry {
+    void *dev = nullptr;
+    XfftPlanHandle h;
+};
+static std::unordered_map<std::string, XfftEntry> g_xplans;
 
 static void append(std::string &k, const void *p, size_t n)
 {
@@ -114,6 +119,28 @@ static bool element_taps(double x, double y, double delta, int nx, int ny, const
     return true;
 }
 
+// Cache key of a station's geometry on one device (everything a plan depends on).
+static std::string geometry_key(const epic_common *common, const epic_station *st, int device)
+{
+    const int n_chan = common->n_chan;
+    const int n_elem = st->n_elem;
+    const int K = st->kernel.support;
+    std::string key;
+    key.reserve(64 + sizeof(double) * (2 * n_elem + n_chan));
+    append(key, &device, sizeof device);
+    append(key, &n_elem, sizeof n_elem);
+    append(key, &st->nx, sizeof st->nx);
+    append(key, &st->ny, sizeof st->ny);
+    append(key, &st->kernel.type, sizeof st->kernel.type);
+    append(key, &K, sizeof K);
+    append(key, &st->kernel.sigma_cells, sizeof st->kernel.sigma_cells);
+    append(key, &common->grid_spacing_wl, sizeof common->grid_spacing_wl);
+    append(key, &n_chan, sizeof n_chan);
+    append(key, common->wavelength_m, sizeof(double) * n_chan);
+    append(key, st->pos_m, sizeof(double) * 2 * n_elem);
+    return key;
+}
+
 epic_status check_geometry(const epic_common *common, const epic_station *st)
 {
     const int K = st->kernel.support;
@@ -139,19 +166,7 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     const int n_chan = common->n_chan;
     const int n_elem = st->n_elem;
     const int K = st->kernel.support;
-    std::string key;
-    key.reserve(64 + sizeof(double) * (2 * n_elem + n_chan));
-    append(key, &device, sizeof device);
-    append(key, &n_elem, sizeof n_elem);
-    append(key, &st->nx, sizeof st->nx);
-    append(key, &st->ny, sizeof st->ny);
-    append(key, &st->kernel.type, sizeof st->kernel.type);
-    append(key, &K, sizeof K);
-    append(key, &st->kernel.sigma_cells, sizeof st->kernel.sigma_cells);
-    append(key, &common->grid_spacing_wl, sizeof common->grid_spacing_wl);
-    append(key, &n_chan, sizeof n_chan);
-    append(key, common->wavelength_m, sizeof(double) * n_chan);
-    append(key, st->pos_m, sizeof(double) * 2 * n_elem);
+    std::string key = geometry_key(common, st, device);
 
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_plans.find(key);
@@ -352,12 +367,136 @@ epic_status get_workspace(int device, hipStream_t stream, int slot, size_t bytes
     return EPIC_OK;
 }
 
+// ------------------------------------------------------------- XFFT plans --
+// Eq. 6 gridding of visibilities.  Per channel: every element's nearest cell
+// and separable weights (as for Eq. 3), and every ordered element pair (a, b)
+// sorted by its baseline cell c_a - c_b (mod the grid), the "centre" of the
+// pair's (2K-1)^2 footprint.  Centres (cells that hold at least one pair)
+// are kept in raster order: neighbouring cells have similar pair counts, and
+// the per-centre partial sums of a channel then lie in cell order.
+epic_status get_xfft_plan(const epic_common *common, const epic_station *st, int device,
+                          XfftPlanHandle *out)
+{
+    const int n_chan = common->n_chan;
+    const int n_elem = st->n_elem;
+    const int K = st->kernel.support;
+    const int nx = st->nx, ny = st->ny, npix = nx * ny;
+    const int64_t n_pairs = static_cast<int64_t>(n_elem) * n_elem;
+    if (n_elem > 65535)
+        return fail(EPIC_ERR_UNSUPPORTED, "XFFT plan: more than 65535 elements");
+    if (n_pairs * n_chan > (int64_t{1} << 31))
+        return fail(EPIC_ERR_UNSUPPORTED,
+                    "XFFT plan: n_elem^2 * n_chan exceeds 2^31 element pairs; call with fewer "
+                    "channels at a time");
+    std::string key = geometry_key(common, st, device);
+    key.push_back('X');
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_xplans.find(key);
+    if (it != g_xplans.end()) {
+        *out = it->second.h;
+        return EPIC_OK;
+    }
+    std::vector<float> elem_w(static_cast<size_t>(n_chan) * n_elem * 2 * K);
+    std::vector<int32_t> cent_cell(static_cast<size_t>(n_chan) * npix, 0);
+    std::vector<int32_t> cent_start(static_cast<size_t>(n_chan) * (npix + 1), 0);
+    std::vector<int32_t> cell_cent(static_cast<size_t>(n_chan) * npix, -1);
+    std::vector<int64_t> cent_base(static_cast<size_t>(n_chan) + 1, 0);
+    std::vector<uint32_t> pairs(static_cast<size_t>(n_pairs) * n_chan);
+    std::vector<int> ci(n_elem), cj(n_elem);
+    std::vector<double> wx(K), wy(K);
+    std::vector<int32_t> count(npix), slot(npix), order;
+    order.reserve(npix);
+    for (int c = 0; c < n_chan; ++c) {
+        const double delta = common->grid_spacing_wl * common->wavelength_m[c];
+        float *ew = elem_w.data() + static_cast<size_t>(c) * n_elem * 2 * K;
+        for (int a = 0; a < n_elem; ++a) {
+            if (!element_taps(st->pos_m[2 * a], st->pos_m[2 * a + 1], delta, nx, ny, st->kernel,
+                              &ci[a], &cj[a], wx.data(), wy.data()))
+                return fail(EPIC_ERR_INVALID_ARG,
+                            "element " + std::to_string(a) + " kernel footprint leaves the grid at channel " +
+                                std::to_string(c));
+            for (int d = 0; d < K; ++d) {
+                ew[static_cast<size_t>(a) * 2 * K + d] = static_cast<float>(wx[d]);
+                ew[static_cast<size_t>(a) * 2 * K + K + d] = static_cast<float>(wy[d]);
+            }
+        }
+        auto centre = [&](int a, int b) {
+            const int dx = ((ci[a] - ci[b]) % nx + nx) % nx;
+            const int dy = ((cj[a] - cj[b]) % ny + ny) % ny;
+            return dy * nx + dx;
+        };
+        std::fill(count.begin(), count.end(), 0);
+        for (int a = 0; a < n_elem; ++a)
+            for (int b = 0; b < n_elem; ++b) ++count[centre(a, b)];
+        order.clear();
+        for (int i = 0; i < npix; ++i)
+            if (count[i] > 0) order.push_back(i);
+        int32_t *cc = cent_cell.data() + static_cast<size_t>(c) * npix;
+        int32_t *cs = cent_start.data() + static_cast<size_t>(c) * (npix + 1);
+        int32_t run = 0;
+        for (size_t k = 0; k < order.size(); ++k) {
+            const int cell = order[k];
+            cc[k] = (cell % nx) | ((cell / nx) << 16);
+            cs[k] = run;
+            slot[cell] = run;
+            run += count[cell];
+        }
+        cs[order.size()] = run;
+        int32_t *cm = cell_cent.data() + static_cast<size_t>(c) * npix;
+        for (size_t k = 0; k < order.size(); ++k) cm[order[k]] = static_cast<int32_t>(k);
+        cent_base[c + 1] = cent_base[c] + static_cast<int64_t>(order.size());
+        uint32_t *pr = pairs.data() + static_cast<size_t>(c) * n_pairs;
+        for (int a = 0; a < n_elem; ++a)
+            for (int b = 0; b < n_elem; ++b)
+                pr[slot[centre(a, b)]++] = static_cast<uint32_t>(a) | (static_cast<uint32_t>(b) << 16);
+    }
+
+    auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+    const size_t b_w = up(sizeof(float) * elem_w.size());
+    const size_t b_cc = up(sizeof(int32_t) * cent_cell.size());
+    const size_t b_cs = up(sizeof(int32_t) * cent_start.size());
+    const size_t b_pr = up(sizeof(uint32_t) * pairs.size());
+    const size_t b_cm = up(sizeof(int32_t) * cell_cent.size());
+    const size_t b_cb = up(sizeof(int64_t) * cent_base.size());
+    void *dev = nullptr;
+    epic_status s = dev_alloc(&dev, b_w + b_cc + b_cs + b_pr + b_cm + b_cb);
+    if (s != EPIC_OK) return s;
+    char *p = static_cast<char *>(dev);
+    size_t off = 0;
+    hipError_t e = hipSuccess;
+    auto put = [&](const void *src, size_t bytes, size_t span) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(p + off, src, bytes, hipMemcpyHostToDevice);
+        const char *where = p + off;
+        off += span;
+        return where;
+    };
+    XfftPlanHandle hd;
+    hd.elem_w = reinterpret_cast<const float *>(put(elem_w.data(), sizeof(float) * elem_w.size(), b_w));
+    hd.cent_cell = reinterpret_cast<const int32_t *>(put(cent_cell.data(), sizeof(int32_t) * cent_cell.size(), b_cc));
+    hd.cent_start = reinterpret_cast<const int32_t *>(put(cent_start.data(), sizeof(int32_t) * cent_start.size(), b_cs));
+    hd.pairs = reinterpret_cast<const uint32_t *>(put(pairs.data(), sizeof(uint32_t) * pairs.size(), b_pr));
+    hd.cell_cent = reinterpret_cast<const int32_t *>(put(cell_cent.data(), sizeof(int32_t) * cell_cent.size(), b_cm));
+    hd.cent_base = reinterpret_cast<const int64_t *>(put(cent_base.data(), sizeof(int64_t) * cent_base.size(), b_cb));
+    hd.n_cent_total = cent_base[n_chan];
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(e, "XFFT plan upload");
+    }
+    hd.K = K;
+    g_xplans.emplace(std::move(key), XfftEntry{dev, hd});
+    *out = hd;
+    return EPIC_OK;
+}
+
 void clear_all_caches()
 {
     std::lock_guard<std::mutex> lock(g_mu);
     (void)hipDeviceSynchronize();
     for (auto &kv : g_plans) (void)hipFree(kv.second.dev);
     g_plans.clear();
+    for (auto &kv : g_xplans) (void)hipFree(kv.second.dev);
+    g_xplans.clear();
     for (auto &kv : g_twiddles) (void)hipFree(kv.second);
     g_twiddles.clear();
     for (auto &kv : g_dft_tables) (void)hipFree(kv.second);

@@ -24,17 +24,19 @@ __device__ __forceinline__ gptr<T> global_ptr(const void *p)
     return (gptr<T>)(p);
 }
 
-// Element i of a device-global array of a trivially copyable 4-, 8- or
+// Element i of a device-global array of a trivially copyable 2-, 4-, 8- or
 // 16-byte type (structs and HIP vector types included), as a global load.
 template <typename T>
 __device__ __forceinline__ T gload(const void *p, size_t i)
 {
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 2) {
+        return __builtin_bit_cast(T, global_ptr<uint16_t>(p)[i]);
+    } else if constexpr (sizeof(T) == 4) {
         return __builtin_bit_cast(T, global_ptr<uint32_t>(p)[i]);
     } else if constexpr (sizeof(T) == 8) {
         return __builtin_bit_cast(T, global_ptr<uint64_t>(p)[i]);
     } else {
-        static_assert(sizeof(T) == 16, "gload: 4, 8 or 16 bytes");
+        static_assert(sizeof(T) == 16, "gload: 2, 4, 8 or 16 bytes");
         using u32x4 = __attribute__((ext_vector_type(4))) uint32_t;
         return __builtin_bit_cast(T, global_ptr<u32x4>(p)[i]);
     }

@@ -34,7 +34,8 @@ KERNEL_GAUSSIAN = 1
 
 # every function the header declares
 ABI_FUNCTIONS = ("grid_voltages", "fft2_batched", "accumulate_power", "image_cadence",
-                 "image_to_visibilities", "combine_incoherent", "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
+                 "image_to_visibilities", "combine_incoherent", "xfft_correlate", "xfft_image",
+                 "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
                  "epic_timing_reset", "epic_status_string", "epic_last_error",
                  "epic_cache_clear")
 
@@ -89,6 +90,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.image_to_visibilities.restype = i32
     lib.combine_incoherent.argtypes = [i32, i32, i32, i32, i32, P, P, P, P]
     lib.combine_incoherent.restype = i32
+    lib.xfft_correlate.argtypes = [P, P, P, P]
+    lib.xfft_correlate.restype = i32
+    lib.xfft_image.argtypes = [P, P, P, P, P]
+    lib.xfft_image.restype = i32
     lib.epic_autotune.argtypes = [P, P, i32, P]
     lib.epic_autotune.restype = i32
     lib.epic_validate.argtypes = [P, P, i32]
@@ -236,6 +241,26 @@ def combine_incoherent(n_pol: int, nx: int, ny: int, n_chan: int, images, out, w
     ptrs = (ctypes.c_void_p * max(1, len(images)))(*[_dptr(t) for t in images])
     _check(lib.combine_incoherent(n_pol, nx, ny, n_chan, len(images), ptrs if images else None,
                                   _dptr(weights), _dptr(out), _stream(stream)))
+
+
+def xfft_correlate(common: Common, station: Station, vis, stream=None):
+    """Eq. 4 visibilities of one station into vis (device cf32
+    [n_chan][n_elem][n_pol][n_elem][n_pol])."""
+    lib = load()
+    c, keep1 = common.to_c()
+    s, keep2 = station.to_c()
+    _check(lib.xfft_correlate(ctypes.byref(c), ctypes.byref(s), _dptr(vis), _stream(stream)))
+
+
+def xfft_image(common: Common, station: Station, vis, gridded=None, stream=None):
+    """Eq. 6 gridding of vis and the transform into station.image; gridded
+    (device cf32 [n_chan][n_pol^2][ny][nx] or None) receives the gridded
+    visibilities."""
+    lib = load()
+    c, keep1 = common.to_c()
+    s, keep2 = station.to_c()
+    _check(lib.xfft_image(ctypes.byref(c), ctypes.byref(s), _dptr(vis), _dptr(gridded),
+                          _stream(stream)))
 
 
 def _stations_c(stations):

@@ -142,6 +142,33 @@ def test_unfused_calls_reject_bad_shapes_without_a_device():
         epic.grid_voltages(common, station, 0, 0, 0x3000, stream=0)
 
 
+def test_xfft_calls_reject_bad_arguments_without_a_device():
+    common, station = _c2_like()
+    with pytest.raises(epic.EpicError) as e:
+        epic.xfft_correlate(common, station, None, stream=0)
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    with pytest.raises(epic.EpicError) as e:
+        epic.xfft_image(common, station, None, stream=0)
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    common, station = _c2_like(volts=None)
+    with pytest.raises(epic.EpicError) as e:
+        epic.xfft_correlate(common, station, 0x3000, stream=0)        # needs the voltages
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    common, station = _c2_like(image=None)
+    with pytest.raises(epic.EpicError) as e:
+        epic.xfft_image(common, station, 0x3000, stream=0)            # needs the image
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    common, station = _c2_like(n_pol=3)
+    with pytest.raises(epic.EpicError) as e:
+        epic.xfft_correlate(common, station, 0x3000, stream=0)
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    pos = np.zeros((70000, 2))
+    common, station = _c2_like(pos_m=pos)
+    with pytest.raises(epic.EpicError) as e:
+        epic.xfft_correlate(common, station, 0x3000, stream=0)
+    assert e.value.status == epic.EPIC_ERR_UNSUPPORTED
+
+
 def test_struct_layout_matches_header():
     # epic_common: 2 x int32, pointer, double, 3 x int32 (+ pad) ; epic_station as declared
     assert ctypes.sizeof(epic._Common) == 40
