@@ -37,6 +37,8 @@ PEAK_HBM_GBS = 8000.0
 # counts packed FP32 (two FMAs per lane per instruction).
 PEAK_FP32_VALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 PEAK_FP16_MFMA_TFLOPS = 2500.0
+PEAK_INT8_MFMA_TOPS = 5000.0          # dense int8 matrix cores
+PEAK_FP32_MFMA_TFLOPS = 157.3         # dense FP32 matrix cores
 PREC_NAMES = {"fp32": W.FP32_FFT, "fp16": W.FP16_SPLIT, "bf16": W.BF16_SPLIT}
 
 
@@ -384,10 +386,51 @@ def stage_rooflines(cfg, common, station, nt=64, reps=3):
                                    "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
                                    "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
     del wts, copies
+    res.update(xfft_stages(cfg, common, station, timed))
     res["_block"] = f"{cfg.n_chan} channels x {nt} samples x {cfg.n_pol} pols of {st.nx}x{st.ny}"
     del grid, out, acc, img
     torch.cuda.empty_cache()
     return res
+
+
+def xfft_stages(cfg, common, station, timed):
+    """The XFFT route (Sec. 5.4) on the whole cadence of the first station:
+    the correlator of Eq. 4 against the matrix-core roofline of its dtype
+    (algorithmic ops: 8 per complex product, over the R (R + 1) / 2 distinct
+    entries of each channel's Hermitian matrix, R = n_elem * n_pol), the
+    gridding of Eq. 6 plus the transform against HBM (algorithmic bytes: the
+    visibilities read once and the image written once), and the route's
+    image rate in the headline's unit (it returns the same image)."""
+    import torch
+    from paper_2411_17804_amd import epic
+    st = cfg.stations[0]
+    R = st.n_elem * cfg.n_pol
+    vis_bytes = cfg.n_chan * R * R * 8
+    if vis_bytes > (64 << 30):
+        return {"xfft": f"skipped: the visibility matrices take {vis_bytes / 2**30:.0f} GiB"}
+    vis = torch.empty((cfg.n_chan, st.n_elem, cfg.n_pol, st.n_elem, cfg.n_pol, 2),
+                      dtype=torch.float32, device="cuda:0")
+    ms_c = timed(lambda: epic.xfft_correlate(common, station, vis))
+    ms_i = timed(lambda: epic.xfft_image(common, station, vis))
+    ops = cfg.n_chan * R * (R + 1) // 2 * cfg.n_time * 8
+    i8 = cfg.volt_type == W.CI8
+    peak = PEAK_INT8_MFMA_TOPS if i8 else PEAK_FP32_MFMA_TFLOPS
+    img_bytes = cfg.n_chan * cfg.n_pol ** 2 * st.nx * st.ny * 8
+    out = {
+        "xfft_correlate": {"ms": round(ms_c, 3), "bound": "mfma", "dtype": "i8" if i8 else "f32",
+                           "ops": ops, "achieved": round(ops / ms_c / 1e9, 1),
+                           "unit": "TOP/s" if i8 else "TFLOP/s",
+                           "frac": round(ops / ms_c / 1e9 / peak, 4)},
+        "xfft_image": {"ms": round(ms_i, 3), "bound": "hbm", "bytes": vis_bytes + img_bytes,
+                       "achieved": round((vis_bytes + img_bytes) / ms_i / 1e6, 1), "unit": "GB/s",
+                       "frac": round((vis_bytes + img_bytes) / ms_i / 1e6 / PEAK_HBM_GBS, 4)},
+        "xfft_route": {"ms": round(ms_c + ms_i, 3),
+                       "pixel_samples_per_s": cfg.n_chan * cfg.n_time * st.nx * st.ny / (ms_c + ms_i) * 1e3,
+                       "cadence": f"{cfg.n_chan} channels x {cfg.n_time} samples"},
+    }
+    del vis
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(cfg, stations, host_volts, n_sample_chan):
