@@ -207,6 +207,45 @@ def image(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K, sigma_c
     return out
 
 
+def station_beams(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K, sigma_cells,
+                  volts, lib=None):
+    """The station-synthesised electric fields of Sec. 6.2: for every channel
+    and sample, the Eq. 3 transform of the gridded voltages before any
+    squaring, i.e. the station acting as a virtual telescope pointed at every
+    pixel k of its sky grid.  volts as for image(); returns complex128
+    [n_chan, n_time, n_pol, ny, nx]."""
+    lib = lib or load()
+    _, v = _volt_type(volts)
+    n_chan, n_time, n_elem, n_pol = v.shape[:4]
+    out = np.empty((n_chan, n_time, n_pol, ny, nx), np.complex128)
+    for c in range(n_chan):
+        out[c] = fft2(grid(pos_m, wavelengths_m[c], grid_spacing_wl, nx, ny, kernel_type, K,
+                           sigma_cells, volts[c], lib=lib), lib=lib)
+    return out
+
+
+def array_image(beams, pixels, array_pos_m, wavelengths_m, array_spacing_wl, nx, ny,
+                kernel_type, K, sigma_cells, lib=None):
+    """Coherent inter-station EPIC (Sec. 6.2, Eq. 10 then Eq. 9): the M
+    stations are the elements of an array-scale EPIC imager.  For every
+    channel c and selected station pixel k (flat index ky * beam_nx + kx),
+    the fields beams[m][c][t][p][k] of the stations (station_beams() of each)
+    are gridded at the station positions array_pos_m on the array grid,
+    transformed, squared and averaged over the cadence, exactly as image()
+    does for elements.  Returns complex128 [n_chan, n_sel, n_pol^2, ny, nx]."""
+    lib = lib or load()
+    b = np.stack([np.asarray(x, np.complex128) for x in beams])      # [m, c, t, p, by, bx]
+    n_st, n_chan, n_time, n_pol = b.shape[:4]
+    flat = b.reshape(n_st, n_chan, n_time, n_pol, -1)
+    pix = np.asarray(pixels, np.int64)
+    # array-scale voltages of every (channel, pixel) problem: [c, s, t, m, p]
+    v = np.transpose(flat[..., pix], (1, 4, 2, 0, 3))
+    lam = np.repeat(np.asarray(wavelengths_m, np.float64), pix.size)
+    img = image(array_pos_m, lam, array_spacing_wl, nx, ny, kernel_type, K, sigma_cells,
+                np.ascontiguousarray(v.reshape(n_chan * pix.size, n_time, n_st, n_pol)), lib=lib)
+    return img.reshape(n_chan, pix.size, n_pol * n_pol, ny, nx)
+
+
 def visibilities(volts):
     """Eq. 4, the correlator of the XFFT architecture (Sec. 5.4): per channel the
     mean over the cadence of E_a^p(t) conj(E_b^q(t)) for every ordered element

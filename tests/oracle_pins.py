@@ -30,6 +30,15 @@ What each pin is tied to:
                             (Hadamard) codes give the identity matrix; random
                             voltages give a Hermitian positive semi-definite
                             matrix whose diagonal is the mean power.
+* pin_array_point_source  -- Eq. 10 then Eq. 9 over station beams: a plane
+                            wave on every element of M stations, with its
+                            direction on both the station and the array pixel
+                            grids, gives (M n_e)^2 <|A|^2> at the array pixel
+                            of that direction, for the station pixel of that
+                            direction, and that is the image maximum.
+* pin_array_single_station -- one station at the array origin: its
+                            array-scale image is flat and equals its own
+                            station image at the selected pixel.
 * pin_incoherent_combination -- Eq. 7 as a weighted mean: invariant under a
                             per-pixel rescaling of the weights, returns a lone
                             weighted station or identical images unchanged,
@@ -62,6 +71,8 @@ PIN_TOL = {
     "point_source_offset": 1e-12,
     "visibility_closed_forms": 1e-12,
     "incoherent_combination": 1e-13,
+    "array_point_source": 1e-12,
+    "array_single_station": 1e-12,
     "visibility_correlator": 1e-12,
     "xfft_equivalence": 1e-12,
     "translation": 1e-12,
@@ -263,6 +274,69 @@ def pin_visibility_correlator(lib, vis_fn=None):
     return err
 
 
+def _two_level_scene(rng, lams):
+    # elements on station-grid cell centres (nearest kernel, exact), stations
+    # on array-grid cells; a source at l = (1/8, -1/8): station pixel (1, -1)
+    # of a 16-cell grid at lambda/2, array pixel (8, -8) of a 16-cell grid at
+    # 4 lambda, for every lambda used
+    n_el, n_st, n_time = 6, 3, 5
+    cells = rng.choice(7 * 7, n_el, replace=False)
+    elem = np.stack([cells % 7 - 3, cells // 7 - 3], axis=1).astype(np.float64)   # metres
+    sc = rng.choice(7 * 7, n_st, replace=False)
+    cen = np.stack([sc % 7 - 3, sc // 7 - 3], axis=1).astype(np.float64) * 8.0     # metres
+    l = np.array([1.0 / 8, -1.0 / 8])
+    A = _cnormal(rng, (len(lams), n_time))
+    E = np.zeros((n_st, len(lams), n_time, n_el, 1), np.complex128)
+    for m in range(n_st):
+        for c, lam in enumerate(lams):
+            ph = np.exp(-2j * np.pi * ((cen[m] + elem) @ l) / lam)               # [a]
+            E[m, c, :, :, 0] = A[c][:, None] * ph[None, :]
+    return elem, cen, E, A
+
+
+def pin_array_point_source(lib, array_fn=None):
+    array_fn = array_fn or oracle.array_image
+    rng = _rng(15)
+    lams = np.array([2.0, 1.0])
+    elem, cen, E, A = _two_level_scene(rng, lams)
+    n_st, n_el = cen.shape[0], elem.shape[0]
+    beams = [oracle.station_beams(elem, lams, 0.5, 16, 16, oracle.KERNEL_NEAREST, 1, 0.0, E[m],
+                                  lib=lib) for m in range(n_st)]
+    ks = (1 % 16) + 16 * (-1 % 16)                    # station pixel (kx, ky) = (1, -1)
+    other = 3 + 16 * 5
+    img = array_fn(beams, [ks, other], cen, lams, 4.0, 16, 16, oracle.KERNEL_NEAREST, 1, 0.0,
+                   lib=lib)
+    err = 0.0
+    for c in range(len(lams)):
+        want = (n_st * n_el) ** 2 * np.mean(np.abs(A[c]) ** 2)
+        got = img[c, 0, 0]
+        err = max(err, abs(got[-8 % 16, 8] - want) / want)
+        err = max(err, max(0.0, np.abs(got).max() - abs(got[-8 % 16, 8])) / want)
+    return err
+
+
+def pin_array_single_station(lib, array_fn=None):
+    array_fn = array_fn or oracle.array_image
+    rng = _rng(16)
+    lams = np.array([2.0, 1.5])
+    pos = rng.uniform(-2.0, 2.0, (7, 2))
+    E = _cnormal(rng, (2, 6, 7, 2))
+    beams = [oracle.station_beams(pos, lams, 0.5, 16, 16, oracle.KERNEL_GAUSSIAN, 3, 0.5, E,
+                                  lib=lib)]
+    st_img = oracle.image(pos, lams, 0.5, 16, 16, oracle.KERNEL_GAUSSIAN, 3, 0.5, E, lib=lib)
+    pix = [0, 5 + 16 * 2, 15 + 16 * 9]
+    img = array_fn(beams, pix, np.zeros((1, 2)), lams, 2.0, 16, 16, oracle.KERNEL_NEAREST, 1, 0.0,
+                   lib=lib)
+    err = 0.0
+    for c in range(2):
+        for si, k in enumerate(pix):
+            want = st_img[c][:, k // 16, k % 16]                   # the 4 products at pixel k
+            got = img[c, si]
+            scale = np.abs(want).max()
+            err = max(err, float(np.abs(got - want[:, None, None]).max()) / scale)
+    return err
+
+
 def pin_incoherent_combination(lib):
     # Eq. 7 as weighted mean: invariant under a per-pixel rescaling of all
     # weights; a single weighted station is returned as it is; identical
@@ -377,6 +451,8 @@ ALL_PINS = {
     "xfft_equivalence": pin_xfft_equivalence,
     "visibility_closed_forms": pin_visibility_closed_forms,
     "incoherent_combination": pin_incoherent_combination,
+    "array_point_source": pin_array_point_source,
+    "array_single_station": pin_array_single_station,
     "visibility_correlator": pin_visibility_correlator,
     "translation": pin_translation,
     "pol_symmetry": pin_pol_symmetry,

@@ -96,6 +96,33 @@ def test_correlator_pin_catches_mistakes(lib, mutant):
     assert not err <= P.PIN_TOL["visibility_correlator"], mutant
 
 
+def _array_mutants():
+    # plausible slips in the Python inter-station composition (Eq. 10), on the CPU
+    def build(transpose_pix=False, conj=False, lam0=False, rev_st=False):
+        def fn(beams, pixels, array_pos_m, wavelengths_m, *rest, lib=None):
+            b = [np.conj(x) if conj else x for x in beams]
+            if rev_st:
+                b = b[::-1]
+            pix = np.asarray(pixels)
+            if transpose_pix:
+                ny, nx = np.asarray(beams[0]).shape[-2:]
+                pix = (pix % nx) * ny + pix // nx
+            lam = np.full_like(np.asarray(wavelengths_m, float), wavelengths_m[0]) if lam0 else wavelengths_m
+            return oracle.array_image(b, pix, array_pos_m, lam, *rest, lib=lib)
+        return fn
+
+    return {"transposed_pixel": build(transpose_pix=True), "conj_beams": build(conj=True),
+            "first_wavelength": build(lam0=True), "stations_reversed": build(rev_st=True)}
+
+
+@pytest.mark.parametrize("mutant", sorted(_array_mutants()))
+def test_array_pins_catch_mistakes(lib, mutant):
+    fn = _array_mutants()[mutant]
+    errs = [P.pin_array_point_source(lib, array_fn=fn), P.pin_array_single_station(lib, array_fn=fn)]
+    assert not (errs[0] <= P.PIN_TOL["array_point_source"]
+                and errs[1] <= P.PIN_TOL["array_single_station"]), (mutant, errs)
+
+
 # (source fragment, replacement) -- each a plausible slip in the oracle
 MUTANTS = {
     "transform_sign": ("const double ang = EO_TWO_PI *", "const double ang = -EO_TWO_PI *"),
