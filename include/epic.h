@@ -242,6 +242,44 @@ epic_status xfft_image(const epic_common *common, const epic_station *station, c
                        void *gridded, hipStream_t stream);
 
 /*
+ * Coherent inter-station EPIC (Sec. 6.2, Eq. 10 then Eq. 9): the M stations
+ * of an array act as the elements of an array-scale EPIC imager.  Each
+ * station's synthesised field towards the directions of its sky grid (the
+ * per-sample Eq. 3 transform before squaring, e.g. grid_voltages then
+ * fft2_batched of that station) is the input; for every channel c and every
+ * selected beam pixel k (one direction s_k of the stations' common sky grid),
+ * the M fields are gridded at the station positions on the array grid,
+ * transformed, squared and averaged over the cadence, as image_cadence does
+ * for elements:
+ *     image[c][s][p*n_pol+q][y][x],  s = index into pixels.
+ * common: n_pol, channels, n_time, precision as for image_cadence;
+ *         grid_spacing_wl is the ARRAY grid spacing; volt_type is ignored
+ *         (the fields are cf32);
+ * array:  the array geometry as a station: n_elem = M (1..128) station
+ *         positions pos_m in metres in the array frame, the array grid
+ *         (nx, ny) and kernel; volts is ignored; image is the device output,
+ *         cf32 [n_chan][n_sel][n_pol^2][ny][nx];
+ * beams:  host array of M device pointers, station m's fields cf32
+ *         [n_chan][n_time][n_pol][beam_ny][beam_nx] (the stations must share
+ *         one sky grid: the same beam_nx, beam_ny and grid spacing in
+ *         wavelengths; each field is phase-referenced to its own station's
+ *         grid, and the common per-pixel phase this leaves cancels in the
+ *         products);
+ * pixels: host int32 [n_sel], flat beam pixels ky * beam_nx + kx (natural
+ *         order, as the transform writes them).
+ * The (channel, pixel) problems are processed in chunks whose array-scale
+ * voltages fit 1 GiB of library workspace (EPIC_ARRAY_BUDGET_KB overrides);
+ * each chunk runs image_cadence's kernels (plans and graphs are cached per
+ * chunk); the chunking never changes the result.
+ * Errors: EPIC_ERR_INVALID_ARG for arguments as image_cadence, NULL beams,
+ * more than 128 stations, beam grids that are not powers of two in 16..256,
+ * or a selected pixel off the beam grid.
+ */
+epic_status array_cadence(const epic_common *common, const epic_station *array,
+                          const void *const *beams, int32_t beam_nx, int32_t beam_ny,
+                          int32_t n_sel, const int32_t *pixels, hipStream_t stream);
+
+/*
  * Tile tuning (auxiliary).  image_cadence runs every station whose grid is
  * square and at most 64 x 64 (and, in FP32, every 128 x 128 one) in fused
  * kernels that process one (station, channel, time chunk) item per

@@ -3,6 +3,7 @@
 // argument has been checked.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -349,6 +350,75 @@ epic_status xfft_image(const epic_common *common, const epic_station *station, c
                          common->n_chan, nx, ny, static_cast<float2 *>(part), g, stream);
     if (st != EPIC_OK) return st;
     return launch_fft2_f32(nx, ny, batch, g, static_cast<float2 *>(station->image), dev, stream);
+}
+
+epic_status array_cadence(const epic_common *common, const epic_station *array,
+                          const void *const *beams, int32_t beam_nx, int32_t beam_ny,
+                          int32_t n_sel, const int32_t *pixels, hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!array) return fail(EPIC_ERR_INVALID_ARG, "array is NULL");
+    st = check_station(array, 0, false);
+    if (st != EPIC_OK) return st;
+    if (!array->image) return fail(EPIC_ERR_INVALID_ARG, "array image is NULL");
+    const int n_st = array->n_elem;
+    if (n_st > kMaxCombine) return fail(EPIC_ERR_INVALID_ARG, "at most 128 stations");
+    if (!beams) return fail(EPIC_ERR_INVALID_ARG, "beams is NULL");
+    StationImages bt{};
+    for (int m = 0; m < n_st; ++m) {
+        if (!beams[m]) return fail(EPIC_ERR_INVALID_ARG, "a station beam pointer is NULL");
+        bt.p[m] = static_cast<const float2 *>(beams[m]);
+    }
+    if (!is_pow2_grid(beam_nx) || !is_pow2_grid(beam_ny))
+        return fail(EPIC_ERR_INVALID_ARG, "beam_nx, beam_ny must be powers of two in 16..256");
+    if (n_sel < 1 || !pixels) return fail(EPIC_ERR_INVALID_ARG, "need n_sel >= 1 selected pixels");
+    const int npix_b = beam_nx * beam_ny;
+    for (int s = 0; s < n_sel; ++s)
+        if (pixels[s] < 0 || pixels[s] >= npix_b)
+            return fail(EPIC_ERR_INVALID_ARG, "selected pixel " + std::to_string(s) + " is off the beam grid");
+    st = check_geometry(common, array);
+    if (st != EPIC_OK) return fail(st, std::string("array: ") + last_error_cstr());
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    void *ws_pix = nullptr, *ws_v = nullptr;
+    st = get_workspace(dev, stream, 7, sizeof(int32_t) * static_cast<size_t>(n_sel), &ws_pix);
+    if (st != EPIC_OK) return st;
+    EPIC_HIP_TRY(hipMemcpyAsync(ws_pix, pixels, sizeof(int32_t) * n_sel, hipMemcpyHostToDevice, stream));
+    // the (channel, pixel) problems in chunks whose array-scale voltages fit 1 GiB
+    const int n_pol = common->n_pol;
+    const int64_t per_item = static_cast<int64_t>(common->n_time) * n_st * n_pol * 8;
+    const int64_t total = static_cast<int64_t>(common->n_chan) * n_sel;
+    int64_t budget = int64_t{1} << 30;
+    if (const char *e = std::getenv("EPIC_ARRAY_BUDGET_KB")) budget = std::max<int64_t>(1, std::atoll(e)) << 10;
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(total, budget / per_item));
+    st = get_workspace(dev, stream, 6, static_cast<size_t>(chunk * per_item), &ws_v);
+    if (st != EPIC_OK) return st;
+    const size_t plane = static_cast<size_t>(n_pol) * n_pol * array->nx * array->ny;
+    for (int64_t i0 = 0; i0 < total; i0 += chunk) {
+        const int n = static_cast<int>(std::min(chunk, total - i0));
+        st = launch_gather_beams(bt, n_st, n_pol, common->n_time, npix_b, n_sel,
+                                 static_cast<const int32_t *>(ws_pix), i0, n,
+                                 static_cast<float2 *>(ws_v), stream);
+        if (st != EPIC_OK) return st;
+        std::vector<double> lam(n);
+        for (int k = 0; k < n; ++k) lam[k] = common->wavelength_m[(i0 + k) / n_sel];
+        epic_common c2 = *common;
+        c2.n_chan = n;
+        c2.wavelength_m = lam.data();
+        c2.volt_type = EPIC_CF32;
+        epic_station s2 = *array;
+        s2.volts = ws_v;
+        s2.image = static_cast<float2 *>(array->image) + static_cast<size_t>(i0) * plane;
+        PlanHandle p;
+        st = get_plan(&c2, &s2, dev, &p);
+        if (st != EPIC_OK) return st;
+        st = run_cadence(&c2, &s2, 1, &p, dev, stream);
+        if (st != EPIC_OK) return st;
+    }
+    return EPIC_OK;
 }
 
 epic_status image_cadence(const epic_common *common, const epic_station *stations,

@@ -239,6 +239,14 @@ struct StationImages {
 epic_status launch_combine(const StationImages &imgs, int n_stations, int plane, int n_chan,
                            const float *weights, float2 *out, hipStream_t stream);
 
+// Corner turn of coherent inter-station EPIC (k_beams.hip): station fields
+// beams.p[m] [n_chan][n_time][n_pol][npix_b] (up to kMaxCombine stations) ->
+// out[i][t][m][p] for problems i = item0 .. item0 + n_items - 1 of the order
+// c * n_sel + s, beam pixel pix[s] (device array).
+epic_status launch_gather_beams(const StationImages &beams, int n_st, int n_pol, int n_time,
+                                int npix_b, int n_sel, const int32_t *pix, int64_t item0,
+                                int64_t n_items, float2 *out, hipStream_t stream);
+
 // Ordered, compensated reduction of the partial sums of every chunk, then the
 // mean, written as the n_pol^2 complex products.
 epic_status launch_reduce_partials(int n_pol, int npix, int n_chan, int n_chunks,

@@ -28,8 +28,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXB = 64;            // output rows (and columns) of a block
 constexpr int kXThreads = 256;
-constexpr int kP8 = 80;            // bytes per row of an int8 plane: 64 samples + 16 pad
-constexpr int kKT8 = 64;           // samples per chunk (ci8): one MFMA K step
+constexpr int kP8 = 144;           // bytes per row of an int8 plane: 128 samples + 16 pad
+constexpr int kKT8 = 128;          // samples per chunk (ci8): two MFMA K steps of 64
 constexpr int kKT32 = 32;          // samples per chunk (cf32): eight MFMA K steps of 4
 constexpr int kP32 = 80;           // floats per sample row of an FP32 plane: 64 rows + 16 pad
 // Largest sample count whose int8 products cannot overflow a 32-bit sum:
@@ -53,49 +53,58 @@ __device__ __forceinline__ void block_pair(int p, int nb, int &I, int &J)
     J = i + p;
 }
 
-// ci8: a thread stages 4 samples x 8 rows (one 16-byte load per sample) and
-// writes, per row, the 4 samples' real and imaginary bytes as one 32-bit word
-// of the re and im planes ([row][sample], kP8 bytes per row).
+// ci8: a thread stages 4 samples x 8 rows of each block (one 16-byte load per
+// sample and block) and writes, per row, the 4 samples' real and imaginary
+// bytes as one 32-bit word of the re and im planes ([row][sample], kP8 bytes
+// per row).  32 sample quads x 8 row octets cover a block; with the 144-byte
+// pitch a wave's stores and the 16-lane fragment reads are bank-conflict free.
 struct Stage8 {
-    uint32_t d[4][4];
+    uint32_t d[2][4][4];
 
     __device__ __forceinline__ void load(const int8_t *v, int R, int n_time, size_t cbase, int t,
-                                         int row0, bool vec)
+                                         const int *row0, int nside, bool vec)
     {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int tt = t + u;
+        for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-            for (int w = 0; w < 4; ++w) d[u][w] = 0u;
-            if (tt >= n_time) continue;
-            const size_t off = (cbase + static_cast<size_t>(tt) * R + row0) * 2;
-            if (vec) {
-                if (row0 < R) {
-                    const i32x4 q = gload<i32x4>(v + off, 0);
+            for (int u = 0; u < 4; ++u) {
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) d[u][w] = static_cast<uint32_t>(q[w]);
-                }
-            } else {
+                for (int w = 0; w < 4; ++w) d[sd][u][w] = 0u;
+                const int tt = t + u;
+                if (sd >= nside || tt >= n_time) continue;
+                const size_t off = (cbase + static_cast<size_t>(tt) * R + row0[sd]) * 2;
+                if (vec) {
+                    if (row0[sd] < R) {
+                        const i32x4 q = gload<i32x4>(v + off, 0);
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if (row0 + k < R) {
-                        const uint32_t h = gload<uint16_t>(v + off + 2 * k, 0);
-                        d[u][k >> 1] |= h << (16 * (k & 1));
+                        for (int w = 0; w < 4; ++w) d[sd][u][w] = static_cast<uint32_t>(q[w]);
                     }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (row0[sd] + k < R) {
+                            const uint32_t h = gload<uint16_t>(v + off + 2 * k, 0);
+                            d[sd][u][k >> 1] |= h << (16 * (k & 1));
+                        }
+                }
             }
-        }
     }
 
-    __device__ __forceinline__ void store(uint8_t *re, uint8_t *im, int row_l, int col) const
+    __device__ __forceinline__ void store(uint8_t *const *re, uint8_t *const *im, int nside,
+                                          int row_l, int col) const
     {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int w = k >> 1;
-            const uint32_t sel = (k & 1) ? 0x07030602u : 0x05010400u;
-            const uint32_t p01 = byte_perm(d[1][w], d[0][w], sel);   // re0 re1 im0 im1
-            const uint32_t p23 = byte_perm(d[3][w], d[2][w], sel);   // re2 re3 im2 im3
-            *reinterpret_cast<uint32_t *>(re + (row_l + k) * kP8 + col) = byte_perm(p23, p01, 0x05040100u);
-            *reinterpret_cast<uint32_t *>(im + (row_l + k) * kP8 + col) = byte_perm(p23, p01, 0x07060302u);
+        for (int sd = 0; sd < 2; ++sd) {
+            if (sd >= nside) break;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int w = k >> 1;
+                const uint32_t sel = (k & 1) ? 0x07030602u : 0x05010400u;
+                const uint32_t p01 = byte_perm(d[sd][1][w], d[sd][0][w], sel);   // re0 re1 im0 im1
+                const uint32_t p23 = byte_perm(d[sd][3][w], d[sd][2][w], sel);   // re2 re3 im2 im3
+                *reinterpret_cast<uint32_t *>(re[sd] + (row_l + k) * kP8 + col) = byte_perm(p23, p01, 0x05040100u);
+                *reinterpret_cast<uint32_t *>(im[sd] + (row_l + k) * kP8 + col) = byte_perm(p23, p01, 0x07060302u);
+            }
         }
     }
 };
@@ -181,36 +190,40 @@ __global__ __launch_bounds__(kXThreads) void k_xcorr(const void *__restrict__ vo
         __shared__ __attribute__((aligned(16))) uint8_t lds[4][kXB * kP8];
         uint8_t *are = lds[0], *aim = lds[1];
         uint8_t *bre = diag ? lds[0] : lds[2], *bim = diag ? lds[1] : lds[3];
-        uint8_t *sre = lds[2 * side], *sim = lds[2 * side + 1];
+        uint8_t *const sre[2] = {lds[0], lds[2]}, *const sim[2] = {lds[1], lds[3]};
+        const int nside = diag ? 1 : 2;
         const bool vec = (R & 7) == 0;
         const int8_t *v = static_cast<const int8_t *>(volts);
-        const int tq = i & 15, ro = i >> 4;
+        const int tq = tid & 31, ro = tid >> 5;
+        const int row0[2] = {I * kXB + 8 * ro, J * kXB + 8 * ro};
         Stage8 st;
-        if (stager) st.load(v, R, t_end, cbase, t_beg + 4 * tq, blk0 + 8 * ro, vec);
+        st.load(v, R, t_end, cbase, t_beg + 4 * tq, row0, nside, vec);
         for (int t0 = t_beg; t0 < t_end; t0 += kKT8) {
             __syncthreads();
-            if (stager) st.store(sre, sim, 8 * ro, 4 * tq);
+            st.store(sre, sim, nside, 8 * ro, 4 * tq);
             __syncthreads();
-            if (t0 + kKT8 < t_end && stager)
-                st.load(v, R, t_end, cbase, t0 + kKT8 + 4 * tq, blk0 + 8 * ro, vec);
-            const int fo = (lane & 15) * kP8 + 16 * (lane >> 4);
-            i32x4 xr[2], xi[2], yr[2], yi[2];
+            if (t0 + kKT8 < t_end) st.load(v, R, t_end, cbase, t0 + kKT8 + 4 * tq, row0, nside, vec);
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                xr[a] = *reinterpret_cast<const i32x4 *>(are + (mi + 16 * a) * kP8 + fo);
-                xi[a] = *reinterpret_cast<const i32x4 *>(aim + (mi + 16 * a) * kP8 + fo);
-                yr[a] = *reinterpret_cast<const i32x4 *>(bre + (nj + 16 * a) * kP8 + fo);
-                yi[a] = *reinterpret_cast<const i32x4 *>(bim + (nj + 16 * a) * kP8 + fo);
-            }
+            for (int ks = 0; ks < kKT8 / 64; ++ks) {
+                const int fo = (lane & 15) * kP8 + 64 * ks + 16 * (lane >> 4);
+                i32x4 xr[2], xi[2], yr[2], yi[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    rr[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xr[a], yr[b], rr[a][b], 0, 0, 0);
-                    rr[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xi[a], yi[b], rr[a][b], 0, 0, 0);
-                    ir[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xi[a], yr[b], ir[a][b], 0, 0, 0);
-                    ri[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xr[a], yi[b], ri[a][b], 0, 0, 0);
+                for (int a = 0; a < 2; ++a) {
+                    xr[a] = *reinterpret_cast<const i32x4 *>(are + (mi + 16 * a) * kP8 + fo);
+                    xi[a] = *reinterpret_cast<const i32x4 *>(aim + (mi + 16 * a) * kP8 + fo);
+                    yr[a] = *reinterpret_cast<const i32x4 *>(bre + (nj + 16 * a) * kP8 + fo);
+                    yi[a] = *reinterpret_cast<const i32x4 *>(bim + (nj + 16 * a) * kP8 + fo);
                 }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        rr[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xr[a], yr[b], rr[a][b], 0, 0, 0);
+                        rr[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xi[a], yi[b], rr[a][b], 0, 0, 0);
+                        ir[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xi[a], yr[b], ir[a][b], 0, 0, 0);
+                        ri[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xr[a], yi[b], ri[a][b], 0, 0, 0);
+                    }
+            }
         }
     } else {
         __shared__ __attribute__((aligned(16))) float lds[4][kKT32 * kP32];

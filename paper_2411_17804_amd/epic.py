@@ -34,7 +34,7 @@ KERNEL_GAUSSIAN = 1
 
 # every function the header declares
 ABI_FUNCTIONS = ("grid_voltages", "fft2_batched", "accumulate_power", "image_cadence",
-                 "image_to_visibilities", "combine_incoherent", "xfft_correlate", "xfft_image",
+                 "image_to_visibilities", "combine_incoherent", "xfft_correlate", "xfft_image", "array_cadence",
                  "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
                  "epic_timing_reset", "epic_status_string", "epic_last_error",
                  "epic_cache_clear")
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.xfft_correlate.restype = i32
     lib.xfft_image.argtypes = [P, P, P, P, P]
     lib.xfft_image.restype = i32
+    lib.array_cadence.argtypes = [P, P, P, i32, i32, i32, P, P]
+    lib.array_cadence.restype = i32
     lib.epic_autotune.argtypes = [P, P, i32, P]
     lib.epic_autotune.restype = i32
     lib.epic_validate.argtypes = [P, P, i32]
@@ -261,6 +263,22 @@ def xfft_image(common: Common, station: Station, vis, gridded=None, stream=None)
     s, keep2 = station.to_c()
     _check(lib.xfft_image(ctypes.byref(c), ctypes.byref(s), _dptr(vis), _dptr(gridded),
                           _stream(stream)))
+
+
+def array_cadence(common: Common, array: Station, beams, beam_nx: int, beam_ny: int, pixels,
+                  stream=None):
+    """Coherent inter-station EPIC: array.image (device cf32
+    [n_chan][n_sel][n_pol^2][ny][nx]) from the stations' fields beams
+    (sequence of device tensors cf32 [n_chan][n_time][n_pol][beam_ny][beam_nx])
+    at the selected flat beam pixels."""
+    lib = load()
+    c, keep1 = common.to_c()
+    s, keep2 = array.to_c()
+    ptrs = (ctypes.c_void_p * max(1, len(beams)))(*[_dptr(t) for t in beams])
+    pix = np.ascontiguousarray(pixels, dtype=np.int32)
+    _check(lib.array_cadence(ctypes.byref(c), ctypes.byref(s), ptrs if beams else None, beam_nx,
+                             beam_ny, pix.size, pix.ctypes.data if pix.size else None,
+                             _stream(stream)))
 
 
 def _stations_c(stations):

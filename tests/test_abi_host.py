@@ -169,6 +169,23 @@ def test_xfft_calls_reject_bad_arguments_without_a_device():
     assert e.value.status == epic.EPIC_ERR_UNSUPPORTED
 
 
+def test_array_cadence_rejects_bad_arguments_without_a_device():
+    common, station = _c2_like()
+    station.pos_m = station.pos_m[:8]
+    station.nx = station.ny = 64
+    ok = [0x1000] * 8
+    for beams, nb, pix in [(None, 64, [0]), ([0x1000] * 7 + [None], 64, [0]), (ok, 48, [0]),
+                           (ok, 64, []), (ok, 64, [64 * 64]), (ok, 64, [-1])]:
+        with pytest.raises(epic.EpicError) as e:
+            epic.array_cadence(common, station, beams or [], nb, nb, pix, stream=0)
+        assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    big = epic.Station(np.zeros((129, 2)), 64, 64, station.kernel_type, station.support,
+                       station.sigma_cells, image=0x2000)
+    with pytest.raises(epic.EpicError) as e:
+        epic.array_cadence(common, big, [0x1000] * 129, 64, 64, [0], stream=0)
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+
+
 def test_struct_layout_matches_header():
     # epic_common: 2 x int32, pointer, double, 3 x int32 (+ pad) ; epic_station as declared
     assert ctypes.sizeof(epic._Common) == 40
