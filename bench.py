@@ -302,6 +302,8 @@ def main():
         c0 = epic.Common(cfg.n_pol, cfg.wavelengths_m, W.GRID_SPACING_WL, cfg.n_time,
                          cfg.volt_type, cfg.precision)
         out["stages"] = stage_rooflines(cfg, c0, stations[0])
+        if len(cfg.stations) == 1:
+            out["stages"]["inter_station_epic"] = array_stage(cfg)
         log(f"stages: {out['stages']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, stations, host_volts, args.cpu_channels)
@@ -429,6 +431,74 @@ def xfft_stages(cfg, common, station, timed):
                        "cadence": f"{cfg.n_chan} channels x {cfg.n_time} samples"},
     }
     del vis
+    torch.cuda.empty_cache()
+    return out
+
+
+def array_stage(cfg, reps=2):
+    """Coherent inter-station EPIC (Eq. 10 then Eq. 9) on a synthetic array of
+    16 copies of the first station (centres in a 300 m circle, 45 m apart):
+    4 channels x 256 samples, every beam pixel, array grid 32 x 32 at half the
+    station diameter, nearest-cell gridding.  Station fields come from
+    grid_voltages + fft2_batched (timed as beam formation); array_cadence is
+    timed on its own; its rate is array-grid pixel-samples per second."""
+    import torch
+    from paper_2411_17804_amd import epic
+    st = cfg.stations[0]
+    n_st, n_ch, nt = 16, 4, 256
+    lams = cfg.wavelengths_m[:n_ch]
+    cen = W.array_centres(n_st, 300.0, 45.0, cfg.seed)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(cfg.seed)
+    common_s = epic.Common(cfg.n_pol, lams, W.GRID_SPACING_WL, nt, cfg.volt_type, epic.FP32_FFT)
+    bv = 2 if cfg.volt_type == W.CI8 else 8
+    beams, volts = [], []
+    for m in range(n_st):
+        if cfg.volt_type == W.CI8:
+            v = torch.randint(-48, 48, (n_ch, nt, st.n_elem, cfg.n_pol, 2), dtype=torch.int8,
+                              device="cuda:0", generator=gen)
+        else:
+            v = torch.randn((n_ch, nt, st.n_elem, cfg.n_pol, 2), device="cuda:0", generator=gen)
+        volts.append(v)
+        beams.append(torch.empty((n_ch, nt, cfg.n_pol, st.ny, st.nx, 2), dtype=torch.float32,
+                                 device="cuda:0"))
+
+    def form():
+        for m in range(n_st):
+            s_m = epic.Station(st.pos_m, st.nx, st.ny, st.kernel_type, st.support, st.sigma_cells,
+                               volts=volts[m])
+            epic.grid_voltages(common_s, s_m, 0, nt, beams[m])
+            epic.fft2_batched(st.nx, st.ny, n_ch * nt * cfg.n_pol, epic.FP32_FFT, beams[m], beams[m])
+
+    na = 32
+    dA = 0.5 * 2.0 * float(np.max(np.linalg.norm(st.pos_m, axis=1))) / float(lams.max())
+    pix = np.arange(st.nx * st.ny, dtype=np.int32)
+    img = torch.empty((n_ch, pix.size, cfg.n_pol ** 2, na, na, 2), dtype=torch.float32, device="cuda:0")
+    common_a = epic.Common(cfg.n_pol, lams, dA, nt, W.CF32, epic.FP32_FFT)
+    arr = epic.Station(cen, na, na, W.KERNEL_NEAREST, 1, 0.0, image=img)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    ms_b = timed(form)
+    ms_a = timed(lambda: epic.array_cadence(common_a, arr, beams, st.nx, st.ny, pix))
+    problems = n_ch * pix.size
+    out = {"stations": n_st, "channels": n_ch, "samples": nt, "beam_pixels": int(pix.size),
+           "array_grid": na, "array_spacing_wl": round(dA, 3),
+           "beam_formation_ms": round(ms_b, 3), "array_cadence_ms": round(ms_a, 3),
+           "array_pixel_samples_per_s": problems * nt * na * na / ms_a * 1e3,
+           "voltage_bytes": n_st * n_ch * nt * st.n_elem * cfg.n_pol * bv}
+    del beams, volts, img
     torch.cuda.empty_cache()
     return out
 

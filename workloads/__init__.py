@@ -240,6 +240,12 @@ def make_config(index: int, n_chan: int | None = None, n_time: int | None = None
                   stations=stations)
 
 
+def array_centres(n_stations: int, diameter_m: float, min_spacing_m: float, seed: int) -> np.ndarray:
+    """Station centres of a synthetic array (metres, array frame): uniform in a
+    circle with a minimum spacing, for the inter-station (Eq. 10) workload."""
+    return _dart_circle(np.random.default_rng([seed, 0xA77A]), n_stations, diameter_m, min_spacing_m)
+
+
 def channel_volts(cfg: Config, station_idx: int, chan_pos: int) -> np.ndarray:
     """Voltages of one station at one channel of cfg: [n_time, n_elem, n_pol].
 
