@@ -207,6 +207,50 @@ def image(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K, sigma_c
     return out
 
 
+def grid_pol(pos_m, wavelength_m, grid_spacing_wl, nx, ny, K, kernels, volts, lib=None):
+    """Gridded field of one channel with full polarimetric complex kernels
+    (Eq. 3, inner bracket, in general form):
+        G^a[j] = sum_elem sum_p conj(W_elem^{ap}[j - c_elem + h]) E_elem^p
+    on the K x K cells around each element's nearest cell c_elem (h = (K-1)/2;
+    the cells are those of plan()).  kernels: complex [n_elem, n_pol (a),
+    n_pol (p), K (dy), K (dx)], the caller's kernel values at those cells.
+    volts: [n_time, n_elem, n_pol] complex (or [..., 2] int8).  Returns
+    complex128 [n_time, n_pol, ny, nx]."""
+    lib = lib or load()
+    _, v = _volt_type(volts)
+    if v.dtype == np.int8:
+        v = v[..., 0].astype(np.float64) + 1j * v[..., 1].astype(np.float64)
+    v = np.asarray(v, np.complex128)
+    n_time, n_elem, n_pol = v.shape
+    W = np.asarray(kernels, np.complex128)
+    ix, iy, _, _ = plan(pos_m, wavelength_m, grid_spacing_wl, nx, ny, KERNEL_NEAREST if K == 1
+                        else KERNEL_GAUSSIAN, K, 1.0, lib=lib)
+    h = (K - 1) // 2
+    out = np.zeros((n_time, n_pol, ny, nx), np.complex128)
+    for a in range(n_elem):
+        for dy in range(K):
+            for dx in range(K):
+                y, x = iy[a] - h + dy, ix[a] - h + dx
+                for al in range(n_pol):
+                    for p in range(n_pol):
+                        out[:, al, y, x] += np.conj(W[a, al, p, dy, dx]) * v[:, a, p]
+    return out
+
+
+def image_pol(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, K, kernels, volts, lib=None):
+    """EPIC image (Eq. 3 with grid_pol(), then Eq. 2) for every channel;
+    kernels: complex [n_chan, n_elem, n_pol, n_pol, K, K].  Returns complex128
+    [n_chan, n_pol*n_pol, ny, nx]."""
+    lib = lib or load()
+    n_chan = len(wavelengths_m)
+    out = []
+    for c in range(n_chan):
+        f = fft2(grid_pol(pos_m, wavelengths_m[c], grid_spacing_wl, nx, ny, K, kernels[c],
+                          volts[c], lib=lib), lib=lib)
+        out.append(power_mean(f, lib=lib))
+    return np.stack(out)
+
+
 def station_beams(pos_m, wavelengths_m, grid_spacing_wl, nx, ny, kernel_type, K, sigma_cells,
                   volts, lib=None):
     """The station-synthesised electric fields of Sec. 6.2: for every channel

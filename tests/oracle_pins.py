@@ -39,6 +39,12 @@ What each pin is tied to:
 * pin_array_single_station -- one station at the array origin: its
                             array-scale image is flat and equals its own
                             station image at the selected pixel.
+* pin_pol_kernels         -- Eq. 3 with full polarimetric complex kernels:
+                            a real diagonal kernel built from the plan's
+                            weights reproduces image(); a complex unitary pol
+                            mix U turns the image into conj(U) I U^T; a linear
+                            phase screen exp(-2 pi i k0.j / N) on the kernels
+                            shifts the image by k0 pixels.
 * pin_incoherent_combination -- Eq. 7 as a weighted mean: invariant under a
                             per-pixel rescaling of the weights, returns a lone
                             weighted station or identical images unchanged,
@@ -71,6 +77,7 @@ PIN_TOL = {
     "point_source_offset": 1e-12,
     "visibility_closed_forms": 1e-12,
     "incoherent_combination": 1e-13,
+    "pol_kernels": 1e-12,
     "array_point_source": 1e-12,
     "array_single_station": 1e-12,
     "visibility_correlator": 1e-12,
@@ -337,6 +344,51 @@ def pin_array_single_station(lib, array_fn=None):
     return err
 
 
+def pin_pol_kernels(lib, image_fn=None):
+    image_fn = image_fn or oracle.image_pol
+    rng = _rng(17)
+    nx = ny = 16
+    lams = np.array([2.0, 1.6])
+    K, sig = 3, 0.5
+    n_el, n_time, n_pol = 6, 5, 2
+    pos = rng.uniform(-3.0, 3.0, (n_el, 2))
+    E = _cnormal(rng, (2, n_time, n_el, n_pol))
+    base = oracle.image(pos, lams, 0.5, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, E, lib=lib)
+    diag = np.zeros((2, n_el, n_pol, n_pol, K, K), np.complex128)
+    cells = []
+    for c, lam in enumerate(lams):
+        ix, iy, wx, wy = oracle.plan(pos, lam, 0.5, nx, ny, oracle.KERNEL_GAUSSIAN, K, sig, lib=lib)
+        cells.append((ix, iy))
+        for p in range(n_pol):
+            diag[c, :, p, p] = wy[:, :, None] * wx[:, None, :]
+    err = _rel(image_fn(pos, lams, 0.5, nx, ny, K, diag, E, lib=lib), base)
+    # complex unitary pol mix: conj(U) I U^T
+    q, _ = np.linalg.qr(_cnormal(rng, (2, 2)))
+    kern = np.zeros_like(diag)
+    for c in range(2):
+        for a in range(n_pol):
+            for p in range(n_pol):
+                kern[c, :, a, p] = q[a, p] * diag[c, :, p, p]
+    got = image_fn(pos, lams, 0.5, nx, ny, K, kern, E, lib=lib).reshape(2, 2, 2, ny, nx)
+    b = base.reshape(2, 2, 2, ny, nx)
+    want = np.einsum("ap,cpqyx,bq->cabyx", np.conj(q), b, q)
+    err = max(err, _rel(got, want))
+    # linear phase screen on the absolute cells: the image shifts by k0
+    k0 = (3, -2)
+    scr = diag.copy()
+    h = (K - 1) // 2
+    for c in range(2):
+        ix, iy = cells[c]
+        jx = ix[:, None] - h + np.arange(K)[None, :]          # [elem, dx]
+        jy = iy[:, None] - h + np.arange(K)[None, :]          # [elem, dy]
+        ph = np.exp(-2j * np.pi * (k0[0] * jx[:, None, :] / nx + k0[1] * jy[:, :, None] / ny))
+        scr[c] = diag[c] * ph[:, None, None, :, :]
+    got = image_fn(pos, lams, 0.5, nx, ny, K, scr, E, lib=lib)
+    want = np.roll(base, (-k0[1], -k0[0]), axis=(-2, -1))
+    err = max(err, _rel(got, want))
+    return err
+
+
 def pin_incoherent_combination(lib):
     # Eq. 7 as weighted mean: invariant under a per-pixel rescaling of all
     # weights; a single weighted station is returned as it is; identical
@@ -451,6 +503,7 @@ ALL_PINS = {
     "xfft_equivalence": pin_xfft_equivalence,
     "visibility_closed_forms": pin_visibility_closed_forms,
     "incoherent_combination": pin_incoherent_combination,
+    "pol_kernels": pin_pol_kernels,
     "array_point_source": pin_array_point_source,
     "array_single_station": pin_array_single_station,
     "visibility_correlator": pin_visibility_correlator,

@@ -123,6 +123,24 @@ def test_array_pins_catch_mistakes(lib, mutant):
                 and errs[1] <= P.PIN_TOL["array_single_station"]), (mutant, errs)
 
 
+def _pol_mutants():
+    # plausible slips in the polarimetric gridding, planted on the CPU by
+    # handing the true routine a mis-indexed kernel table
+    def wrap(f):
+        return lambda pos, lams, dwl, nx, ny, K, kern, E, lib=None: oracle.image_pol(
+            pos, lams, dwl, nx, ny, K, f(np.asarray(kern)), E, lib=lib)
+
+    return {"dropped_conj": wrap(np.conj),
+            "pol_axes_swapped": wrap(lambda k: np.swapaxes(k, 2, 3)),
+            "dx_dy_swapped": wrap(lambda k: np.swapaxes(k, 4, 5))}
+
+
+@pytest.mark.parametrize("mutant", sorted(_pol_mutants()))
+def test_pol_pin_catches_mistakes(lib, mutant):
+    err = P.pin_pol_kernels(lib, image_fn=_pol_mutants()[mutant])
+    assert not err <= P.PIN_TOL["pol_kernels"], mutant
+
+
 # (source fragment, replacement) -- each a plausible slip in the oracle
 MUTANTS = {
     "transform_sign": ("const double ang = EO_TWO_PI *", "const double ang = -EO_TWO_PI *"),
