@@ -197,6 +197,39 @@ epic_status combine_incoherent(int32_t n_pol, int32_t nx, int32_t ny, int32_t n_
                                const float *weights, void *out, hipStream_t stream);
 
 /*
+ * Gridding with full polarimetric complex kernels (Sec. 5.2, Eq. 3 in its
+ * general form): every output pol a collects every input pol p of every
+ * element through that element's own complex kernel, applied conjugated,
+ *     grid[c][t - t0][a][j] = sum_elem sum_p conj(W[c][elem][a][p][dy][dx]) E_elem^p(t),
+ * over the K x K cells j = (c_x - h + dx, c_y - h + dy) around the element's
+ * nearest cell c (the cells of grid_voltages; h = (K - 1) / 2, K =
+ * station->kernel.support).  This carries an antenna's holographic
+ * illumination pattern with its pol leakage and w-projection phase screens
+ * (a larger K for non-coplanar elements).
+ * kernels: device cf32 [n_chan][n_elem][n_pol (a)][n_pol (p)][K (dy)][K (dx)],
+ *          the kernel values at those cells (the caller evaluates them at the
+ *          element's true position); station->kernel.type and sigma_cells are
+ *          not used;
+ * grid:    as for grid_voltages.  FP32 sums over the cell's taps in element
+ *          order (deterministic).
+ * Errors: as grid_voltages, plus EPIC_ERR_INVALID_ARG for kernels NULL.
+ */
+epic_status grid_voltages_pol(const epic_common *common, const epic_station *station,
+                              const void *kernels, int32_t t0, int32_t nt, void *grid,
+                              hipStream_t stream);
+
+/*
+ * The whole cadence of one station (Eq. 3 with grid_voltages_pol's kernels,
+ * then Eq. 2) into station->image [n_chan][n_pol^2][ny][nx]: gridding,
+ * transform (common->precision: the FP32 FFT or a split-precision DFT-matrix
+ * product), products and compensated time average, in time chunks through a
+ * library workspace.  kernels as for grid_voltages_pol.
+ * Errors: as image_cadence, plus EPIC_ERR_INVALID_ARG for kernels NULL.
+ */
+epic_status image_cadence_pol(const epic_common *common, const epic_station *station,
+                              const void *kernels, hipStream_t stream);
+
+/*
  * Correlator of the XFFT architecture (Sec. 5.4, Eq. 4): the visibilities of
  * one station, for every channel c, ordered element pair (a, b)
  * (autocorrelations included) and pol pair (p, q),

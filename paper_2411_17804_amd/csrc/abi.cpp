@@ -18,7 +18,7 @@ using namespace epic;
 namespace epic {
 StationDev make_station_dev(const epic_station *s, const PlanHandle &p);
 epic_status cadence_composed(const epic_common *c, const epic_station *s, const PlanHandle &p,
-                             int device, hipStream_t stream);
+                             int device, hipStream_t stream, const float2 *pol_kernels = nullptr);
 }
 
 namespace {
@@ -106,9 +106,11 @@ StationDev epic::make_station_dev(const epic_station *s, const PlanHandle &p)
 
 // The composed cadence path: grid -> transform -> square/accumulate through a
 // library-owned workspace, in time chunks.  Used for the grids and precisions
-// that the fused kernel does not cover.
+// that the fused kernel does not cover, and for gridding with full
+// polarimetric kernels (pol_kernels non-null).
 epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
-                                   const PlanHandle &p, int device, hipStream_t stream)
+                                   const PlanHandle &p, int device, hipStream_t stream,
+                                   const float2 *pol_kernels)
 {
     const int n_pol = c->n_pol, n_chan = c->n_chan;
     const int64_t npix = static_cast<int64_t>(s->nx) * s->ny;
@@ -129,7 +131,7 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
     float2 *field = static_cast<float2 *>(ws_field);
     // large stations: sample-blocked voltage copy for the gather (k_grid.hip)
     float2 *tv = nullptr;
-    if (s->n_elem >= kGridTbMinElem) {
+    if (s->n_elem >= kGridTbMinElem && !pol_kernels) {
         void *ws_tv = nullptr;
         const size_t tv_bytes = sizeof(float2) * static_cast<size_t>(n_chan) * ((chunk + 7) / 8) * 8 *
                                 s->n_elem * n_pol;
@@ -139,8 +141,13 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
     }
     for (int t0 = 0; t0 < c->n_time; t0 += chunk) {
         const int nt = std::min(chunk, c->n_time - t0);
-        st = tv ? launch_grid_tb(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, tv, field, stream)
-                : launch_grid(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, field, stream);
+        if (pol_kernels)
+            st = launch_grid_pol(sd, p.elem_cell, pol_kernels, s->kernel.support, n_pol, n_chan,
+                                 c->n_time, c->volt_type, t0, nt, field, stream);
+        else if (tv)
+            st = launch_grid_tb(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, tv, field, stream);
+        else
+            st = launch_grid(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, field, stream);
         if (st != EPIC_OK) return st;
         const int64_t batch = static_cast<int64_t>(n_chan) * nt * n_pol;
         if (c->precision == EPIC_FP32_FFT)
@@ -218,6 +225,52 @@ epic_status grid_voltages(const epic_common *common, const epic_station *station
     if (st != EPIC_OK) return st;
     return launch_grid(make_station_dev(station, p), common->n_pol, common->n_chan, common->n_time,
                        common->volt_type, t0, nt, static_cast<float2 *>(grid), stream);
+}
+
+epic_status grid_voltages_pol(const epic_common *common, const epic_station *station,
+                              const void *kernels, int32_t t0, int32_t nt, void *grid,
+                              hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!station) return fail(EPIC_ERR_INVALID_ARG, "station is NULL");
+    st = check_station(station, 0);
+    if (st != EPIC_OK) return st;
+    if (!kernels) return fail(EPIC_ERR_INVALID_ARG, "kernels is NULL");
+    if (t0 < 0 || nt < 1 || static_cast<int64_t>(t0) + nt > common->n_time)
+        return fail(EPIC_ERR_INVALID_ARG, "need 0 <= t0, nt >= 1, t0 + nt <= n_time");
+    if (!grid) return fail(EPIC_ERR_INVALID_ARG, "grid is NULL");
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    PlanHandle p;
+    st = get_plan(common, station, dev, &p);
+    if (st != EPIC_OK) return st;
+    return launch_grid_pol(make_station_dev(station, p), p.elem_cell,
+                           static_cast<const float2 *>(kernels), station->kernel.support,
+                           common->n_pol, common->n_chan, common->n_time, common->volt_type, t0, nt,
+                           static_cast<float2 *>(grid), stream);
+}
+
+epic_status image_cadence_pol(const epic_common *common, const epic_station *station,
+                              const void *kernels, hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!station) return fail(EPIC_ERR_INVALID_ARG, "station is NULL");
+    st = check_station(station, 0);
+    if (st != EPIC_OK) return st;
+    if (!kernels) return fail(EPIC_ERR_INVALID_ARG, "kernels is NULL");
+    if (!station->image) return fail(EPIC_ERR_INVALID_ARG, "station image is NULL");
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    PlanHandle p;
+    st = get_plan(common, station, dev, &p);
+    if (st != EPIC_OK) return st;
+    return cadence_composed(common, station, p, dev, stream, static_cast<const float2 *>(kernels));
 }
 
 epic_status fft2_batched(int32_t nx, int32_t ny, int64_t batch, int32_t precision, const void *in,

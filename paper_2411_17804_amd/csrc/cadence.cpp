@@ -39,7 +39,7 @@ namespace epic {
 
 StationDev make_station_dev(const epic_station *s, const PlanHandle &p);
 epic_status cadence_composed(const epic_common *c, const epic_station *s, const PlanHandle &p,
-                             int device, hipStream_t stream);
+                             int device, hipStream_t stream, const float2 *pol_kernels = nullptr);
 
 namespace {
 

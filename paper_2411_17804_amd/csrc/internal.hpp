@@ -102,6 +102,7 @@ struct PlanHandle {
     const int32_t *cell_start = nullptr;
     const Tap *taps = nullptr;
     const int32_t *cell_order = nullptr;
+    const int32_t *elem_cell = nullptr;   // [n_chan][n_elem]: nearest cell ci | cj << 16
     int32_t max_box = 0;       // max bw*bh over channels
     int32_t max_bw = 0, max_bh = 0;
     int32_t max_cell_taps = 0; // max taps landing on one cell over channels
@@ -177,6 +178,13 @@ bool timing_on();
 // ---------------------------------------------------------------------------
 epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
                         int t0, int nt, float2 *grid, hipStream_t stream);
+
+// Gridding with full polarimetric complex kernels (k_grid.hip): kernels
+// [n_chan][n_elem][n_pol][n_pol][K][K] cf32 applied conjugated at the K x K
+// cells around each element's nearest cell elem_cell[c][a].
+epic_status launch_grid_pol(const StationDev &sd, const int32_t *elem_cell, const float2 *kernels,
+                            int K, int n_pol, int n_chan, int n_time, int volt_type, int t0, int nt,
+                            float2 *grid, hipStream_t stream);
 
 // XFFT route (k_xfft.hip).  Correlator (Eq. 4): vis[c][R][R] (R = n_elem *
 // n_pol rows in voltage order) = mean over n_time of X X^H.

@@ -150,6 +150,100 @@ __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk
     }
 }
 
+// Full polarimetric gridding (Eq. 3 in general form): every cell sums, over
+// its plan taps in order, conj(W_a^{ap}[dy][dx]) E_a^p for both output pols
+// a and input pols p, with (dx, dy) the cell's offset in element a's K x K
+// footprint.  Same work decomposition as k_grid.
+template <int NP, int VT, int TB>
+__global__ __launch_bounds__(256) void k_grid_pol(StationDev sd, const int32_t *__restrict__ elem_cell,
+                                                  const float2 *__restrict__ kernels, int K,
+                                                  int n_time, int t0, int nt,
+                                                  float2 *__restrict__ grid)
+{
+    constexpr int CB = kGridCellBlock;
+    const int tb = blockIdx.x * TB;
+    const int c = blockIdx.y;
+    const int nts = min(TB, nt - tb);
+    const ChanPlan cp = sd.chan[c];
+    const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
+    const Tap *taps = sd.taps + cp.tap_off;
+    const int nx = sd.nx, ny = sd.ny;
+    const int npix = nx * ny;
+    const int h = (K - 1) / 2, kk = K * K;
+    const gptr<int32_t> ecell = global_ptr<int32_t>(elem_cell) + static_cast<size_t>(c) * sd.n_elem;
+    const float2 *kc = kernels + static_cast<size_t>(c) * sd.n_elem * NP * NP * kk;
+    const size_t vrow0 = (static_cast<size_t>(c) * n_time + t0 + tb) * sd.n_elem;
+    const size_t vstride = sd.n_elem;
+    float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
+    const int i_end = min(npix, static_cast<int>(blockIdx.z + 1) * CB);
+    for (int i = blockIdx.z * CB + threadIdx.x; i < i_end; i += blockDim.x) {
+        const int y = i / nx, x = i - y * nx;
+        const int bx = x - cp.x0, by = y - cp.y0;
+        float2 acc[TB][NP];
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) acc[t][p] = make_float2(0.f, 0.f);
+        if (bx >= 0 && bx < cp.bw && by >= 0 && by < cp.bh) {
+            const int cell = by * cp.bw + bx;
+            const int k1 = cs[cell + 1];
+            for (int k = cs[cell]; k < k1; ++k) {
+                const Tap tp = gload<Tap>(taps, k);
+                const int ec = ecell[tp.elem];
+                const int dx = x - (ec & 0xffff) + h, dy = y - (ec >> 16) + h;
+                const float2 *wk = kc + static_cast<size_t>(tp.elem) * NP * NP * kk + dy * K + dx;
+                float2 w[NP][NP];
+#pragma unroll
+                for (int a = 0; a < NP; ++a)
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) w[a][p] = gload<float2>(wk, (a * NP + p) * kk);
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    if (t < nts) {
+                        float2 e[NP];
+                        load_volt<NP, VT>(sd.volts, vrow0 + t * vstride + tp.elem, e);
+#pragma unroll
+                        for (int a = 0; a < NP; ++a)
+#pragma unroll
+                            for (int p = 0; p < NP; ++p) {
+                                // conj(w) e
+                                acc[t][a].x = fmaf(w[a][p].x, e[p].x, fmaf(w[a][p].y, e[p].y, acc[t][a].x));
+                                acc[t][a].y = fmaf(w[a][p].x, e[p].y, fmaf(-w[a][p].y, e[p].x, acc[t][a].y));
+                            }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+            if (t < nts)
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    out[(static_cast<size_t>(t) * NP + p) * npix + i] = acc[t][p];
+    }
+}
+
+epic_status launch_grid_pol(const StationDev &sd, const int32_t *elem_cell, const float2 *kernels,
+                            int K, int n_pol, int n_chan, int n_time, int volt_type, int t0, int nt,
+                            float2 *grid, hipStream_t stream)
+{
+    constexpr int TB = kGridTB;
+    const int npix = sd.nx * sd.ny;
+    const dim3 blocks((nt + TB - 1) / TB, n_chan, (npix + kGridCellBlock - 1) / kGridCellBlock),
+        threads(256);
+    KernelTimer timer("grid_pol", stream);
+    if (n_pol == 1 && volt_type == EPIC_CI8)
+        hipLaunchKernelGGL((k_grid_pol<1, EPIC_CI8, TB>), blocks, threads, 0, stream, sd, elem_cell, kernels, K, n_time, t0, nt, grid);
+    else if (n_pol == 1)
+        hipLaunchKernelGGL((k_grid_pol<1, EPIC_CF32, TB>), blocks, threads, 0, stream, sd, elem_cell, kernels, K, n_time, t0, nt, grid);
+    else if (volt_type == EPIC_CI8)
+        hipLaunchKernelGGL((k_grid_pol<2, EPIC_CI8, TB>), blocks, threads, 0, stream, sd, elem_cell, kernels, K, n_time, t0, nt, grid);
+    else
+        hipLaunchKernelGGL((k_grid_pol<2, EPIC_CF32, TB>), blocks, threads, 0, stream, sd, elem_cell, kernels, K, n_time, t0, nt, grid);
+    EPIC_HIP_TRY(hipGetLastError());
+    return EPIC_OK;
+}
+
 epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
                            int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream)
 {

@@ -180,6 +180,7 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     std::vector<ChanPlan> chans(n_chan);
     std::vector<int32_t> cell_start;
     std::vector<int32_t> cell_order;   // per channel: box cells by descending tap count
+    std::vector<int32_t> elem_cell(static_cast<size_t>(n_chan) * n_elem);   // ci | cj << 16
     std::vector<Tap> taps;
     std::vector<int> ci(n_elem), cj(n_elem);
     std::vector<double> wx(static_cast<size_t>(n_elem) * K), wy(static_cast<size_t>(n_elem) * K);
@@ -201,6 +202,8 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
             y_lo = std::min(y_lo, cj[a] - h);
             y_hi = std::max(y_hi, cj[a] + h);
         }
+        for (int a = 0; a < n_elem; ++a)
+            elem_cell[static_cast<size_t>(c) * n_elem + a] = ci[a] | (cj[a] << 16);
         ChanPlan &cp = chans[c];
         cp.x0 = x_lo;
         cp.y0 = y_lo;
@@ -261,8 +264,9 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     const size_t b_cell = up(sizeof(int32_t) * cell_start.size());
     const size_t b_taps = up(sizeof(Tap) * taps.size());
     const size_t b_order = up(sizeof(int32_t) * cell_order.size());
+    const size_t b_ec = up(sizeof(int32_t) * elem_cell.size());
     void *dev = nullptr;
-    epic_status s = dev_alloc(&dev, b_chan + b_cell + b_taps + b_order);
+    epic_status s = dev_alloc(&dev, b_chan + b_cell + b_taps + b_order + b_ec);
     if (s != EPIC_OK) return s;
     char *p = static_cast<char *>(dev);
     hipError_t e = hipMemcpy(p, chans.data(), sizeof(ChanPlan) * chans.size(), hipMemcpyHostToDevice);
@@ -275,6 +279,9 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     if (e == hipSuccess)
         e = hipMemcpy(p + b_chan + b_cell + b_taps, cell_order.data(),
                       sizeof(int32_t) * cell_order.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p + b_chan + b_cell + b_taps + b_order, elem_cell.data(),
+                      sizeof(int32_t) * elem_cell.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(dev);
         return hip_fail(e, "plan upload");
@@ -283,6 +290,7 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     hd.cell_start = reinterpret_cast<const int32_t *>(p + b_chan);
     hd.taps = reinterpret_cast<const Tap *>(p + b_chan + b_cell);
     hd.cell_order = reinterpret_cast<const int32_t *>(p + b_chan + b_cell + b_taps);
+    hd.elem_cell = reinterpret_cast<const int32_t *>(p + b_chan + b_cell + b_taps + b_order);
     g_plans.emplace(std::move(key), PlanEntry{dev, hd});
     *out = hd;
     return EPIC_OK;

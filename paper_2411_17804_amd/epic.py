@@ -34,7 +34,7 @@ KERNEL_GAUSSIAN = 1
 
 # every function the header declares
 ABI_FUNCTIONS = ("grid_voltages", "fft2_batched", "accumulate_power", "image_cadence",
-                 "image_to_visibilities", "combine_incoherent", "xfft_correlate", "xfft_image", "array_cadence",
+                 "image_to_visibilities", "combine_incoherent", "xfft_correlate", "xfft_image", "array_cadence", "grid_voltages_pol", "image_cadence_pol",
                  "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
                  "epic_timing_reset", "epic_status_string", "epic_last_error",
                  "epic_cache_clear")
@@ -94,6 +94,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.xfft_correlate.restype = i32
     lib.xfft_image.argtypes = [P, P, P, P, P]
     lib.xfft_image.restype = i32
+    lib.grid_voltages_pol.argtypes = [P, P, P, i32, i32, P, P]
+    lib.grid_voltages_pol.restype = i32
+    lib.image_cadence_pol.argtypes = [P, P, P, P]
+    lib.image_cadence_pol.restype = i32
     lib.array_cadence.argtypes = [P, P, P, i32, i32, i32, P, P]
     lib.array_cadence.restype = i32
     lib.epic_autotune.argtypes = [P, P, i32, P]
@@ -243,6 +247,26 @@ def combine_incoherent(n_pol: int, nx: int, ny: int, n_chan: int, images, out, w
     ptrs = (ctypes.c_void_p * max(1, len(images)))(*[_dptr(t) for t in images])
     _check(lib.combine_incoherent(n_pol, nx, ny, n_chan, len(images), ptrs if images else None,
                                   _dptr(weights), _dptr(out), _stream(stream)))
+
+
+def grid_voltages_pol(common: Common, station: Station, kernels, t0: int, nt: int, grid,
+                      stream=None):
+    """Gridding with full polarimetric complex kernels (device cf32
+    [n_chan][n_elem][n_pol][n_pol][K][K]) into grid [n_chan][nt][n_pol][ny][nx]."""
+    lib = load()
+    c, keep1 = common.to_c()
+    s, keep2 = station.to_c()
+    _check(lib.grid_voltages_pol(ctypes.byref(c), ctypes.byref(s), _dptr(kernels), t0, nt,
+                                 _dptr(grid), _stream(stream)))
+
+
+def image_cadence_pol(common: Common, station: Station, kernels, stream=None):
+    """The cadence of one station with full polarimetric kernels into station.image."""
+    lib = load()
+    c, keep1 = common.to_c()
+    s, keep2 = station.to_c()
+    _check(lib.image_cadence_pol(ctypes.byref(c), ctypes.byref(s), _dptr(kernels),
+                                 _stream(stream)))
 
 
 def xfft_correlate(common: Common, station: Station, vis, stream=None):

@@ -186,6 +186,23 @@ def test_array_cadence_rejects_bad_arguments_without_a_device():
     assert e.value.status == epic.EPIC_ERR_INVALID_ARG
 
 
+def test_pol_calls_reject_bad_arguments_without_a_device():
+    common, station = _c2_like()
+    with pytest.raises(epic.EpicError) as e:
+        epic.grid_voltages_pol(common, station, None, 0, 4, 0x3000, stream=0)
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    with pytest.raises(epic.EpicError) as e:
+        epic.grid_voltages_pol(common, station, 0x4000, 6, 4, 0x3000, stream=0)
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    with pytest.raises(epic.EpicError) as e:
+        epic.image_cadence_pol(common, station, None, stream=0)
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+    common, station = _c2_like(image=None)
+    with pytest.raises(epic.EpicError) as e:
+        epic.image_cadence_pol(common, station, 0x4000, stream=0)
+    assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+
+
 def test_struct_layout_matches_header():
     # epic_common: 2 x int32, pointer, double, 3 x int32 (+ pad) ; epic_station as declared
     assert ctypes.sizeof(epic._Common) == 40
