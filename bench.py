@@ -388,6 +388,18 @@ def stage_rooflines(cfg, common, station, nt=64, reps=3):
                                    "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
                                    "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
     del wts, copies
+    # gridding with full polarimetric complex kernels (seeded random 2x2 pol
+    # mixing on the K x K cells; algorithmic bytes: voltages, kernel table and
+    # grid, each once)
+    K = st.support
+    kern = torch.randn((cfg.n_chan, st.n_elem, cfg.n_pol, cfg.n_pol, K, K, 2), device="cuda:0",
+                       generator=torch.Generator(device="cuda:0").manual_seed(cfg.seed))
+    ms = timed(lambda: epic.grid_voltages_pol(common, station, kern, 0, nt, grid))
+    b = cfg.n_chan * nt * st.n_elem * cfg.n_pol * bv + kern.numel() * 4 + field_bytes
+    res["grid_voltages_pol"] = {"ms": round(ms, 3), "bound": "hbm", "bytes": b,
+                                "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
+                                "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    del kern
     res.update(xfft_stages(cfg, common, station, timed))
     res["_block"] = f"{cfg.n_chan} channels x {nt} samples x {cfg.n_pol} pols of {st.nx}x{st.ny}"
     del grid, out, acc, img

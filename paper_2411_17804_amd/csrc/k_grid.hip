@@ -14,7 +14,46 @@ constexpr int kGridTB = 8;             // samples per gridding work-group
 // cell's tap list is read once and applied to the TB samples, whose voltage
 // loads are independent of each other.  Writes all n_pol planes of each
 // sample's ny x nx grid (zero outside the footprint box).  The cell blocks
-// keep the launch wide when a few samples of a large grid are gridded.
+// keep the launch wide when a few samples of a large grid are gridded.  A
+// thread owns two neighbouring cells of a row and writes them as one 16-byte
+// streaming store (the grid is write-once data).
+// Two neighbouring cells' values as one 16-byte streaming store.
+__device__ __forceinline__ void store_pair(float2 *dst, float2 a, float2 b)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(f4{a.x, a.y, b.x, b.y}, reinterpret_cast<f4 *>(dst));
+}
+
+template <int NP, int VT, int TB>
+__device__ __forceinline__ void grid_cell(const StationDev &sd, const ChanPlan &cp,
+                                          const gptr<int32_t> &cs, const Tap *taps, int x, int y,
+                                          size_t vrow0, int nts, float2 (&acc)[TB][NP])
+{
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) acc[t][p] = make_float2(0.f, 0.f);
+    const int bx = x - cp.x0, by = y - cp.y0;
+    if (bx < 0 || bx >= cp.bw || by < 0 || by >= cp.bh) return;
+    const int cell = by * cp.bw + bx;
+    const int k1 = cs[cell + 1];
+    for (int k = cs[cell]; k < k1; ++k) {
+        const Tap tp = gload<Tap>(taps, k);
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            if (t < nts) {
+                float2 e[NP];
+                load_volt<NP, VT>(sd.volts, vrow0 + t * static_cast<size_t>(sd.n_elem) + tp.elem, e);
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    acc[t][p].x = fmaf(tp.w, e[p].x, acc[t][p].x);
+                    acc[t][p].y = fmaf(tp.w, e[p].y, acc[t][p].y);
+                }
+            }
+        }
+    }
+}
+
 template <int NP, int VT, int TB>
 __global__ __launch_bounds__(256) void k_grid(StationDev sd, int n_time, int t0, int nt,
                                               float2 *__restrict__ grid)
@@ -29,42 +68,19 @@ __global__ __launch_bounds__(256) void k_grid(StationDev sd, int n_time, int t0,
     const int nx = sd.nx, ny = sd.ny;
     const int npix = nx * ny;
     const size_t vrow0 = (static_cast<size_t>(c) * n_time + t0 + tb) * sd.n_elem;
-    const size_t vstride = sd.n_elem;                      // elements per sample
     float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
     const int i_end = min(npix, static_cast<int>(blockIdx.z + 1) * CB);
-    for (int i = blockIdx.z * CB + threadIdx.x; i < i_end; i += blockDim.x) {
-        const int y = i / nx, x = i - y * nx;
-        const int bx = x - cp.x0, by = y - cp.y0;
-        float2 acc[TB][NP];
-#pragma unroll
-        for (int t = 0; t < TB; ++t)
-#pragma unroll
-            for (int p = 0; p < NP; ++p) acc[t][p] = make_float2(0.f, 0.f);
-        if (bx >= 0 && bx < cp.bw && by >= 0 && by < cp.bh) {
-            const int cell = by * cp.bw + bx;
-            const int k1 = cs[cell + 1];
-            for (int k = cs[cell]; k < k1; ++k) {
-                const Tap tp = gload<Tap>(taps, k);
-#pragma unroll
-                for (int t = 0; t < TB; ++t) {
-                    if (t < nts) {
-                        float2 e[NP];
-                        load_volt<NP, VT>(sd.volts, vrow0 + t * vstride + tp.elem, e);
-#pragma unroll
-                        for (int p = 0; p < NP; ++p) {
-                            acc[t][p].x = fmaf(tp.w, e[p].x, acc[t][p].x);
-                            acc[t][p].y = fmaf(tp.w, e[p].y, acc[t][p].y);
-                        }
-                    }
-                }
-            }
-        }
+    for (int i = blockIdx.z * CB + 2 * threadIdx.x; i < i_end; i += 2 * blockDim.x) {
+        const int y = i / nx, x = i - y * nx;             // x even: x + 1 is on the same row
+        float2 a0[TB][NP], a1[TB][NP];
+        grid_cell<NP, VT, TB>(sd, cp, cs, taps, x, y, vrow0, nts, a0);
+        grid_cell<NP, VT, TB>(sd, cp, cs, taps, x + 1, y, vrow0, nts, a1);
 #pragma unroll
         for (int t = 0; t < TB; ++t)
             if (t < nts)
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
-                    out[(static_cast<size_t>(t) * NP + p) * npix + i] = acc[t][p];
+                    store_pair(out + (static_cast<size_t>(t) * NP + p) * npix + i, a0[t][p], a1[t][p]);
     }
 }
 
@@ -101,6 +117,33 @@ __global__ __launch_bounds__(256) void k_volts_tb(const void *__restrict__ volts
 }
 
 template <int NP, int TB>
+__device__ __forceinline__ void grid_cell_tb(const ChanPlan &cp, const gptr<int32_t> &cs,
+                                             const Tap *taps, const float2 *src, int x, int y,
+                                             float2 (&acc)[TB][NP])
+{
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) acc[t][p] = make_float2(0.f, 0.f);
+    const int bx = x - cp.x0, by = y - cp.y0;
+    if (bx < 0 || bx >= cp.bw || by < 0 || by >= cp.bh) return;
+    const int cell = by * cp.bw + bx;
+    const int k1 = cs[cell + 1];
+    for (int k = cs[cell]; k < k1; ++k) {
+        const Tap tp = gload<Tap>(taps, k);
+        const float2 *e = src + static_cast<size_t>(tp.elem) * TB * NP;
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const float2 v = gload<float2>(e, t * NP + p);
+                acc[t][p].x = fmaf(tp.w, v.x, acc[t][p].x);
+                acc[t][p].y = fmaf(tp.w, v.y, acc[t][p].y);
+            }
+    }
+}
+
+template <int NP, int TB>
 __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk,
                                                  const float2 *__restrict__ tv,
                                                  float2 *__restrict__ grid)
@@ -117,36 +160,62 @@ __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk
     const float2 *src = tv + (static_cast<size_t>(c) * nblk + blk) * sd.n_elem * TB * NP;
     float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
     const int i_end = min(npix, static_cast<int>(blockIdx.z + 1) * CB);
+    // one cell per thread: large stations have many taps per cell, and the
+    // wider launch hides their load latency better than paired stores save
     for (int i = blockIdx.z * CB + threadIdx.x; i < i_end; i += blockDim.x) {
         const int y = i / nx, x = i - y * nx;
-        const int bx = x - cp.x0, by = y - cp.y0;
         float2 acc[TB][NP];
-#pragma unroll
-        for (int t = 0; t < TB; ++t)
-#pragma unroll
-            for (int p = 0; p < NP; ++p) acc[t][p] = make_float2(0.f, 0.f);
-        if (bx >= 0 && bx < cp.bw && by >= 0 && by < cp.bh) {
-            const int cell = by * cp.bw + bx;
-            const int k1 = cs[cell + 1];
-            for (int k = cs[cell]; k < k1; ++k) {
-                const Tap tp = gload<Tap>(taps, k);
-                const float2 *e = src + static_cast<size_t>(tp.elem) * TB * NP;
-#pragma unroll
-                for (int t = 0; t < TB; ++t)
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-                        const float2 v = gload<float2>(e, t * NP + p);
-                        acc[t][p].x = fmaf(tp.w, v.x, acc[t][p].x);
-                        acc[t][p].y = fmaf(tp.w, v.y, acc[t][p].y);
-                    }
-            }
-        }
+        grid_cell_tb<NP, TB>(cp, cs, taps, src, x, y, acc);
 #pragma unroll
         for (int t = 0; t < TB; ++t)
             if (t < nts)
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
                     out[(static_cast<size_t>(t) * NP + p) * npix + i] = acc[t][p];
+    }
+}
+
+template <int NP, int VT, int TB>
+__device__ __forceinline__ void grid_cell_pol(const StationDev &sd, const ChanPlan &cp,
+                                              const gptr<int32_t> &cs, const Tap *taps,
+                                              const gptr<int32_t> &ecell, const float2 *kc, int K,
+                                              int x, int y, size_t vrow0, int nts,
+                                              float2 (&acc)[TB][NP])
+{
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) acc[t][p] = make_float2(0.f, 0.f);
+    const int bx = x - cp.x0, by = y - cp.y0;
+    if (bx < 0 || bx >= cp.bw || by < 0 || by >= cp.bh) return;
+    const int h = (K - 1) / 2, kk = K * K;
+    const int cell = by * cp.bw + bx;
+    const int k1 = cs[cell + 1];
+    for (int k = cs[cell]; k < k1; ++k) {
+        const Tap tp = gload<Tap>(taps, k);
+        const int ec = ecell[tp.elem];
+        const int dx = x - (ec & 0xffff) + h, dy = y - (ec >> 16) + h;
+        const float2 *wk = kc + static_cast<size_t>(tp.elem) * NP * NP * kk + dy * K + dx;
+        float2 w[NP][NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) w[a][p] = gload<float2>(wk, (a * NP + p) * kk);
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            if (t < nts) {
+                float2 e[NP];
+                load_volt<NP, VT>(sd.volts, vrow0 + t * static_cast<size_t>(sd.n_elem) + tp.elem, e);
+#pragma unroll
+                for (int a = 0; a < NP; ++a)
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        // conj(w) e
+                        acc[t][a].x = fmaf(w[a][p].x, e[p].x, fmaf(w[a][p].y, e[p].y, acc[t][a].x));
+                        acc[t][a].y = fmaf(w[a][p].x, e[p].y, fmaf(-w[a][p].y, e[p].x, acc[t][a].y));
+                    }
+            }
+        }
     }
 }
 
@@ -169,57 +238,22 @@ __global__ __launch_bounds__(256) void k_grid_pol(StationDev sd, const int32_t *
     const Tap *taps = sd.taps + cp.tap_off;
     const int nx = sd.nx, ny = sd.ny;
     const int npix = nx * ny;
-    const int h = (K - 1) / 2, kk = K * K;
     const gptr<int32_t> ecell = global_ptr<int32_t>(elem_cell) + static_cast<size_t>(c) * sd.n_elem;
-    const float2 *kc = kernels + static_cast<size_t>(c) * sd.n_elem * NP * NP * kk;
+    const float2 *kc = kernels + static_cast<size_t>(c) * sd.n_elem * NP * NP * K * K;
     const size_t vrow0 = (static_cast<size_t>(c) * n_time + t0 + tb) * sd.n_elem;
-    const size_t vstride = sd.n_elem;
     float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
     const int i_end = min(npix, static_cast<int>(blockIdx.z + 1) * CB);
-    for (int i = blockIdx.z * CB + threadIdx.x; i < i_end; i += blockDim.x) {
-        const int y = i / nx, x = i - y * nx;
-        const int bx = x - cp.x0, by = y - cp.y0;
-        float2 acc[TB][NP];
-#pragma unroll
-        for (int t = 0; t < TB; ++t)
-#pragma unroll
-            for (int p = 0; p < NP; ++p) acc[t][p] = make_float2(0.f, 0.f);
-        if (bx >= 0 && bx < cp.bw && by >= 0 && by < cp.bh) {
-            const int cell = by * cp.bw + bx;
-            const int k1 = cs[cell + 1];
-            for (int k = cs[cell]; k < k1; ++k) {
-                const Tap tp = gload<Tap>(taps, k);
-                const int ec = ecell[tp.elem];
-                const int dx = x - (ec & 0xffff) + h, dy = y - (ec >> 16) + h;
-                const float2 *wk = kc + static_cast<size_t>(tp.elem) * NP * NP * kk + dy * K + dx;
-                float2 w[NP][NP];
-#pragma unroll
-                for (int a = 0; a < NP; ++a)
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) w[a][p] = gload<float2>(wk, (a * NP + p) * kk);
-#pragma unroll
-                for (int t = 0; t < TB; ++t) {
-                    if (t < nts) {
-                        float2 e[NP];
-                        load_volt<NP, VT>(sd.volts, vrow0 + t * vstride + tp.elem, e);
-#pragma unroll
-                        for (int a = 0; a < NP; ++a)
-#pragma unroll
-                            for (int p = 0; p < NP; ++p) {
-                                // conj(w) e
-                                acc[t][a].x = fmaf(w[a][p].x, e[p].x, fmaf(w[a][p].y, e[p].y, acc[t][a].x));
-                                acc[t][a].y = fmaf(w[a][p].x, e[p].y, fmaf(-w[a][p].y, e[p].x, acc[t][a].y));
-                            }
-                    }
-                }
-            }
-        }
+    for (int i = blockIdx.z * CB + 2 * threadIdx.x; i < i_end; i += 2 * blockDim.x) {
+        const int y = i / nx, x = i - y * nx;             // x even: x + 1 is on the same row
+        float2 a0[TB][NP], a1[TB][NP];
+        grid_cell_pol<NP, VT, TB>(sd, cp, cs, taps, ecell, kc, K, x, y, vrow0, nts, a0);
+        grid_cell_pol<NP, VT, TB>(sd, cp, cs, taps, ecell, kc, K, x + 1, y, vrow0, nts, a1);
 #pragma unroll
         for (int t = 0; t < TB; ++t)
             if (t < nts)
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
-                    out[(static_cast<size_t>(t) * NP + p) * npix + i] = acc[t][p];
+                    store_pair(out + (static_cast<size_t>(t) * NP + p) * npix + i, a0[t][p], a1[t][p]);
     }
 }
 
