@@ -32,8 +32,17 @@ __global__ __launch_bounds__(BLOCK) void k_fft2_lds(const float2 *__restrict__ i
     const float2 *src = in + item * (NX * NY);
     for (int i = threadIdx.x; i < NX; i += BLOCK) tx[i] = twx[i];
     for (int i = threadIdx.x; i < NY; i += BLOCK) ty[i] = twy[i];
-    for (int i = threadIdx.x; i < NX * NY; i += BLOCK)
-        buf[(i / NX) * P + (i % NX)] = INV ? conj_scaled(src[i], 1.f) : src[i];
+    // every load of the plane in flight before the LDS writes
+    constexpr int PER = NX * NY / BLOCK;
+    static_assert(PER * BLOCK == NX * NY, "plane must split evenly over the block");
+    float2 v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = src[threadIdx.x + r * BLOCK];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int i = threadIdx.x + r * BLOCK;
+        buf[(i / NX) * P + (i % NX)] = INV ? conj_scaled(v[r], 1.f) : v[r];
+    }
     __syncthreads();
     constexpr int MAXL = NX > NY ? NX : NY;
     fft_lines<NX, BLOCK, MAXL, false>(buf, LineMap{NY, 0, 0, P, 1}, NY, tx);
