@@ -68,8 +68,19 @@ __global__ __launch_bounds__(BLOCK) void k_fft_rows(const float2 *__restrict__ i
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * ROWS;
     const int nr = static_cast<int>(min<int64_t>(ROWS, n_rows - row0));
     for (int i = threadIdx.x; i < NX; i += BLOCK) t[i] = tw[i];
-    for (int i = threadIdx.x; i < nr * NX; i += BLOCK)
-        buf[(i / NX) * P + (i % NX)] = INV ? conj_scaled(in[row0 * NX + i], 1.f) : in[row0 * NX + i];
+    // every load of the rows in flight before the LDS writes
+    constexpr int PER = (ROWS * NX + BLOCK - 1) / BLOCK;
+    float2 v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int i = threadIdx.x + r * BLOCK;
+        v[r] = i < nr * NX ? in[row0 * NX + i] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int i = threadIdx.x + r * BLOCK;
+        if (i < nr * NX) buf[(i / NX) * P + (i % NX)] = INV ? conj_scaled(v[r], 1.f) : v[r];
+    }
     __syncthreads();
     fft_lines<NX, BLOCK, ROWS, false>(buf, LineMap{ROWS, 0, 0, P, 1}, nr, t);
     for (int i = threadIdx.x; i < nr * NX; i += BLOCK) out[row0 * NX + i] = buf[(i / NX) * P + (i % NX)];
@@ -89,7 +100,20 @@ __global__ __launch_bounds__(BLOCK) void k_fft_cols(float2 *__restrict__ data,
     const int c0 = (blockIdx.x % TILES) * COLS;
     float2 *base = data + item * (NX * NY) + c0;
     for (int i = threadIdx.x; i < NY; i += BLOCK) t[i] = tw[i];
-    for (int i = threadIdx.x; i < NY * COLS; i += BLOCK) buf[(i / COLS) * P + (i % COLS)] = base[(i / COLS) * NX + (i % COLS)];
+    // every load of the tile in flight before the LDS writes
+    constexpr int PER = NY * COLS / BLOCK;
+    static_assert(PER * BLOCK == NY * COLS, "tile must split evenly over the block");
+    float2 v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int i = threadIdx.x + r * BLOCK;
+        v[r] = base[(i / COLS) * NX + (i % COLS)];
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int i = threadIdx.x + r * BLOCK;
+        buf[(i / COLS) * P + (i % COLS)] = v[r];
+    }
     __syncthreads();
     fft_lines<NY, BLOCK, COLS, false>(buf, LineMap{COLS, 0, 0, 1, P}, COLS, t);
     constexpr float kInv = 1.f / static_cast<float>(NX * NY);
