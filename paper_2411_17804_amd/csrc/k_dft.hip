@@ -144,25 +144,34 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
     }
     const int j_lo = 16 * ks_lo, nrows = 16 * (ks_hi - ks_lo + 1);
 
+    // the block's input, read once into registers (rows past the pruned
+    // range read as zero)
+    constexpr int PER = N * CB / 256;
+    float2 xin[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        xin[q] = i < nrows * CB ? src[(j_lo + i / CB) * M + c0 + i % CB] : make_float2(0.f, 0.f);
+    }
     float s = 1.f;
     if constexpr (S::needs_scale) {
         float mx = 0.f;
-        for (int i = threadIdx.x; i < nrows * CB; i += 256) {
-            const float2 v = src[(j_lo + i / CB) * M + c0 + i % CB];
-            mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
-        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) mx = fmaxf(mx, fmaxf(fabsf(xin[q].x), fabsf(xin[q].y)));
         for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
         if (lane == 0) red[wave] = mx;
         __syncthreads();
         mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
         s = pow2_scale(mx);
     }
-    for (int i = threadIdx.x; i < nrows * CB; i += 256) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        if (i >= nrows * CB) break;
         const int j = j_lo + i / CB, c = i % CB;
-        const float2 v = src[j * M + c0 + c];
         scalar hr, lr, hi_, li;
-        split<PREC>(v.x * s, hr, lr);
-        split<PREC>(v.y * s, hi_, li);
+        split<PREC>(xin[q].x * s, hr, lr);
+        split<PREC>(xin[q].y * s, hi_, li);
         const uint32_t ph = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hr)) |
                             (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hi_)) << 16);
         const uint32_t pl = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, lr)) |
@@ -178,9 +187,10 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
 #pragma unroll
         for (int t = 0; t < NTW; ++t) acc[w][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 
+    // DFT-table fragments double-buffered: step ks + 1's loads are in flight
+    // while step ks's products run
     const vec8 *tab_lo = tab + static_cast<size_t>(MT) * KS * 64;
-    for (int ks = ks_lo; ks <= ks_hi; ++ks) {
-        vec8 ah[MTW], al[MTW];
+    auto load_a = [&](int ks, vec8 *ah, vec8 *al) {
 #pragma unroll
         for (int w = 0; w < MTW; ++w) {
             const int mt = wave + 4 * w;
@@ -189,6 +199,8 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
                 al[w] = tab_lo[(mt * KS + ks) * 64 + lane];
             }
         }
+    };
+    auto step = [&](int ks, const vec8 *ah, const vec8 *al) {
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
             const int c = t * 16 + r, j0 = ks * 16 + 4 * g;
@@ -198,6 +210,15 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
             for (int w = 0; w < MTW; ++w)
                 if (wave + 4 * w < MT) acc[w][t] = mma3<PREC>(ah[w], al[w], bh, bl, acc[w][t]);
         }
+    };
+    vec8 ah0[MTW], al0[MTW], ah1[MTW], al1[MTW];
+    load_a(ks_lo, ah0, al0);
+    for (int ks = ks_lo; ks <= ks_hi; ks += 2) {
+        if (ks + 1 <= ks_hi) load_a(ks + 1, ah1, al1);
+        step(ks, ah0, al0);
+        if (ks + 1 > ks_hi) break;
+        if (ks + 2 <= ks_hi) load_a(ks + 2, ah0, al0);
+        step(ks + 1, ah1, al1);
     }
 
     const float inv = 1.f / s;
