@@ -103,6 +103,26 @@ def test_xfft_correlate(torch, case):
     assert np.array_equal(m, np.conj(np.transpose(m, (0, 2, 1)))), "Hermitian by construction"
 
 
+def test_xfft_correlate_long_cadence(torch):
+    # more than 65408 ci8 samples: the correlator sums in segments (exact int32
+    # within each) and adds them in FP32; 64 elements, one pol
+    from paper_2411_17804_amd import epic
+    say("xfft_correlate ci8, 70000 samples (two segments)")
+    cfg = W.make_config(1, chan_subset=[2], n_time=70000)
+    cfg.volt_type = W.CI8
+    st = cfg.stations[0]
+    rng = np.random.default_rng([17804, 30])
+    v = np.clip(np.rint(rng.standard_normal((1, cfg.n_time, st.n_elem, 1, 2)) * 40), -128, 127).astype(np.int8)
+    common, (station,) = station_objects(cfg, [to_device_volts(v)])
+    vis = torch.zeros((1, st.n_elem, 1, st.n_elem, 1, 2), dtype=torch.float32, device="cuda")
+    epic.xfft_correlate(common, station, vis)
+    torch.cuda.synchronize()
+    got, ref = to_complex(vis), oracle.visibilities(v)
+    err = _rel(got, ref)
+    say(f"  error {err:.2e}")
+    assert err <= 2.0 ** -22, err
+
+
 # ------------------------------------------------------- gridding + image ----
 IMAGE_CASES = {
     # name: (config, channels, n_time, n_elem, support, check gridded against the oracle)
