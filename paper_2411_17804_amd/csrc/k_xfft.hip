@@ -479,7 +479,7 @@ template <int NP, int K>
 epic_status vg_launch(const float2 *vis, const XfftPlanHandle &pl, int n_elem, int n_chan, int nx,
                       int ny, float2 *part, float2 *grid, hipStream_t stream)
 {
-    constexpr int W = 2 * K - 1, NQ = NP * NP;
+    constexpr int NQ = NP * NP;
     constexpr int L = NQ * VcSplit<K>::S, CPB = (kVcThreads / 64) * (64 / L);
     const int npix = nx * ny;
     const size_t ew_bytes = sizeof(float) * static_cast<size_t>(n_elem) * ((2 * K + 3) & ~3);
