@@ -555,7 +555,9 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
 #pragma unroll
             for (int k = 0; k < 8; ++k) plane[bt ^ (k ^ jr)] = v[k];
         }
-        __syncthreads();
+        // a row is read and written by the 8 lanes of one wave in R1 and R2,
+        // and a wave's LDS accesses are performed in order: no block barrier
+        __builtin_amdgcn_wave_barrier();
         // R2: second pass along x, in place
         if (row_active) {
             float2 v[8];
@@ -578,11 +580,13 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
                 v[m] = in ? plane[cm[m] + 512 * m] : make_float2(0.f, 0.f);
             }
             Dft<8>::run(v);
-            __syncthreads();
+            // a column is read and rewritten only by its own 8 lanes (one
+            // wave; the swizzle permutes columns within each row)
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int k = 0; k < 8; ++k) plane[cm[k] + dj + 64 * k] = v[k];
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         // C2: second pass along y; pixel (ky = j + 8k, kx) of this thread's pol.
         // A thread reads and rewrites only its own eight addresses, so the
         // result goes back in place without a barrier in between.  Pol X
