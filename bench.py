@@ -452,8 +452,10 @@ def array_stage(cfg, reps=2):
     16 copies of the first station (centres in a 300 m circle, 45 m apart):
     4 channels x 256 samples, every beam pixel, array grid 32 x 32 at half the
     station diameter, nearest-cell gridding.  Station fields come from
-    grid_voltages + fft2_batched (timed as beam formation); array_cadence is
-    timed on its own; its rate is array-grid pixel-samples per second."""
+    grid_voltages + fft2_batched (timed as beam formation); array_cadence (the
+    EPIC route at array scale) and array_xfft (the XFFT route) are timed on
+    their own; the rate is array-grid pixel-samples per second of the EPIC
+    route."""
     import torch
     from paper_2411_17804_amd import epic
     st = cfg.stations[0]
@@ -504,11 +506,13 @@ def array_stage(cfg, reps=2):
 
     ms_b = timed(form)
     ms_a = timed(lambda: epic.array_cadence(common_a, arr, beams, st.nx, st.ny, pix))
+    ms_x = timed(lambda: epic.array_xfft(common_a, arr, beams, st.nx, st.ny, pix))
     problems = n_ch * pix.size
     out = {"stations": n_st, "channels": n_ch, "samples": nt, "beam_pixels": int(pix.size),
            "array_grid": na, "array_spacing_wl": round(dA, 3),
            "beam_formation_ms": round(ms_b, 3), "array_cadence_ms": round(ms_a, 3),
            "array_pixel_samples_per_s": problems * nt * na * na / ms_a * 1e3,
+           "array_xfft_ms": round(ms_x, 3),
            "voltage_bytes": n_st * n_ch * nt * st.n_elem * cfg.n_pol * bv}
     del beams, volts, img
     torch.cuda.empty_cache()

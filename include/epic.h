@@ -313,6 +313,23 @@ epic_status array_cadence(const epic_common *common, const epic_station *array,
                           int32_t n_sel, const int32_t *pixels, hipStream_t stream);
 
 /*
+ * Coherent inter-station imaging by the XFFT route (Sec. 6.2, Eq. 11 then
+ * Eq. 13): the same arguments, chunking and output as array_cadence, but each
+ * (channel, beam pixel) problem correlates the M station fields over the
+ * cadence (the inter-station visibilities phased towards s_k, as
+ * xfft_correlate does for elements) and grids them at the station
+ * separations with the cross-correlated array kernels before one transform
+ * (as xfft_image).  The image equals array_cadence's up to FP32 rounding
+ * (Wiener-Khinchin on the circular array grid); the work per problem scales
+ * with M^2 instead of the array grid size.
+ * Errors: as array_cadence, plus EPIC_ERR_UNSUPPORTED for an array visibility
+ * kernel (2K - 1 cells) wider than the array grid.
+ */
+epic_status array_xfft(const epic_common *common, const epic_station *array,
+                       const void *const *beams, int32_t beam_nx, int32_t beam_ny, int32_t n_sel,
+                       const int32_t *pixels, hipStream_t stream);
+
+/*
  * Tile tuning (auxiliary).  image_cadence runs every station whose grid is
  * square and at most 64 x 64 (and, in FP32, every 128 x 128 one) in fused
  * kernels that process one (station, channel, time chunk) item per

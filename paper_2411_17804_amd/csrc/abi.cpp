@@ -19,6 +19,11 @@ namespace epic {
 StationDev make_station_dev(const epic_station *s, const PlanHandle &p);
 epic_status cadence_composed(const epic_common *c, const epic_station *s, const PlanHandle &p,
                              int device, hipStream_t stream, const float2 *pol_kernels = nullptr);
+epic_status xfft_image_run(const epic_common *common, const epic_station *station,
+                           const float2 *vis, float2 *gridded, int dev, hipStream_t stream);
+epic_status array_run(const epic_common *common, const epic_station *array,
+                      const void *const *beams, int32_t beam_nx, int32_t beam_ny, int32_t n_sel,
+                      const int32_t *pixels, bool xfft, hipStream_t stream);
 }
 
 namespace {
@@ -161,6 +166,121 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
         const bool last = t0 + nt >= c->n_time;
         st = launch_power(n_pol, static_cast<int>(npix), n_chan, nt, field, acc_sum, acc_comp,
                           last ? c->n_time : 0, static_cast<float2 *>(s->image), stream);
+        if (st != EPIC_OK) return st;
+    }
+    return EPIC_OK;
+}
+
+// Eq. 6 gridding of visibilities and the transform into station->image, for
+// arguments already checked (xfft_image, array_xfft).
+epic_status epic::xfft_image_run(const epic_common *common, const epic_station *station,
+                                 const float2 *vis, float2 *gridded, int dev, hipStream_t stream)
+{
+    XfftPlanHandle pl;
+    epic_status st = get_xfft_plan(common, station, dev, &pl);
+    if (st != EPIC_OK) return st;
+    const int n_pol = common->n_pol, nx = station->nx, ny = station->ny;
+    const int64_t batch = static_cast<int64_t>(common->n_chan) * n_pol * n_pol;
+    float2 *g = gridded;
+    if (!g) {
+        void *ws = nullptr;
+        st = get_workspace(dev, stream, 4, sizeof(float2) * static_cast<size_t>(batch) * nx * ny, &ws);
+        if (st != EPIC_OK) return st;
+        g = static_cast<float2 *>(ws);
+    }
+    const int W = 2 * station->kernel.support - 1;
+    void *part = nullptr;
+    st = get_workspace(dev, stream, 5, sizeof(float2) * static_cast<size_t>(batch) * W * W * nx * ny,
+                       &part);
+    if (st != EPIC_OK) return st;
+    st = launch_vis_grid(vis, pl, n_pol, station->n_elem, common->n_chan, nx, ny,
+                         static_cast<float2 *>(part), g, stream);
+    if (st != EPIC_OK) return st;
+    return launch_fft2_f32(nx, ny, batch, g, static_cast<float2 *>(station->image), dev, stream);
+}
+
+// Coherent inter-station imaging over station fields (Sec. 6.2): the corner
+// turn of every chunk of (channel, beam pixel) problems, then either the
+// EPIC cadence (Eq. 10, 9) or the XFFT route (Eq. 11, 13) at array scale.
+epic_status epic::array_run(const epic_common *common, const epic_station *array,
+                            const void *const *beams, int32_t beam_nx, int32_t beam_ny,
+                            int32_t n_sel, const int32_t *pixels, bool xfft, hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!array) return fail(EPIC_ERR_INVALID_ARG, "array is NULL");
+    st = check_station(array, 0, false);
+    if (st != EPIC_OK) return st;
+    if (!array->image) return fail(EPIC_ERR_INVALID_ARG, "array image is NULL");
+    const int n_st = array->n_elem;
+    if (n_st > kMaxCombine) return fail(EPIC_ERR_INVALID_ARG, "at most 128 stations");
+    if (!beams) return fail(EPIC_ERR_INVALID_ARG, "beams is NULL");
+    StationImages bt{};
+    for (int m = 0; m < n_st; ++m) {
+        if (!beams[m]) return fail(EPIC_ERR_INVALID_ARG, "a station beam pointer is NULL");
+        bt.p[m] = static_cast<const float2 *>(beams[m]);
+    }
+    if (!is_pow2_grid(beam_nx) || !is_pow2_grid(beam_ny))
+        return fail(EPIC_ERR_INVALID_ARG, "beam_nx, beam_ny must be powers of two in 16..256");
+    if (n_sel < 1 || !pixels) return fail(EPIC_ERR_INVALID_ARG, "need n_sel >= 1 selected pixels");
+    const int npix_b = beam_nx * beam_ny;
+    for (int s = 0; s < n_sel; ++s)
+        if (pixels[s] < 0 || pixels[s] >= npix_b)
+            return fail(EPIC_ERR_INVALID_ARG, "selected pixel " + std::to_string(s) + " is off the beam grid");
+    if (xfft && 2 * array->kernel.support - 1 > std::min(array->nx, array->ny))
+        return fail(EPIC_ERR_UNSUPPORTED, "visibility kernel wider than the array grid");
+    st = check_geometry(common, array);
+    if (st != EPIC_OK) return fail(st, std::string("array: ") + last_error_cstr());
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    void *ws_pix = nullptr, *ws_v = nullptr, *ws_vis = nullptr;
+    st = get_workspace(dev, stream, 7, sizeof(int32_t) * static_cast<size_t>(n_sel), &ws_pix);
+    if (st != EPIC_OK) return st;
+    EPIC_HIP_TRY(hipMemcpyAsync(ws_pix, pixels, sizeof(int32_t) * n_sel, hipMemcpyHostToDevice, stream));
+    // the (channel, pixel) problems in chunks whose array-scale voltages fit 1 GiB
+    const int n_pol = common->n_pol;
+    const int R = n_st * n_pol;
+    const int64_t per_item = static_cast<int64_t>(common->n_time) * n_st * n_pol * 8;
+    const int64_t total = static_cast<int64_t>(common->n_chan) * n_sel;
+    int64_t budget = int64_t{1} << 30;
+    if (const char *e = std::getenv("EPIC_ARRAY_BUDGET_KB")) budget = std::max<int64_t>(1, std::atoll(e)) << 10;
+    int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(total, budget / per_item));
+    if (xfft)   // the XFFT plan holds n_st^2 pairs per problem
+        chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t{1} << 31) / (int64_t{n_st} * n_st)));
+    st = get_workspace(dev, stream, 6, static_cast<size_t>(chunk * per_item), &ws_v);
+    if (st != EPIC_OK) return st;
+    if (xfft) {
+        st = get_workspace(dev, stream, 8, sizeof(float2) * static_cast<size_t>(chunk) * R * R, &ws_vis);
+        if (st != EPIC_OK) return st;
+    }
+    const size_t plane = static_cast<size_t>(n_pol) * n_pol * array->nx * array->ny;
+    for (int64_t i0 = 0; i0 < total; i0 += chunk) {
+        const int n = static_cast<int>(std::min(chunk, total - i0));
+        st = launch_gather_beams(bt, n_st, n_pol, common->n_time, npix_b, n_sel,
+                                 static_cast<const int32_t *>(ws_pix), i0, n,
+                                 static_cast<float2 *>(ws_v), stream);
+        if (st != EPIC_OK) return st;
+        std::vector<double> lam(n);
+        for (int k = 0; k < n; ++k) lam[k] = common->wavelength_m[(i0 + k) / n_sel];
+        epic_common c2 = *common;
+        c2.n_chan = n;
+        c2.wavelength_m = lam.data();
+        c2.volt_type = EPIC_CF32;
+        epic_station s2 = *array;
+        s2.volts = ws_v;
+        s2.image = static_cast<float2 *>(array->image) + static_cast<size_t>(i0) * plane;
+        if (xfft) {
+            st = launch_xcorr(ws_v, EPIC_CF32, R, n, common->n_time, static_cast<float2 *>(ws_vis), stream);
+            if (st != EPIC_OK) return st;
+            st = xfft_image_run(&c2, &s2, static_cast<const float2 *>(ws_vis), nullptr, dev, stream);
+        } else {
+            PlanHandle p;
+            st = get_plan(&c2, &s2, dev, &p);
+            if (st != EPIC_OK) return st;
+            st = run_cadence(&c2, &s2, 1, &p, dev, stream);
+        }
         if (st != EPIC_OK) return st;
     }
     return EPIC_OK;
@@ -382,96 +502,22 @@ epic_status xfft_image(const epic_common *common, const epic_station *station, c
     int dev = 0;
     st = current_device(&dev);
     if (st != EPIC_OK) return st;
-    XfftPlanHandle pl;
-    st = get_xfft_plan(common, station, dev, &pl);
-    if (st != EPIC_OK) return st;
-    const int n_pol = common->n_pol, nx = station->nx, ny = station->ny;
-    const int64_t batch = static_cast<int64_t>(common->n_chan) * n_pol * n_pol;
-    float2 *g = static_cast<float2 *>(gridded);
-    if (!g) {
-        void *ws = nullptr;
-        st = get_workspace(dev, stream, 4, sizeof(float2) * static_cast<size_t>(batch) * nx * ny, &ws);
-        if (st != EPIC_OK) return st;
-        g = static_cast<float2 *>(ws);
-    }
-    const int W = 2 * station->kernel.support - 1;
-    void *part = nullptr;
-    st = get_workspace(dev, stream, 5, sizeof(float2) * static_cast<size_t>(batch) * W * W * nx * ny,
-                       &part);
-    if (st != EPIC_OK) return st;
-    st = launch_vis_grid(static_cast<const float2 *>(vis), pl, n_pol, station->n_elem,
-                         common->n_chan, nx, ny, static_cast<float2 *>(part), g, stream);
-    if (st != EPIC_OK) return st;
-    return launch_fft2_f32(nx, ny, batch, g, static_cast<float2 *>(station->image), dev, stream);
+    return xfft_image_run(common, station, static_cast<const float2 *>(vis),
+                          static_cast<float2 *>(gridded), dev, stream);
 }
 
 epic_status array_cadence(const epic_common *common, const epic_station *array,
                           const void *const *beams, int32_t beam_nx, int32_t beam_ny,
                           int32_t n_sel, const int32_t *pixels, hipStream_t stream)
 {
-    set_error("");
-    epic_status st = check_common(common);
-    if (st != EPIC_OK) return st;
-    if (!array) return fail(EPIC_ERR_INVALID_ARG, "array is NULL");
-    st = check_station(array, 0, false);
-    if (st != EPIC_OK) return st;
-    if (!array->image) return fail(EPIC_ERR_INVALID_ARG, "array image is NULL");
-    const int n_st = array->n_elem;
-    if (n_st > kMaxCombine) return fail(EPIC_ERR_INVALID_ARG, "at most 128 stations");
-    if (!beams) return fail(EPIC_ERR_INVALID_ARG, "beams is NULL");
-    StationImages bt{};
-    for (int m = 0; m < n_st; ++m) {
-        if (!beams[m]) return fail(EPIC_ERR_INVALID_ARG, "a station beam pointer is NULL");
-        bt.p[m] = static_cast<const float2 *>(beams[m]);
-    }
-    if (!is_pow2_grid(beam_nx) || !is_pow2_grid(beam_ny))
-        return fail(EPIC_ERR_INVALID_ARG, "beam_nx, beam_ny must be powers of two in 16..256");
-    if (n_sel < 1 || !pixels) return fail(EPIC_ERR_INVALID_ARG, "need n_sel >= 1 selected pixels");
-    const int npix_b = beam_nx * beam_ny;
-    for (int s = 0; s < n_sel; ++s)
-        if (pixels[s] < 0 || pixels[s] >= npix_b)
-            return fail(EPIC_ERR_INVALID_ARG, "selected pixel " + std::to_string(s) + " is off the beam grid");
-    st = check_geometry(common, array);
-    if (st != EPIC_OK) return fail(st, std::string("array: ") + last_error_cstr());
-    int dev = 0;
-    st = current_device(&dev);
-    if (st != EPIC_OK) return st;
-    void *ws_pix = nullptr, *ws_v = nullptr;
-    st = get_workspace(dev, stream, 7, sizeof(int32_t) * static_cast<size_t>(n_sel), &ws_pix);
-    if (st != EPIC_OK) return st;
-    EPIC_HIP_TRY(hipMemcpyAsync(ws_pix, pixels, sizeof(int32_t) * n_sel, hipMemcpyHostToDevice, stream));
-    // the (channel, pixel) problems in chunks whose array-scale voltages fit 1 GiB
-    const int n_pol = common->n_pol;
-    const int64_t per_item = static_cast<int64_t>(common->n_time) * n_st * n_pol * 8;
-    const int64_t total = static_cast<int64_t>(common->n_chan) * n_sel;
-    int64_t budget = int64_t{1} << 30;
-    if (const char *e = std::getenv("EPIC_ARRAY_BUDGET_KB")) budget = std::max<int64_t>(1, std::atoll(e)) << 10;
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(total, budget / per_item));
-    st = get_workspace(dev, stream, 6, static_cast<size_t>(chunk * per_item), &ws_v);
-    if (st != EPIC_OK) return st;
-    const size_t plane = static_cast<size_t>(n_pol) * n_pol * array->nx * array->ny;
-    for (int64_t i0 = 0; i0 < total; i0 += chunk) {
-        const int n = static_cast<int>(std::min(chunk, total - i0));
-        st = launch_gather_beams(bt, n_st, n_pol, common->n_time, npix_b, n_sel,
-                                 static_cast<const int32_t *>(ws_pix), i0, n,
-                                 static_cast<float2 *>(ws_v), stream);
-        if (st != EPIC_OK) return st;
-        std::vector<double> lam(n);
-        for (int k = 0; k < n; ++k) lam[k] = common->wavelength_m[(i0 + k) / n_sel];
-        epic_common c2 = *common;
-        c2.n_chan = n;
-        c2.wavelength_m = lam.data();
-        c2.volt_type = EPIC_CF32;
-        epic_station s2 = *array;
-        s2.volts = ws_v;
-        s2.image = static_cast<float2 *>(array->image) + static_cast<size_t>(i0) * plane;
-        PlanHandle p;
-        st = get_plan(&c2, &s2, dev, &p);
-        if (st != EPIC_OK) return st;
-        st = run_cadence(&c2, &s2, 1, &p, dev, stream);
-        if (st != EPIC_OK) return st;
-    }
-    return EPIC_OK;
+    return array_run(common, array, beams, beam_nx, beam_ny, n_sel, pixels, false, stream);
+}
+
+epic_status array_xfft(const epic_common *common, const epic_station *array,
+                       const void *const *beams, int32_t beam_nx, int32_t beam_ny, int32_t n_sel,
+                       const int32_t *pixels, hipStream_t stream)
+{
+    return array_run(common, array, beams, beam_nx, beam_ny, n_sel, pixels, true, stream);
 }
 
 epic_status image_cadence(const epic_common *common, const epic_station *stations,

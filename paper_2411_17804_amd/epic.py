@@ -34,7 +34,7 @@ KERNEL_GAUSSIAN = 1
 
 # every function the header declares
 ABI_FUNCTIONS = ("grid_voltages", "fft2_batched", "accumulate_power", "image_cadence",
-                 "image_to_visibilities", "combine_incoherent", "xfft_correlate", "xfft_image", "array_cadence", "grid_voltages_pol", "image_cadence_pol",
+                 "image_to_visibilities", "combine_incoherent", "xfft_correlate", "xfft_image", "array_cadence", "array_xfft", "grid_voltages_pol", "image_cadence_pol",
                  "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
                  "epic_timing_reset", "epic_status_string", "epic_last_error",
                  "epic_cache_clear")
@@ -100,6 +100,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.image_cadence_pol.restype = i32
     lib.array_cadence.argtypes = [P, P, P, i32, i32, i32, P, P]
     lib.array_cadence.restype = i32
+    lib.array_xfft.argtypes = [P, P, P, i32, i32, i32, P, P]
+    lib.array_xfft.restype = i32
     lib.epic_autotune.argtypes = [P, P, i32, P]
     lib.epic_autotune.restype = i32
     lib.epic_validate.argtypes = [P, P, i32]
@@ -303,6 +305,20 @@ def array_cadence(common: Common, array: Station, beams, beam_nx: int, beam_ny: 
     _check(lib.array_cadence(ctypes.byref(c), ctypes.byref(s), ptrs if beams else None, beam_nx,
                              beam_ny, pix.size, pix.ctypes.data if pix.size else None,
                              _stream(stream)))
+
+
+def array_xfft(common: Common, array: Station, beams, beam_nx: int, beam_ny: int, pixels,
+               stream=None):
+    """Coherent inter-station imaging by the XFFT route: arguments and output as
+    array_cadence."""
+    lib = load()
+    c, keep1 = common.to_c()
+    s, keep2 = array.to_c()
+    ptrs = (ctypes.c_void_p * max(1, len(beams)))(*[_dptr(t) for t in beams])
+    pix = np.ascontiguousarray(pixels, dtype=np.int32)
+    _check(lib.array_xfft(ctypes.byref(c), ctypes.byref(s), ptrs if beams else None, beam_nx,
+                          beam_ny, pix.size, pix.ctypes.data if pix.size else None,
+                          _stream(stream)))
 
 
 def _stations_c(stations):

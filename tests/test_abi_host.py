@@ -176,9 +176,10 @@ def test_array_cadence_rejects_bad_arguments_without_a_device():
     ok = [0x1000] * 8
     for beams, nb, pix in [(None, 64, [0]), ([0x1000] * 7 + [None], 64, [0]), (ok, 48, [0]),
                            (ok, 64, []), (ok, 64, [64 * 64]), (ok, 64, [-1])]:
-        with pytest.raises(epic.EpicError) as e:
-            epic.array_cadence(common, station, beams or [], nb, nb, pix, stream=0)
-        assert e.value.status == epic.EPIC_ERR_INVALID_ARG
+        for fn in (epic.array_cadence, epic.array_xfft):
+            with pytest.raises(epic.EpicError) as e:
+                fn(common, station, beams or [], nb, nb, pix, stream=0)
+            assert e.value.status == epic.EPIC_ERR_INVALID_ARG
     big = epic.Station(np.zeros((129, 2)), 64, 64, station.kernel_type, station.support,
                        station.sigma_cells, image=0x2000)
     with pytest.raises(epic.EpicError) as e:

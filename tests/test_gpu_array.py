@@ -101,3 +101,35 @@ def test_array_cadence(torch, case, monkeypatch):
     epic.array_cadence(common, arr, beams, nb, nb, pix)
     torch.cuda.synchronize()
     assert torch.equal(img, img2)
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_array_xfft_matches_array_cadence(torch, K):
+    # the XFFT route at array scale (Eq. 11, 13) against the EPIC route and
+    # the oracle: one image, up to FP32 rounding
+    from paper_2411_17804_amd import epic
+    say(f"array_xfft vs array_cadence, array kernel K={K}")
+    n_st, n_el, n_pol, nt, nb, na = 6, 10, 2, 24, 16, 32
+    lams = np.array([2.0, 1.5])
+    elems, cen, volts = _scene(40 + K, n_st, n_el, n_pol, nt, lams)
+    pix = np.sort(np.random.default_rng([17804, 12]).choice(nb * nb, 29, replace=False)).astype(np.int32)
+    beams = _gpu_beams(epic, torch, elems, volts, lams, n_pol, nt, nb, 3)
+    ktype = W.KERNEL_GAUSSIAN if K > 1 else W.KERNEL_NEAREST
+    common = epic.Common(n_pol, lams, 4.0, nt, W.CF32, epic.FP32_FFT)
+    shape = (len(lams), pix.size, n_pol ** 2, na, na, 2)
+    a = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    b = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    epic.array_cadence(common, epic.Station(cen, na, na, ktype, K, K / 6.0, image=a), beams, nb, nb, pix)
+    epic.array_xfft(common, epic.Station(cen, na, na, ktype, K, K / 6.0, image=b), beams, nb, nb, pix)
+    torch.cuda.synchronize()
+    ga, gb = to_complex(a), to_complex(b)
+    obeams = [oracle.station_beams(e, lams, 0.5, nb, nb, W.KERNEL_GAUSSIAN, 3, 0.5, v)
+              for e, v in zip(elems, volts)]
+    ref = oracle.array_image(obeams, pix, cen, lams, 4.0, na, na, ktype, K, K / 6.0)
+    worst_x = worst_ab = 0.0
+    for c in range(len(lams)):
+        for si in range(pix.size):
+            worst_x = max(worst_x, float(oracle.image_error(gb[c, si], ref[c, si], n_pol).max()))
+            worst_ab = max(worst_ab, float(oracle.image_error(gb[c, si], ga[c, si], n_pol).max()))
+    say(f"  XFFT vs oracle {worst_x:.2e}, XFFT vs EPIC route {worst_ab:.2e}")
+    assert worst_x <= FP32_TOL and worst_ab <= 2 * FP32_TOL
