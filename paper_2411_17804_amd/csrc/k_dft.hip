@@ -237,6 +237,146 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
     }
 }
 
+// The whole 2-D transform of one N x N plane (N <= 64) in one work-group:
+// the pass along y leaves its result in LDS, rescaled by a new power of two
+// and re-split, as the operand of the pass along x, so HBM sees the plane
+// once in and once out (the two-launch form writes and re-reads the
+// intermediate).  Same fragments, tables and arithmetic as k_dft_pass.
+template <int N, int PREC>
+__global__ __launch_bounds__(256) void k_dft2_plane(const float2 *__restrict__ in,
+                                                    float2 *__restrict__ out,
+                                                    const typename Split<PREC>::vec8 *__restrict__ tab)
+{
+    using S = Split<PREC>;
+    using vec8 = typename S::vec8;
+    using scalar = typename S::scalar;
+    constexpr int NTW = N / 16;           // column tiles: the whole plane
+    constexpr int MT = 2 * N / 16;        // real M-tiles
+    constexpr int KS = N / 16;            // K-steps
+    constexpr int MTW = (MT + 3) / 4;     // M-tiles per wave
+    constexpr int JP = N + 4;             // LDS pitch (packed complex) per column
+    constexpr int PER = N * N / 256;      // plane values per thread
+    extern __shared__ uint32_t lds[];
+    uint32_t *lhi = lds;                  // [N][JP]: column c, transform index j
+    uint32_t *llo = lds + N * JP;
+    __shared__ float red[4];
+
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int g = lane / 16, r = lane % 16;
+    const size_t b = blockIdx.x;
+    const float2 *src = in + b * N * N;
+    const vec8 *tab_lo = tab + static_cast<size_t>(MT) * KS * 64;
+
+    auto block_max = [&](float mx) {
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        __syncthreads();                  // red[] of an earlier use has been read
+        if (lane == 0) red[wave] = mx;
+        __syncthreads();
+        return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    };
+    auto put = [&](int c, int j, float re, float im) {
+        scalar hr, lr, hi_, li;
+        split<PREC>(re, hr, lr);
+        split<PREC>(im, hi_, li);
+        lhi[c * JP + j] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hr)) |
+                          (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hi_)) << 16);
+        llo[c * JP + j] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, lr)) |
+                          (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, li)) << 16);
+    };
+    floatx4_t acc[MTW][NTW];
+    auto transform = [&]() {              // acc = F . (LDS operand), both split parts
+#pragma unroll
+        for (int w = 0; w < MTW; ++w)
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) acc[w][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        // every K step's table fragments are loaded before the first product
+        vec8 ah[KS][MTW], al[KS][MTW];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int w = 0; w < MTW; ++w) {
+                const int mt = wave + 4 * w;
+                if (mt < MT) {
+                    ah[ks][w] = tab[(mt * KS + ks) * 64 + lane];
+                    al[ks][w] = tab_lo[(mt * KS + ks) * 64 + lane];
+                }
+            }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) {
+                const int c = t * 16 + r, j0 = ks * 16 + 4 * g;
+                const vec8 bh = *reinterpret_cast<const vec8 *>(&lhi[c * JP + j0]);
+                const vec8 bl = *reinterpret_cast<const vec8 *>(&llo[c * JP + j0]);
+#pragma unroll
+                for (int w = 0; w < MTW; ++w)
+                    if (wave + 4 * w < MT) acc[w][t] = mma3<PREC>(ah[ks][w], al[ks][w], bh, bl, acc[w][t]);
+            }
+        }
+    };
+
+    // pass along y: operand column x, index y
+    float2 xin[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) xin[q] = src[threadIdx.x + 256 * q];
+    float s1 = 1.f;
+    if constexpr (S::needs_scale) {
+        float mx = 0.f;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) mx = fmaxf(mx, fmaxf(fabsf(xin[q].x), fabsf(xin[q].y)));
+        s1 = pow2_scale(block_max(mx));
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + 256 * q;          // i = y * N + x
+        put(i % N, i / N, xin[q].x * s1, xin[q].y * s1);
+    }
+    __syncthreads();
+    transform();                                      // acc: P[k_y][x] * s1
+
+    // pass along x: operand column k_y, index x, rescaled for the split
+    float s2 = 1.f / s1;
+    if constexpr (S::needs_scale) {
+        float mx = 0.f;
+#pragma unroll
+        for (int w = 0; w < MTW; ++w)
+#pragma unroll
+            for (int t = 0; t < NTW; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) mx = fmaxf(mx, fabsf(acc[w][t][e]));
+        const float m = block_max(mx) / s1;           // largest |P| component
+        s2 = pow2_scale(m) / s1;                      // exact: powers of two
+    }
+    __syncthreads();                                  // every pass-1 operand read
+#pragma unroll
+    for (int w = 0; w < MTW; ++w) {
+        const int mt = wave + 4 * w;
+        if (mt >= MT) continue;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const int x = t * 16 + r, k = mt * 8 + 2 * g;
+            const floatx4_t a = acc[w][t];
+            put(k, x, a[0] * s2, a[1] * s2);
+            put(k + 1, x, a[2] * s2, a[3] * s2);
+        }
+    }
+    __syncthreads();
+    transform();                                      // acc: Z[k_y][k_x] * (s1 s2)
+    const float inv = 1.f / (s1 * s2);
+#pragma unroll
+    for (int w = 0; w < MTW; ++w) {
+        const int mt = wave + 4 * w;
+        if (mt >= MT) continue;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const int ky = t * 16 + r, kx = mt * 8 + 2 * g;
+            const floatx4_t a = acc[w][t];
+            *reinterpret_cast<float4 *>(&out[(b * N + ky) * N + kx]) =
+                make_float4(a[0] * inv, a[1] * inv, a[2] * inv, a[3] * inv);
+        }
+    }
+}
+
 namespace {
 
 struct Prune {
@@ -293,6 +433,44 @@ epic_status pass_any(int n, int64_t batch, int m, const float2 *in, float2 *out,
     return fail(EPIC_ERR_INTERNAL, "dft pass: unexpected size");
 }
 
+template <int N, int PREC>
+epic_status dft2_plane(int64_t batch, const float2 *in, float2 *out, const void *tab, hipStream_t stream)
+{
+    const size_t bytes = sizeof(uint32_t) * 2 * N * (N + 4);
+    auto k = k_dft2_plane<N, PREC>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(bytes));
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    KernelTimer timer("dft2_plane", stream);
+    for (int64_t b0 = 0; b0 < batch; b0 += (int64_t{1} << 30)) {
+        const int64_t nb = std::min<int64_t>(int64_t{1} << 30, batch - b0);
+        hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(nb)), dim3(256), bytes, stream,
+                           in + b0 * N * N, out + b0 * N * N,
+                           static_cast<const typename Split<PREC>::vec8 *>(tab));
+        EPIC_HIP_TRY(hipGetLastError());
+    }
+    return EPIC_OK;
+}
+
+epic_status dft2_plane_any(int n, int64_t batch, int precision, const float2 *in, float2 *out,
+                           int device, hipStream_t stream)
+{
+    const void *tab = nullptr;
+    epic_status s = get_dft_tables(n, precision, device, &tab);
+    if (s != EPIC_OK) return s;
+    const bool f16 = precision == EPIC_FP16_SPLIT;
+    switch (n) {
+    case 16: return f16 ? dft2_plane<16, EPIC_FP16_SPLIT>(batch, in, out, tab, stream)
+                        : dft2_plane<16, EPIC_BF16_SPLIT>(batch, in, out, tab, stream);
+    case 32: return f16 ? dft2_plane<32, EPIC_FP16_SPLIT>(batch, in, out, tab, stream)
+                        : dft2_plane<32, EPIC_BF16_SPLIT>(batch, in, out, tab, stream);
+    case 64: return f16 ? dft2_plane<64, EPIC_FP16_SPLIT>(batch, in, out, tab, stream)
+                        : dft2_plane<64, EPIC_BF16_SPLIT>(batch, in, out, tab, stream);
+    }
+    return fail(EPIC_ERR_INTERNAL, "dft2 plane: unexpected size");
+}
+
 }  // namespace
 
 epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, const float2 *in,
@@ -300,6 +478,7 @@ epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, cons
                               int items_per_chan)
 {
     const Prune p1{chan, items_per_chan, 0}, p2{chan, items_per_chan, 1};
+    if (!chan && nx == ny && nx <= 64) return dft2_plane_any(nx, batch, precision, in, out, device, stream);
     const void *tab_y = nullptr, *tab_x = nullptr;
     epic_status s = get_dft_tables(ny, precision, device, &tab_y);
     if (s != EPIC_OK) return s;
