@@ -118,6 +118,31 @@ def split_mfma_flops(cfg):
     return total
 
 
+def tiles128_mfma_flops(cfg):
+    """Matrix-core flops of the 128 x 128 split-precision plane transform for
+    one cadence (stations with 128 x 128 grids): per sample, pol and channel,
+    16 M-tiles (16 output rows each) times ka x cb tiles in the first pass and
+    cb x 8 in the second, three split products of 16x16x32 each, where ka >= cb
+    are the footprint box's sides in 16-cell tiles counted from its first cell
+    (the longer side is transformed first).  The box follows the element cells and kernel support
+    exactly as the plan places them."""
+    total = 0
+    for st in cfg.stations:
+        if st.nx != 128 or st.ny != 128:
+            continue
+        h = (st.support - 1) // 2
+        for lam in cfg.wavelengths_m:
+            d = W.GRID_SPACING_WL * lam
+            ci = np.floor(st.pos_m[:, 0] / d + st.nx // 2 + 0.5)
+            cj = np.floor(st.pos_m[:, 1] / d + st.ny // 2 + 0.5)
+            bw = int(ci.max() - ci.min()) + 2 * h + 1
+            bh = int(cj.max() - cj.min()) + 2 * h + 1
+            sx, sy = -(-bw // 16), -(-bh // 16)
+            ka, cb = max(sx, sy), min(sx, sy)
+            total += 3 * 16 * 16 * 32 * 2 * 16 * cb * (ka + 8) * cfg.n_time * cfg.n_pol
+    return total
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,7 +287,8 @@ def main():
                 "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": dom_chunk,
                 "flop_per_pixel_sample": round(flop_px, 2)}
     else:
-        fl = split_mfma_flops(cfg) if dom_name == "fused_dft_cadence" else None
+        fl = {"fused_dft_cadence": split_mfma_flops,
+              "dft2_tiles128": tiles128_mfma_flops}.get(dom_name, lambda c: None)(cfg)
         achieved = fl / launches_per_step / (dom_avg_ms / 1e3) / 1e12 if fl else None
         roof = {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
                 "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
@@ -354,13 +380,18 @@ def stage_rooflines(cfg, common, station, nt=64, reps=3):
     res["fft2_batched_fp32"] = {"ms": round(ms, 3), "bound": "hbm", "bytes": b,
                                 "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
                                 "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    # the dense DFT-matrix products: planes non-zero everywhere (the gridded
+    # planes are zero outside the footprint, and the 128 x 128 transform skips
+    # all-zero tiles, which the dense flop count would not reflect)
+    dense = torch.randn_like(grid)
     for name, p in (("fp16", epic.FP16_SPLIT), ("bf16", epic.BF16_SPLIT)):
-        ms = timed(lambda: epic.fft2_batched(st.nx, st.ny, batch, p, grid, out))
+        ms = timed(lambda: epic.fft2_batched(st.nx, st.ny, batch, p, dense, out))
         fl = batch * 3 * 8 * (st.ny ** 2 * st.nx + st.nx ** 2 * st.ny)
         res[f"fft2_batched_{name}_split"] = {
             "ms": round(ms, 3), "bound": "mfma", "flops": fl,
             "achieved": round(fl / ms / 1e9, 1), "unit": "TFLOP/s",
             "frac": round(fl / ms / 1e9 / PEAK_FP16_MFMA_TFLOPS, 4)}
+    del dense
     ms = timed(lambda: epic.accumulate_power(cfg.n_pol, st.nx, st.ny, cfg.n_chan, nt, out, acc[0],
                                              acc[1], nt, img))
     b = field_bytes + 5 * cfg.n_chan * cfg.n_pol ** 2 * npix * 8

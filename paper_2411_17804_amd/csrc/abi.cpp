@@ -161,7 +161,7 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
             // the planes are zero outside each channel's footprint box: the
             // transform sums over the box's tiles only
             st = launch_dft2_split(s->nx, s->ny, batch, c->precision, field, field, device, stream,
-                                   sd.chan, nt * n_pol);
+                                   sd.chan, nt * n_pol, p.max_bw, p.max_bh);
         if (st != EPIC_OK) return st;
         const bool last = t0 + nt >= c->n_time;
         st = launch_power(n_pol, static_cast<int>(npix), n_chan, nt, field, acc_sum, acc_comp,

@@ -212,10 +212,13 @@ epic_status launch_power(int n_pol, int npix, int n_chan, int nt, const float2 *
 
 // With chan set, batch item b is a plane of channel b / items_per_chan whose
 // input is zero outside that channel's footprint box; the transform then sums
-// only the footprint's 16-row/16-column tiles (same result).
+// only the footprint's 16-row/16-column tiles (same result).  max_bw / max_bh
+// bound the boxes' sides over the channels (they size the LDS of the 128 x 128
+// plane kernel).
 epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, const float2 *in,
                               float2 *out, int device, hipStream_t stream,
-                              const ChanPlan *chan = nullptr, int items_per_chan = 1);
+                              const ChanPlan *chan = nullptr, int items_per_chan = 1,
+                              int max_bw = 0, int max_bh = 0);
 
 // Fused FP32 cadence for square grids n in {16, 32, 64}: partial sums of the
 // four real product components per (station, channel, time chunk) item.

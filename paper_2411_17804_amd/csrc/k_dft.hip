@@ -9,6 +9,7 @@
 // the integer (k j mod n) / n), split into hi + lo parts and stored in MFMA
 // A-fragment order.  Each work-group scales its block of input columns by a
 // power of two so the FP16 parts cannot overflow (exact, undone on store).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -377,6 +378,288 @@ __global__ __launch_bounds__(256) void k_dft2_plane(const float2 *__restrict__ i
     }
 }
 
+// acc[w][t] = sum over K tiles 0 .. nks - 1 of the 128-point DFT table's
+// M-tile mt0 + mt_step w times the LDS operand's column tile col0 + t
+// (t < ncols <= TMAX; operand pitch jp words per column), both split parts.  The table fragments are double-buffered:
+// step s + 1's loads are in flight while step s's products run.
+template <int PREC, int MTW, int TMAX>
+__device__ __forceinline__ void tile_products128(floatx4_t (&acc)[MTW][TMAX],
+                                                 const typename Split<PREC>::vec8 *__restrict__ tab,
+                                                 const uint32_t *lhi, const uint32_t *llo, int mt0,
+                                                 int mt_step, int nks, int col0, int ncols, int jp)
+{
+    using vec8 = typename Split<PREC>::vec8;
+    constexpr int MT = 16, KS = 8;
+    const int lane = threadIdx.x % 64, g = lane / 16, r = lane % 16;
+    const vec8 *tab_lo = tab + MT * KS * 64;
+#pragma unroll
+    for (int w = 0; w < MTW; ++w)
+#pragma unroll
+        for (int t = 0; t < TMAX; ++t) acc[w][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    auto load_a = [&](int ks, vec8 *ah, vec8 *al) {
+#pragma unroll
+        for (int w = 0; w < MTW; ++w) {
+            const int i = ((mt0 + mt_step * w) * KS + ks) * 64 + lane;
+            ah[w] = tab[i];
+            al[w] = tab_lo[i];
+        }
+    };
+    auto step = [&](int s, const vec8 *ah, const vec8 *al) {
+#pragma unroll
+        for (int t = 0; t < TMAX; ++t) {
+            if (t >= ncols) break;
+            const int o = ((col0 + t) * 16 + r) * jp + s * 16 + 4 * g;
+            const vec8 bh = *reinterpret_cast<const vec8 *>(&lhi[o]);
+            const vec8 bl = *reinterpret_cast<const vec8 *>(&llo[o]);
+#pragma unroll
+            for (int w = 0; w < MTW; ++w) acc[w][t] = mma3<PREC>(ah[w], al[w], bh, bl, acc[w][t]);
+        }
+    };
+    vec8 ah0[MTW], al0[MTW], ah1[MTW], al1[MTW];
+    load_a(0, ah0, al0);
+    for (int s = 0; s < nks; s += 2) {
+        if (s + 1 < nks) load_a(s + 1, ah1, al1);
+        step(s, ah0, al0);
+        if (s + 1 >= nks) break;
+        if (s + 2 < nks) load_a(s + 2, ah0, al0);
+        step(s + 1, ah1, al1);
+    }
+}
+
+// The 2-D transform of one 128 x 128 plane in one work-group, summing over the
+// box of its non-zero cells only.  The box comes from the channel's footprint
+// (chan set: only the box is read) or, for a dense call, from the plane itself
+// (every cell is read).  The sums run over 16-cell tiles counted from the
+// box's first cell (x0, y0), moved left or down where the tiles would pass
+// the plane's edge, so a box w cells wide takes ceil(w / 16) tiles; by the
+// shift theorem the transform of the shifted operand times
+// exp(+2 pi i (kx x0 + ky y0) / 128) is the transform of the plane (the
+// factors from an FP64 table).  The longer side (ka tiles) is transformed
+// first over the cb <= ka tile columns of the other side; the second pass
+// then sums cb tiles for all 128 outputs of the first, so the LDS holds at
+// most 2 x max(16 cb (16 ka + 4), 128 (16 cb + 4)) words (the operands of the
+// two passes, hi and lo parts, one after the other).  Cells outside the box
+// add exact zeros, so the result depends only on the box.  Fragments,
+// tables, scaling and split as in k_dft2_plane.
+//
+// Every wave multiplies a pair of M-tiles (p, p + 8) by up to 4 column tiles,
+// so each operand fragment read from LDS feeds six products.  NW = 16 waves
+// (any box): pair wave % 8, column tiles 4 (wave / 8) .. + 3 in both passes.
+// NW = 8 waves (footprint boxes with cb <= 4, which need at most 68 KB of
+// LDS, so two work-groups share a compute unit): pair wave, all cb column
+// tiles in the first pass, and the two column halves in two rounds in the
+// second, each stored as it ends.
+template <int PREC, int NW>
+__global__ __launch_bounds__(64 * NW, NW == 8 ? 4 : 1) void k_dft2_tiles128(const float2 *__restrict__ in,
+                                                           float2 *__restrict__ out,
+                                                           const typename Split<PREC>::vec8 *__restrict__ tab,
+                                                           const float2 *__restrict__ phase,
+                                                           const ChanPlan *__restrict__ chan, int64_t item0,
+                                                           int items_per_chan, int lds_words)
+{
+    static_assert(NW == 16 || NW == 8, "16 or 8 waves");
+    using S = Split<PREC>;
+    using scalar = typename S::scalar;
+    constexpr int N = 128, KS = 8, NT = 64 * NW;
+    constexpr int SLOTS = NT / 256;       // tiles read at once (256 threads per tile)
+    constexpr int MAX_TILES = NW == 16 ? 64 : 32;
+    constexpr int PER = MAX_TILES / SLOTS;
+    extern __shared__ uint32_t lds[];
+    __shared__ float red[NW];
+    __shared__ int redi[4][NW];
+
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int g = lane / 16, r = lane % 16;
+    const int tid = threadIdx.x;
+    const size_t b = blockIdx.x;
+    const float2 *src = in + b * N * N;
+    float2 *dst = out + b * N * N;
+
+    auto block_max = [&](float mx) {
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        __syncthreads();                  // red[] of an earlier use has been read
+        if (lane == 0) red[wave] = mx;
+        __syncthreads();
+        float m = red[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) m = fmaxf(m, red[w]);
+        return m;
+    };
+
+    // the region read (first cell x0, y0; sx x sy tiles): the footprint
+    // box's tiles, or the whole plane
+    int x0 = 0, y0 = 0, sx = KS, sy = KS;
+    if (chan) {
+        const ChanPlan cp = chan[(item0 + static_cast<int64_t>(b)) / items_per_chan];
+        sx = (cp.bw + 15) >> 4;
+        sy = (cp.bh + 15) >> 4;
+        x0 = min(cp.x0, N - 16 * sx);
+        y0 = min(cp.y0, N - 16 * sy);
+    }
+    if (sx * sy > MAX_TILES || (NW == 8 && min(sx, sy) > 4)) return;   // the host dispatches by box size
+    // thread: cell (tid % 16, (tid / 16) % 16) of tiles tid / 256, + SLOTS,
+    // + 2 SLOTS, ... of the region in raster order; tt / sx by multiply-shift
+    // (exact for tile indices below 64 and sx <= 8)
+    const uint32_t inv_sx = (65536u + sx - 1) / sx;
+    const int cx = tid % 16, cy = (tid / 16) % 16, slot = tid / 256;
+    const int rsx = sx, rx0 = x0, ry0 = y0, n_tiles = sx * sy;   // the region read
+    float2 xin[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int tt = slot + SLOTS * q;
+        xin[q] = make_float2(0.f, 0.f);
+        if (tt < n_tiles) {
+            const int tr = static_cast<int>((static_cast<uint32_t>(tt) * inv_sx) >> 16), tc = tt - tr * sx;
+            xin[q] = src[(y0 + tr * 16 + cy) * N + x0 + tc * 16 + cx];
+        }
+    }
+    if (!chan) {
+        // dense call: the box of the non-zero cells
+        int lo_x = N, hi_x = -1, lo_y = N, hi_y = -1;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int tt = slot + SLOTS * q;
+            if (xin[q].x != 0.f || xin[q].y != 0.f) {
+                const int x = (tt % KS) * 16 + cx, y = (tt / KS) * 16 + cy;
+                lo_x = min(lo_x, x);
+                hi_x = max(hi_x, x);
+                lo_y = min(lo_y, y);
+                hi_y = max(hi_y, y);
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            lo_x = min(lo_x, __shfl_xor(lo_x, o));
+            hi_x = max(hi_x, __shfl_xor(hi_x, o));
+            lo_y = min(lo_y, __shfl_xor(lo_y, o));
+            hi_y = max(hi_y, __shfl_xor(hi_y, o));
+        }
+        if (lane == 0) {
+            redi[0][wave] = lo_x;
+            redi[1][wave] = hi_x;
+            redi[2][wave] = lo_y;
+            redi[3][wave] = hi_y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            lo_x = min(lo_x, redi[0][w]);
+            hi_x = max(hi_x, redi[1][w]);
+            lo_y = min(lo_y, redi[2][w]);
+            hi_y = max(hi_y, redi[3][w]);
+        }
+        if (hi_x < 0) {                   // an all-zero plane
+            for (int i = tid; i < N * N; i += NT) dst[i] = make_float2(0.f, 0.f);
+            return;
+        }
+        sx = (hi_x - lo_x + 16) >> 4;
+        sy = (hi_y - lo_y + 16) >> 4;
+        x0 = min(lo_x, N - 16 * sx);
+        y0 = min(lo_y, N - 16 * sy);
+    }
+    const bool x_first = sx > sy;         // the longer side first
+    const int ka = x_first ? sx : sy, cb = x_first ? sy : sx;
+    const int jp1 = 16 * ka + 4, jp2 = 16 * cb + 4;   // LDS pitches (words per column)
+    const int half = max(16 * cb * jp1, N * jp2);
+    if (2 * half > lds_words) return;     // cannot happen: the host sizes the LDS for the box
+    uint32_t *lhi = lds, *llo = lds + half;
+
+    auto put = [&](int o, float re, float im) {     // o: word offset in the operand
+        scalar hr, lr, hi_, li;
+        split<PREC>(re, hr, lr);
+        split<PREC>(im, hi_, li);
+        lhi[o] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hr)) |
+                 (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, hi_)) << 16);
+        llo[o] = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, lr)) |
+                 (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, li)) << 16);
+    };
+
+    // pass 1 along the longer side: operand column = position along the
+    // shorter side, index = position along the longer side (box-relative)
+    float s1 = 1.f;
+    if constexpr (S::needs_scale) {
+        float mx = 0.f;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) mx = fmaxf(mx, fmaxf(fabsf(xin[q].x), fabsf(xin[q].y)));
+        s1 = pow2_scale(block_max(mx));
+    }
+    {
+        const uint32_t inv_r = (65536u + rsx - 1) / rsx;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int tt = slot + SLOTS * q;
+            if (tt >= n_tiles) break;
+            const int tr = static_cast<int>((static_cast<uint32_t>(tt) * inv_r) >> 16), tc = tt - tr * rsx;
+            const int dx = rx0 + tc * 16 + cx - x0, dy = ry0 + tr * 16 + cy - y0;  // box-relative
+            if (dx < 0 || dx >= 16 * sx || dy < 0 || dy >= 16 * sy) continue;
+            const int c = x_first ? dy : dx, j = x_first ? dx : dy;
+            put(c * jp1 + j, xin[q].x * s1, xin[q].y * s1);
+        }
+    }
+    __syncthreads();
+    const int pair = wave % 8, col1 = NW == 16 ? 4 * (wave / 8) : 0;
+    const int n1 = min(4, max(0, cb - col1));         // this wave's pass-1 column tiles
+    floatx4_t acc1[2][4];                 // P[k1][c] * s1, k1 along the longer side
+    tile_products128<PREC, 2, 4>(acc1, tab, lhi, llo, pair, 8, ka, col1, n1, jp1);
+
+    // pass 2 along the shorter side: operand column k1, index c
+    float s2 = 1.f / s1;
+    if constexpr (S::needs_scale) {
+        float mx = 0.f;
+#pragma unroll
+        for (int w = 0; w < 2; ++w)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) mx = fmaxf(mx, fabsf(acc1[w][t][e]));
+        const float m = block_max(mx) / s1;           // largest |P| component
+        s2 = pow2_scale(m) / s1;                      // exact: powers of two
+    }
+    __syncthreads();                                  // every pass-1 operand read
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        const int k1 = (pair + 8 * w) * 8 + 2 * g;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t >= n1) break;
+            const int c = (col1 + t) * 16 + r;
+            const floatx4_t a = acc1[w][t];
+            put(k1 * jp2 + c, a[0] * s2, a[1] * s2);
+            put((k1 + 1) * jp2 + c, a[2] * s2, a[3] * s2);
+        }
+    }
+    __syncthreads();
+    const float inv = 1.f / (s1 * s2);
+    // the shift back: output (kx, ky) times phase[(kx x0 + ky y0) mod 128]
+    const int s1x = x_first ? x0 : y0, s2x = x_first ? y0 : x0;   // shifts along k1, k2
+    auto rot = [&](float re, float im, int m) {
+        const float2 w = phase[m & (N - 1)];
+        return make_float2((re * w.x - im * w.y) * inv, (re * w.y + im * w.x) * inv);
+    };
+#pragma unroll
+    for (int round = 0; round < 16 / NW; ++round) {
+        const int col2 = NW == 16 ? 4 * (wave / 8) : 4 * round;
+        floatx4_t acc[2][4];              // Z[k2][k1] * (s1 s2), k2 along the shorter side
+        tile_products128<PREC, 2, 4>(acc, tab, lhi, llo, pair, 8, cb, col2, 4, jp2);
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int k2 = (pair + 8 * w) * 8 + 2 * g;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k1 = (col2 + t) * 16 + r;
+                const floatx4_t a = acc[w][t];
+                const int m = k1 * s1x + k2 * s2x;
+                const float2 v0 = rot(a[0], a[1], m), v1 = rot(a[2], a[3], m + s2x);
+                if (x_first) {            // k1 = kx, k2 = ky
+                    dst[k2 * N + k1] = v0;
+                    dst[(k2 + 1) * N + k1] = v1;
+                } else {                  // k1 = ky, k2 = kx
+                    *reinterpret_cast<float4 *>(&dst[k1 * N + k2]) = make_float4(v0.x, v0.y, v1.x, v1.y);
+                }
+            }
+        }
+    }
+}
+
 namespace {
 
 struct Prune {
@@ -471,13 +754,76 @@ epic_status dft2_plane_any(int n, int64_t batch, int precision, const float2 *in
     return fail(EPIC_ERR_INTERNAL, "dft2 plane: unexpected size");
 }
 
+// exp(+2 pi i m / 128), m = 0 .. 127, as FP32 pairs from FP64
+void fill_phase128(int n, int, void *dst)
+{
+    float2 *p = static_cast<float2 *>(dst);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int m = 0; m < n; ++m)
+        p[m] = make_float2(static_cast<float>(std::cos(two_pi * m / n)),
+                           static_cast<float>(std::sin(two_pi * m / n)));
+}
+
+epic_status get_phase128(int device, const void **out)
+{
+    return cache_dft_table(128, 0x20, device, sizeof(float2) * 128, fill_phase128, out);
+}
+
+template <int PREC>
+epic_status dft2_tiles128(int64_t batch, const float2 *in, float2 *out, const void *tab,
+                          const ChanPlan *chan, int items_per_chan, int max_bw, int max_bh,
+                          hipStream_t stream, int device)
+{
+    // LDS for the largest box: w cells take ceil(w / 16) tiles; the longer
+    // side is transformed first
+    int sx = 8, sy = 8;
+    if (chan) {
+        sx = std::min(8, (max_bw + 15) / 16);
+        sy = std::min(8, (max_bh + 15) / 16);
+    }
+    const void *phase = nullptr;
+    epic_status s = get_phase128(device, &phase);
+    if (s != EPIC_OK) return s;
+    const int ka = std::max(sx, sy), cb = std::min(sx, sy);
+    const int words = 2 * std::max(16 * cb * (16 * ka + 4), 128 * (16 * cb + 4));
+    const size_t bytes = sizeof(uint32_t) * words;
+    // footprint boxes no more than 4 tiles on their shorter side: 8 waves,
+    // two work-groups per compute unit
+    const bool small = chan && cb <= 4;
+    auto k = small ? k_dft2_tiles128<PREC, 8> : k_dft2_tiles128<PREC, 16>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(bytes));
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    KernelTimer timer("dft2_tiles128", stream);
+    for (int64_t b0 = 0; b0 < batch; b0 += (int64_t{1} << 30)) {
+        const int64_t nb = std::min<int64_t>(int64_t{1} << 30, batch - b0);
+        hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(nb)), dim3(small ? 512 : 1024), bytes, stream,
+                           in + b0 * 128 * 128, out + b0 * 128 * 128,
+                           static_cast<const typename Split<PREC>::vec8 *>(tab),
+                           static_cast<const float2 *>(phase), chan, b0, items_per_chan, words);
+        EPIC_HIP_TRY(hipGetLastError());
+    }
+    return EPIC_OK;
+}
+
 }  // namespace
 
 epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, const float2 *in,
                               float2 *out, int device, hipStream_t stream, const ChanPlan *chan,
-                              int items_per_chan)
+                              int items_per_chan, int max_bw, int max_bh)
 {
     const Prune p1{chan, items_per_chan, 0}, p2{chan, items_per_chan, 1};
+    if (nx == 128 && ny == 128 && (!chan || (max_bw > 0 && max_bh > 0))) {
+        const void *tab = nullptr;
+        epic_status s = get_dft_tables(128, precision, device, &tab);
+        if (s != EPIC_OK) return s;
+        return precision == EPIC_FP16_SPLIT
+                   ? dft2_tiles128<EPIC_FP16_SPLIT>(batch, in, out, tab, chan, items_per_chan, max_bw,
+                                                    max_bh, stream, device)
+                   : dft2_tiles128<EPIC_BF16_SPLIT>(batch, in, out, tab, chan, items_per_chan, max_bw,
+                                                    max_bh, stream, device);
+    }
     if (!chan && nx == ny && nx <= 64) return dft2_plane_any(nx, batch, precision, in, out, device, stream);
     const void *tab_y = nullptr, *tab_x = nullptr;
     epic_status s = get_dft_tables(ny, precision, device, &tab_y);

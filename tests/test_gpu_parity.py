@@ -329,6 +329,35 @@ def test_fft2_batched_split(torch, prec, nx, ny):
     assert torch.equal(xin, out)
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_fft2_batched_split_sparse_planes(torch, prec):
+    # 128 x 128 planes that are zero outside a box: the transform finds the
+    # box of non-zero 16 x 16 tiles itself and sums over it only (wide, tall,
+    # single-tile, corner-cell, full and all-zero planes in one batch)
+    from paper_2411_17804_amd import epic
+    say(f"fft2_batched {prec} 128x128 sparse planes")
+    p = epic.FP16_SPLIT if prec == "fp16" else epic.BF16_SPLIT
+    rng = np.random.default_rng([17804, 128, 21])
+    boxes = [(30, 68, 46, 36), (40, 36, 20, 68), (17, 9, 100, 5), (127, 1, 127, 1), (0, 128, 0, 128),
+             None]
+    x = np.zeros((len(boxes), 128, 128), np.complex128)
+    for i, bx in enumerate(boxes):
+        if bx is not None:
+            x0, bw, y0, bh = bx
+            x[i, y0:y0 + bh, x0:x0 + bw] = rng.standard_normal((bh, bw)) + 1j * rng.standard_normal((bh, bw))
+    x = x.astype(np.complex64).astype(np.complex128)
+    xin = from_complex(x)
+    out = torch.empty_like(xin)
+    epic.fft2_batched(128, 128, len(boxes), p, xin, out)
+    torch.cuda.synchronize()
+    got = to_complex(out)
+    ref = oracle.fft2(x)
+    errs = [_rel(got[b], ref[b]) for b in range(len(boxes) - 1)]
+    say(f"  {prec}: errors {['%.2e' % e for e in errs]}")
+    assert max(errs) <= SPLIT_TOL[prec], errs
+    assert not np.any(got[-1]), "an all-zero plane transforms to zeros"
+
+
 SPLIT_CASES = {
     "C2-fp16-2ch": (2, [0, 1023], 40, "fp16"),
     "C3-fp16-2ch": (3, [0, 255], 12, "fp16"),
