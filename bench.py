@@ -286,6 +286,19 @@ def main():
                 if cfg.n_chan == W.make_config(cfg.index).n_chan and args.n_time is None else None,
                 "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": dom_chunk,
                 "flop_per_pixel_sample": round(flop_px, 2)}
+    elif dom_name == "square_accumulate":
+        # the composed path's squaring and compensated accumulation: HBM-bound;
+        # per launch it reads a chunk of transformed planes and reads and
+        # writes the (sum, compensation) accumulators, and the last launch of
+        # each station writes its image
+        acc_b = sum(cfg.n_chan * cfg.n_pol ** 2 * s.nx * s.ny * 8 for s in cfg.stations)
+        field_b = sum(cfg.n_chan * cfg.n_time * cfg.n_pol * s.nx * s.ny * 8 for s in cfg.stations)
+        bytes_step = field_b + launches_per_step * 4 * acc_b / len(cfg.stations) + acc_b
+        achieved = bytes_step / launches_per_step / (dom_avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": None,
+                "bytes_per_step": int(bytes_step)}
     else:
         fl = {"fused_dft_cadence": split_mfma_flops,
               "dft2_tiles128": tiles128_mfma_flops}.get(dom_name, lambda c: None)(cfg)

@@ -120,8 +120,12 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
     const int n_pol = c->n_pol, n_chan = c->n_chan;
     const int64_t npix = static_cast<int64_t>(s->nx) * s->ny;
     const int64_t per_sample = static_cast<int64_t>(n_chan) * n_pol * npix * 8;  // bytes
-    // chunk so that the field workspace stays near 1 GiB
-    int chunk = static_cast<int>(std::max<int64_t>(1, (1LL << 30) / per_sample));
+    // chunk so that the field workspace stays near 4 GiB (EPIC_FIELD_BUDGET_MB
+    // overrides): each chunk reads and writes the accumulators once, so longer
+    // chunks save that traffic
+    int64_t budget = 4LL << 30;
+    if (const char *e = std::getenv("EPIC_FIELD_BUDGET_MB")) budget = std::max<int64_t>(1, std::atoll(e)) << 20;
+    int chunk = static_cast<int>(std::max<int64_t>(1, budget / per_sample));
     chunk = std::min(chunk, c->n_time);
     const size_t acc_bytes = static_cast<size_t>(n_chan) * n_pol * n_pol * npix * 8;
     void *ws_field = nullptr, *ws_acc = nullptr;
@@ -144,15 +148,19 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
         if (st != EPIC_OK) return st;
         tv = static_cast<float2 *>(ws_tv);
     }
+    // the split transform's footprint mode reads only each plane's tile
+    // region: the gridding writes nothing else
+    const int region = c->precision != EPIC_FP32_FFT && split_reads_tile_region(s->nx, s->ny);
     for (int t0 = 0; t0 < c->n_time; t0 += chunk) {
         const int nt = std::min(chunk, c->n_time - t0);
         if (pol_kernels)
             st = launch_grid_pol(sd, p.elem_cell, pol_kernels, s->kernel.support, n_pol, n_chan,
                                  c->n_time, c->volt_type, t0, nt, field, stream);
         else if (tv)
-            st = launch_grid_tb(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, tv, field, stream);
+            st = launch_grid_tb(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, tv, field, stream,
+                                region);
         else
-            st = launch_grid(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, field, stream);
+            st = launch_grid(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, field, stream, region);
         if (st != EPIC_OK) return st;
         const int64_t batch = static_cast<int64_t>(n_chan) * nt * n_pol;
         if (c->precision == EPIC_FP32_FFT)

@@ -33,6 +33,16 @@ struct ChanPlan {
     int32_t pad_;
 };
 
+// The cells along one axis (n cells) that the 128 x 128 split-precision
+// transform reads of a plane whose non-zero cells lie in [lo, lo + len): the
+// ceil(len / 16) tiles of 16 cells from lo, moved back where they would pass
+// the plane's edge.
+__host__ __device__ __forceinline__ void tile_span(int lo, int len, int n, int &r0, int &tiles)
+{
+    tiles = (len + 15) >> 4;
+    r0 = lo < n - 16 * tiles ? lo : n - 16 * tiles;
+}
+
 // Device-side view of one station's plan and buffers (kernel argument).
 struct StationDev {
     const ChanPlan *chan;     // [n_chan]
@@ -176,8 +186,11 @@ bool timing_on();
 // Kernel launchers (each .hip file).  All validate nothing: the ABI layer has
 // already checked every argument against what the kernel assumes.
 // ---------------------------------------------------------------------------
+// With region set, only each channel's tile region (tile_span of its
+// footprint box along x and y) is written: the planes are for the split
+// transform's footprint mode, which reads nothing else (split_reads_tile_region).
 epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
-                        int t0, int nt, float2 *grid, hipStream_t stream);
+                        int t0, int nt, float2 *grid, hipStream_t stream, int region = 0);
 
 // Gridding with full polarimetric complex kernels (k_grid.hip): kernels
 // [n_chan][n_elem][n_pol][n_pol][K][K] cf32 applied conjugated at the K x K
@@ -199,7 +212,8 @@ epic_status launch_vis_grid(const float2 *vis, const XfftPlanHandle &pl, int n_p
 // Gridding of large stations through a sample-blocked copy of the voltages:
 // tv is a device buffer of n_chan * ceil(nt / 8) * n_elem * 8 * n_pol float2.
 epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
-                           int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream);
+                           int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream,
+                           int region = 0);
 constexpr int kGridTbMinElem = 1024;   // stations at least this large take that route
 
 // inverse: (1/(nx ny)) sum_k x[k] exp(-2 pi i k.j / N) instead of the + sign transform
@@ -215,6 +229,9 @@ epic_status launch_power(int n_pol, int npix, int n_chan, int nt, const float2 *
 // only the footprint's 16-row/16-column tiles (same result).  max_bw / max_bh
 // bound the boxes' sides over the channels (they size the LDS of the 128 x 128
 // plane kernel).
+// Whether launch_dft2_split with a ChanPlan reads only each plane's tile
+// region (tile_span of the footprint box) for this grid size.
+bool split_reads_tile_region(int nx, int ny);
 epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, const float2 *in,
                               float2 *out, int device, hipStream_t stream,
                               const ChanPlan *chan = nullptr, int items_per_chan = 1,

@@ -467,6 +467,7 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 4 : 1) void k_dft2_tiles128(cons
     extern __shared__ uint32_t lds[];
     __shared__ float red[NW];
     __shared__ int redi[4][NW];
+    __shared__ float2 ph[N];              // the shift-theorem factors
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int g = lane / 16, r = lane % 16;
@@ -474,6 +475,7 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 4 : 1) void k_dft2_tiles128(cons
     const size_t b = blockIdx.x;
     const float2 *src = in + b * N * N;
     float2 *dst = out + b * N * N;
+    if (tid < N) ph[tid] = phase[tid];    // read after the barriers below
 
     auto block_max = [&](float mx) {
         for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
@@ -491,10 +493,8 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 4 : 1) void k_dft2_tiles128(cons
     int x0 = 0, y0 = 0, sx = KS, sy = KS;
     if (chan) {
         const ChanPlan cp = chan[(item0 + static_cast<int64_t>(b)) / items_per_chan];
-        sx = (cp.bw + 15) >> 4;
-        sy = (cp.bh + 15) >> 4;
-        x0 = min(cp.x0, N - 16 * sx);
-        y0 = min(cp.y0, N - 16 * sy);
+        tile_span(cp.x0, cp.bw, N, x0, sx);
+        tile_span(cp.y0, cp.bh, N, y0, sy);
     }
     if (sx * sy > MAX_TILES || (NW == 8 && min(sx, sy) > 4)) return;   // the host dispatches by box size
     // thread: cell (tid % 16, (tid / 16) % 16) of tiles tid / 256, + SLOTS,
@@ -551,10 +551,8 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 4 : 1) void k_dft2_tiles128(cons
             for (int i = tid; i < N * N; i += NT) dst[i] = make_float2(0.f, 0.f);
             return;
         }
-        sx = (hi_x - lo_x + 16) >> 4;
-        sy = (hi_y - lo_y + 16) >> 4;
-        x0 = min(lo_x, N - 16 * sx);
-        y0 = min(lo_y, N - 16 * sy);
+        tile_span(lo_x, hi_x - lo_x + 1, N, x0, sx);
+        tile_span(lo_y, hi_y - lo_y + 1, N, y0, sy);
     }
     const bool x_first = sx > sy;         // the longer side first
     const int ka = x_first ? sx : sy, cb = x_first ? sy : sx;
@@ -632,7 +630,7 @@ __global__ __launch_bounds__(64 * NW, NW == 8 ? 4 : 1) void k_dft2_tiles128(cons
     // the shift back: output (kx, ky) times phase[(kx x0 + ky y0) mod 128]
     const int s1x = x_first ? x0 : y0, s2x = x_first ? y0 : x0;   // shifts along k1, k2
     auto rot = [&](float re, float im, int m) {
-        const float2 w = phase[m & (N - 1)];
+        const float2 w = ph[m & (N - 1)];
         return make_float2((re * w.x - im * w.y) * inv, (re * w.y + im * w.x) * inv);
     };
 #pragma unroll
@@ -809,12 +807,16 @@ epic_status dft2_tiles128(int64_t batch, const float2 *in, float2 *out, const vo
 
 }  // namespace
 
+bool split_reads_tile_region(int nx, int ny) { return nx == 128 && ny == 128; }
+
 epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, const float2 *in,
                               float2 *out, int device, hipStream_t stream, const ChanPlan *chan,
                               int items_per_chan, int max_bw, int max_bh)
 {
     const Prune p1{chan, items_per_chan, 0}, p2{chan, items_per_chan, 1};
-    if (nx == 128 && ny == 128 && (!chan || (max_bw > 0 && max_bh > 0))) {
+    if (split_reads_tile_region(nx, ny)) {
+        if (chan && (max_bw <= 0 || max_bh <= 0))
+            return fail(EPIC_ERR_INTERNAL, "dft2 split: footprint mode without box bounds");
         const void *tab = nullptr;
         epic_status s = get_dft_tables(128, precision, device, &tab);
         if (s != EPIC_OK) return s;

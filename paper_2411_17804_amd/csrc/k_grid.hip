@@ -56,7 +56,7 @@ __device__ __forceinline__ void grid_cell(const StationDev &sd, const ChanPlan &
 
 template <int NP, int VT, int TB>
 __global__ __launch_bounds__(256) void k_grid(StationDev sd, int n_time, int t0, int nt,
-                                              float2 *__restrict__ grid)
+                                              float2 *__restrict__ grid, int region)
 {
     constexpr int CB = kGridCellBlock;
     const int tb = blockIdx.x * TB;
@@ -69,6 +69,25 @@ __global__ __launch_bounds__(256) void k_grid(StationDev sd, int n_time, int t0,
     const int npix = nx * ny;
     const size_t vrow0 = (static_cast<size_t>(c) * n_time + t0 + tb) * sd.n_elem;
     float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
+    if (region) {
+        // the tile region only, one cell per thread
+        int rx0, rtx, ry0, rty;
+        tile_span(cp.x0, cp.bw, nx, rx0, rtx);
+        tile_span(cp.y0, cp.bh, ny, ry0, rty);
+        const int rw = 16 * rtx, r_end = min(rw * 16 * rty, static_cast<int>(blockIdx.z + 1) * CB);
+        for (int i = blockIdx.z * CB + threadIdx.x; i < r_end; i += blockDim.x) {
+            const int x = rx0 + i % rw, y = ry0 + i / rw;
+            float2 a[TB][NP];
+            grid_cell<NP, VT, TB>(sd, cp, cs, taps, x, y, vrow0, nts, a);
+#pragma unroll
+            for (int t = 0; t < TB; ++t)
+                if (t < nts)
+#pragma unroll
+                    for (int p = 0; p < NP; ++p)
+                        out[(static_cast<size_t>(t) * NP + p) * npix + y * nx + x] = a[t][p];
+        }
+        return;
+    }
     const int i_end = min(npix, static_cast<int>(blockIdx.z + 1) * CB);
     for (int i = blockIdx.z * CB + 2 * threadIdx.x; i < i_end; i += 2 * blockDim.x) {
         const int y = i / nx, x = i - y * nx;             // x even: x + 1 is on the same row
@@ -146,7 +165,7 @@ __device__ __forceinline__ void grid_cell_tb(const ChanPlan &cp, const gptr<int3
 template <int NP, int TB>
 __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk,
                                                  const float2 *__restrict__ tv,
-                                                 float2 *__restrict__ grid)
+                                                 float2 *__restrict__ grid, int region)
 {
     constexpr int CB = kGridCellBlock;
     const int blk = blockIdx.x, tb = blk * TB;
@@ -159,11 +178,20 @@ __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk
     const int npix = nx * ny;
     const float2 *src = tv + (static_cast<size_t>(c) * nblk + blk) * sd.n_elem * TB * NP;
     float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
-    const int i_end = min(npix, static_cast<int>(blockIdx.z + 1) * CB);
+    // all cells, or (region set) the tile region only
+    int rx0 = 0, rw = nx, ry0 = 0, n_cells = npix;
+    if (region) {
+        int rtx, rty;
+        tile_span(cp.x0, cp.bw, nx, rx0, rtx);
+        tile_span(cp.y0, cp.bh, ny, ry0, rty);
+        rw = 16 * rtx;
+        n_cells = rw * 16 * rty;
+    }
+    const int i_end = min(n_cells, static_cast<int>(blockIdx.z + 1) * CB);
     // one cell per thread: large stations have many taps per cell, and the
     // wider launch hides their load latency better than paired stores save
     for (int i = blockIdx.z * CB + threadIdx.x; i < i_end; i += blockDim.x) {
-        const int y = i / nx, x = i - y * nx;
+        const int y = ry0 + i / rw, x = rx0 + i % rw;
         float2 acc[TB][NP];
         grid_cell_tb<NP, TB>(cp, cs, taps, src, x, y, acc);
 #pragma unroll
@@ -171,7 +199,7 @@ __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk
             if (t < nts)
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
-                    out[(static_cast<size_t>(t) * NP + p) * npix + i] = acc[t][p];
+                    out[(static_cast<size_t>(t) * NP + p) * npix + y * nx + x] = acc[t][p];
     }
 }
 
@@ -279,7 +307,7 @@ epic_status launch_grid_pol(const StationDev &sd, const int32_t *elem_cell, cons
 }
 
 epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
-                           int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream)
+                           int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream, int region)
 {
     constexpr int TB = kGridTB;
     const int nblk = (nt + TB - 1) / TB;
@@ -300,15 +328,15 @@ epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_ti
     const dim3 blocks(nblk, n_chan, (npix + kGridCellBlock - 1) / kGridCellBlock);
     KernelTimer timer("grid_gather", stream);
     if (n_pol == 1)
-        hipLaunchKernelGGL((k_grid_tb<1, TB>), blocks, threads, 0, stream, sd, nt, nblk, tv, grid);
+        hipLaunchKernelGGL((k_grid_tb<1, TB>), blocks, threads, 0, stream, sd, nt, nblk, tv, grid, region);
     else
-        hipLaunchKernelGGL((k_grid_tb<2, TB>), blocks, threads, 0, stream, sd, nt, nblk, tv, grid);
+        hipLaunchKernelGGL((k_grid_tb<2, TB>), blocks, threads, 0, stream, sd, nt, nblk, tv, grid, region);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }
 
 epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
-                        int t0, int nt, float2 *grid, hipStream_t stream)
+                        int t0, int nt, float2 *grid, hipStream_t stream, int region)
 {
     constexpr int TB = kGridTB;
     const int npix = sd.nx * sd.ny;
@@ -316,13 +344,13 @@ epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time,
         threads(256);
     KernelTimer timer("grid_gather", stream);
     if (n_pol == 1 && volt_type == EPIC_CI8)
-        hipLaunchKernelGGL((k_grid<1, EPIC_CI8, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid);
+        hipLaunchKernelGGL((k_grid<1, EPIC_CI8, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid, region);
     else if (n_pol == 1)
-        hipLaunchKernelGGL((k_grid<1, EPIC_CF32, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid);
+        hipLaunchKernelGGL((k_grid<1, EPIC_CF32, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid, region);
     else if (volt_type == EPIC_CI8)
-        hipLaunchKernelGGL((k_grid<2, EPIC_CI8, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid);
+        hipLaunchKernelGGL((k_grid<2, EPIC_CI8, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid, region);
     else
-        hipLaunchKernelGGL((k_grid<2, EPIC_CF32, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid);
+        hipLaunchKernelGGL((k_grid<2, EPIC_CF32, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid, region);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }

@@ -382,6 +382,32 @@ def test_image_cadence_split(torch, case):
         assert np.array_equal(imgs[s][:, 2], np.conj(imgs[s][:, 1]))
 
 
+@pytest.mark.parametrize("idx,prec", [(3, "fp16"), (5, "bf16")])
+def test_composed_cadence_in_chunks(torch, monkeypatch, idx, prec):
+    # a field budget of 2 MB splits the composed split-precision cadence into
+    # chunks of a few samples: the accumulators carry across chunks, and on
+    # 128 x 128 grids each chunk grids only the transform's tile region while
+    # the rest of the buffer still holds the previous chunk's transform
+    from paper_2411_17804_amd import epic
+    p = W.FP16_SPLIT if prec == "fp16" else W.BF16_SPLIT
+    cfg = W.make_config(idx, chan_subset=[3, 200] if idx == 3 else [9], n_time=11, precision=p)
+    st = cfg.stations[0]
+    per_sample = cfg.n_chan * cfg.n_pol * st.nx * st.ny * 8
+    say(f"image_cadence C{idx} {prec} in chunks of {max(1, (2 << 20) // per_sample)} samples")
+    v = W.station_volts(cfg, 0)
+    monkeypatch.setenv("EPIC_FIELD_BUDGET_MB", "2")
+    epic.cache_clear()
+    common, (station,) = station_objects(cfg, [to_device_volts(v)], p)
+    epic.image_cadence(common, (station,))
+    torch.cuda.synchronize()
+    got = to_complex(station.image)
+    err = oracle.image_error(got, oracle_image(cfg, 0, v), cfg.n_pol)
+    say(f"  worst error {err.max():.2e}")
+    assert err.max() <= SPLIT_TOL[prec], err
+    monkeypatch.delenv("EPIC_FIELD_BUDGET_MB")
+    epic.cache_clear()
+
+
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_footprint_pruned_transform_matches_dense(torch, prec):
     # the cadence's split transform sums only the footprint's tiles; the dense
