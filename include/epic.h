@@ -117,6 +117,8 @@ typedef struct {
  * (cells outside the kernel footprints are written as 0).  The gridded value
  * of a cell is the FP32 sum of weight * voltage over the element taps that
  * land on it, in ascending element order (deterministic; no atomics).
+ * Stations of 1024 elements or more first copy the samples, per element and
+ * block of 8 samples, into a library-owned workspace (same values).
  * station->image is not used.  0 <= t0, nt >= 1, t0 + nt <= common->n_time.
  */
 epic_status grid_voltages(const epic_common *common, const epic_station *station,

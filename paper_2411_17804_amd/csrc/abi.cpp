@@ -351,8 +351,20 @@ epic_status grid_voltages(const epic_common *common, const epic_station *station
     PlanHandle p;
     st = get_plan(common, station, dev, &p);
     if (st != EPIC_OK) return st;
-    return launch_grid(make_station_dev(station, p), common->n_pol, common->n_chan, common->n_time,
-                       common->volt_type, t0, nt, static_cast<float2 *>(grid), stream);
+    const StationDev sd = make_station_dev(station, p);
+    if (station->n_elem >= kGridTbMinElem) {
+        // large stations: the samples are first made contiguous per element
+        // (same taps, same order, same bits)
+        void *ws_tv = nullptr;
+        const size_t tv_bytes = sizeof(float2) * static_cast<size_t>(common->n_chan) * ((nt + 7) / 8) * 8 *
+                                station->n_elem * common->n_pol;
+        st = get_workspace(dev, stream, 2, tv_bytes, &ws_tv);
+        if (st != EPIC_OK) return st;
+        return launch_grid_tb(sd, common->n_pol, common->n_chan, common->n_time, common->volt_type, t0, nt,
+                              static_cast<float2 *>(ws_tv), static_cast<float2 *>(grid), stream);
+    }
+    return launch_grid(sd, common->n_pol, common->n_chan, common->n_time, common->volt_type, t0, nt,
+                       static_cast<float2 *>(grid), stream);
 }
 
 epic_status grid_voltages_pol(const epic_common *common, const epic_station *station,

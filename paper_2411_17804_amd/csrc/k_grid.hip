@@ -148,17 +148,43 @@ __device__ __forceinline__ void grid_cell_tb(const ChanPlan &cp, const gptr<int3
     if (bx < 0 || bx >= cp.bw || by < 0 || by >= cp.bh) return;
     const int cell = by * cp.bw + bx;
     const int k1 = cs[cell + 1];
-    for (int k = cs[cell]; k < k1; ++k) {
-        const Tap tp = gload<Tap>(taps, k);
-        const float2 *e = src + static_cast<size_t>(tp.elem) * TB * NP;
+    // taps two at a time: both taps' voltage loads are in flight together and
+    // the next pair's tap entries load while this pair is summed; the sum
+    // keeps the taps' order (same bits as one tap at a time)
+    int k = cs[cell];
+    Tap ta = k < k1 ? gload<Tap>(taps, k) : Tap{0, 0.f};
+    Tap tb = k + 1 < k1 ? gload<Tap>(taps, k + 1) : Tap{0, 0.f};
+    for (; k < k1; k += 2) {
+        const bool two = k + 1 < k1;
+        const float wa = ta.w, wb = tb.w;
+        const float2 *ea = src + static_cast<size_t>(ta.elem) * TB * NP;
+        const float2 *eb = src + static_cast<size_t>(tb.elem) * TB * NP;   // element 0 if no second tap
+        float2 va[TB * NP], vb[TB * NP];
+#pragma unroll
+        for (int i = 0; i < TB * NP; ++i) {
+            va[i] = gload<float2>(ea, i);
+            vb[i] = gload<float2>(eb, i);
+        }
+        if (k + 2 < k1) ta = gload<Tap>(taps, k + 2);
+        if (k + 3 < k1) tb = gload<Tap>(taps, k + 3);
 #pragma unroll
         for (int t = 0; t < TB; ++t)
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const float2 v = gload<float2>(e, t * NP + p);
-                acc[t][p].x = fmaf(tp.w, v.x, acc[t][p].x);
-                acc[t][p].y = fmaf(tp.w, v.y, acc[t][p].y);
+                const float2 v = va[t * NP + p];
+                acc[t][p].x = fmaf(wa, v.x, acc[t][p].x);
+                acc[t][p].y = fmaf(wa, v.y, acc[t][p].y);
             }
+        if (two) {
+#pragma unroll
+            for (int t = 0; t < TB; ++t)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    const float2 v = vb[t * NP + p];
+                    acc[t][p].x = fmaf(wb, v.x, acc[t][p].x);
+                    acc[t][p].y = fmaf(wb, v.y, acc[t][p].y);
+                }
+        }
     }
 }
 
