@@ -267,7 +267,7 @@ def main():
     dom_avg_ms = dom_ms / dom_count
     launches_per_step = dom_count / args.steps
     st0 = cfg.stations[0]
-    if args.precision == "fp32":
+    if args.precision == "fp32" and dom_name != "grid_gather":
         # the stations the dominant kernel serves (grids up to 64: the fused
         # FFT kernels with their gridding; 128: the 128 x 128 transform kernel,
         # whose gridding runs in k_grid_box)
@@ -286,6 +286,17 @@ def main():
                 if cfg.n_chan == W.make_config(cfg.index).n_chan and args.n_time is None else None,
                 "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": dom_chunk,
                 "flop_per_pixel_sample": round(flop_px, 2)}
+    elif dom_name == "grid_gather" and args.precision == "fp32":
+        # the composed path's gather gridding (full planes): HBM-bound; the
+        # voltages read once and every grid cell written once per sample
+        bv = 2 if cfg.volt_type == W.CI8 else 8
+        bytes_step = sum(cfg.n_chan * cfg.n_time * cfg.n_pol * (s.n_elem * bv + s.nx * s.ny * 8)
+                         for s in cfg.stations)
+        achieved = bytes_step / launches_per_step / (dom_avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": None,
+                "bytes_per_step": int(bytes_step)}
     elif dom_name == "square_accumulate":
         # the composed path's squaring and compensated accumulation: HBM-bound;
         # per launch it reads a chunk of transformed planes and reads and

@@ -138,9 +138,13 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
     EPIC_HIP_TRY(hipMemsetAsync(ws_acc, 0, 2 * acc_bytes, stream));
     const StationDev sd = make_station_dev(s, p);
     float2 *field = static_cast<float2 *>(ws_field);
-    // large stations: sample-blocked voltage copy for the gather (k_grid.hip)
+    // the split transform's footprint mode reads only each plane's tile
+    // region: the gridding writes nothing else
+    const int region = c->precision != EPIC_FP32_FFT && split_reads_tile_region(s->nx, s->ny);
+    // large stations, and every station gridded by region: sample-blocked
+    // voltage copy for the gather (k_grid.hip)
     float2 *tv = nullptr;
-    if (s->n_elem >= kGridTbMinElem && !pol_kernels) {
+    if ((s->n_elem >= kGridTbMinElem || region) && !pol_kernels) {
         void *ws_tv = nullptr;
         const size_t tv_bytes = sizeof(float2) * static_cast<size_t>(n_chan) * ((chunk + 7) / 8) * 8 *
                                 s->n_elem * n_pol;
@@ -148,9 +152,6 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
         if (st != EPIC_OK) return st;
         tv = static_cast<float2 *>(ws_tv);
     }
-    // the split transform's footprint mode reads only each plane's tile
-    // region: the gridding writes nothing else
-    const int region = c->precision != EPIC_FP32_FFT && split_reads_tile_region(s->nx, s->ny);
     for (int t0 = 0; t0 < c->n_time; t0 += chunk) {
         const int nt = std::min(chunk, c->n_time - t0);
         if (pol_kernels)
