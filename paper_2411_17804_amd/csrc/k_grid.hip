@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk
 {
     constexpr int CB = kGridCellBlock;
     const int blk = blockIdx.x, tb = blk * TB;
-    const int c = blockIdx.y;
+    const int c = blockIdx.y, zb = blockIdx.z;
     const int nts = min(TB, nt - tb);
     const ChanPlan cp = sd.chan[c];
     const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
@@ -213,10 +213,10 @@ __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk
         rw = 16 * rtx;
         n_cells = rw * 16 * rty;
     }
-    const int i_end = min(n_cells, static_cast<int>(blockIdx.z + 1) * CB);
+    const int i_end = min(n_cells, (zb + 1) * CB);
     // one cell per thread: large stations have many taps per cell, and the
     // wider launch hides their load latency better than paired stores save
-    for (int i = blockIdx.z * CB + threadIdx.x; i < i_end; i += blockDim.x) {
+    for (int i = zb * CB + threadIdx.x; i < i_end; i += blockDim.x) {
         const int y = ry0 + i / rw, x = rx0 + i % rw;
         float2 acc[TB][NP];
         grid_cell_tb<NP, TB>(cp, cs, taps, src, x, y, acc);
@@ -311,6 +311,20 @@ __global__ __launch_bounds__(256) void k_grid_pol(StationDev sd, const int32_t *
     }
 }
 
+// Cell blocks per (channel, sample block): the whole plane, or the largest
+// tile region over the channels (a box w cells wide spans ceil(w / 16) tiles)
+static int grid_cell_blocks(const StationDev &sd, int region)
+{
+    int cells = sd.nx * sd.ny;
+    if (region) {
+        int r0, tx, ty;
+        tile_span(0, sd.max_bw, sd.nx, r0, tx);
+        tile_span(0, sd.max_bh, sd.ny, r0, ty);
+        cells = 256 * tx * ty;
+    }
+    return (cells + kGridCellBlock - 1) / kGridCellBlock;
+}
+
 epic_status launch_grid_pol(const StationDev &sd, const int32_t *elem_cell, const float2 *kernels,
                             int K, int n_pol, int n_chan, int n_time, int volt_type, int t0, int nt,
                             float2 *grid, hipStream_t stream)
@@ -350,8 +364,7 @@ epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_ti
             hipLaunchKernelGGL((k_volts_tb<2, EPIC_CF32, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
         EPIC_HIP_TRY(hipGetLastError());
     }
-    const int npix = sd.nx * sd.ny;
-    const dim3 blocks(nblk, n_chan, (npix + kGridCellBlock - 1) / kGridCellBlock);
+    const dim3 blocks(nblk, n_chan, grid_cell_blocks(sd, region));
     KernelTimer timer("grid_gather", stream);
     if (n_pol == 1)
         hipLaunchKernelGGL((k_grid_tb<1, TB>), blocks, threads, 0, stream, sd, nt, nblk, tv, grid, region);
@@ -365,9 +378,7 @@ epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time,
                         int t0, int nt, float2 *grid, hipStream_t stream, int region)
 {
     constexpr int TB = kGridTB;
-    const int npix = sd.nx * sd.ny;
-    const dim3 blocks((nt + TB - 1) / TB, n_chan, (npix + kGridCellBlock - 1) / kGridCellBlock),
-        threads(256);
+    const dim3 blocks((nt + TB - 1) / TB, n_chan, grid_cell_blocks(sd, region)), threads(256);
     KernelTimer timer("grid_gather", stream);
     if (n_pol == 1 && volt_type == EPIC_CI8)
         hipLaunchKernelGGL((k_grid<1, EPIC_CI8, TB>), blocks, threads, 0, stream, sd, n_time, t0, nt, grid, region);
