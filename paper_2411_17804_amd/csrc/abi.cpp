@@ -138,13 +138,17 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
     EPIC_HIP_TRY(hipMemsetAsync(ws_acc, 0, 2 * acc_bytes, stream));
     const StationDev sd = make_station_dev(s, p);
     float2 *field = static_cast<float2 *>(ws_field);
-    // the split transform's footprint mode reads only each plane's tile
-    // region: the gridding writes nothing else
-    const int region = c->precision != EPIC_FP32_FFT && split_reads_tile_region(s->nx, s->ny);
+    // the transform's footprint mode reads only each plane's tile region
+    // (split precision, 128 x 128) or the box's rows (FP32, two-pass grids):
+    // the gridding writes nothing else
+    const bool f32 = c->precision == EPIC_FP32_FFT;
+    const int region = pol_kernels ? 0
+                       : !f32 && split_reads_tile_region(s->nx, s->ny) ? 1
+                       : f32 && fft_f32_two_pass(s->nx, s->ny) ? 2 : 0;
     // large stations, and every station gridded by region: sample-blocked
     // voltage copy for the gather (k_grid.hip)
     float2 *tv = nullptr;
-    if ((s->n_elem >= kGridTbMinElem || region) && !pol_kernels) {
+    if ((s->n_elem >= kGridTbMinElem || region == 1) && !pol_kernels) {
         void *ws_tv = nullptr;
         const size_t tv_bytes = sizeof(float2) * static_cast<size_t>(n_chan) * ((chunk + 7) / 8) * 8 *
                                 s->n_elem * n_pol;
@@ -164,8 +168,9 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
             st = launch_grid(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, field, stream, region);
         if (st != EPIC_OK) return st;
         const int64_t batch = static_cast<int64_t>(n_chan) * nt * n_pol;
-        if (c->precision == EPIC_FP32_FFT)
-            st = launch_fft2_f32(s->nx, s->ny, batch, field, field, device, stream);
+        if (f32)
+            st = launch_fft2_f32(s->nx, s->ny, batch, field, field, device, stream, false,
+                                 region == 2 ? sd.chan : nullptr, nt * n_pol);
         else
             // the planes are zero outside each channel's footprint box: the
             // transform sums over the box's tiles only

@@ -186,9 +186,11 @@ bool timing_on();
 // Kernel launchers (each .hip file).  All validate nothing: the ABI layer has
 // already checked every argument against what the kernel assumes.
 // ---------------------------------------------------------------------------
-// With region set, only each channel's tile region (tile_span of its
-// footprint box along x and y) is written: the planes are for the split
-// transform's footprint mode, which reads nothing else (split_reads_tile_region).
+// With region 1, only each channel's tile region (tile_span of its footprint
+// box along x and y) is written: the planes are for the split transform's
+// footprint mode, which reads nothing else (split_reads_tile_region).  With
+// region 2, only the box's rows (all columns) are written, for the two-pass
+// FP32 transform's footprint mode.
 epic_status launch_grid(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
                         int t0, int nt, float2 *grid, hipStream_t stream, int region = 0);
 
@@ -216,9 +218,15 @@ epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_ti
                            int region = 0);
 constexpr int kGridTbMinElem = 1024;   // stations at least this large take that route
 
-// inverse: (1/(nx ny)) sum_k x[k] exp(-2 pi i k.j / N) instead of the + sign transform
+// inverse: (1/(nx ny)) sum_k x[k] exp(-2 pi i k.j / N) instead of the + sign
+// transform.  With chan set (two-pass grids only, fft_f32_two_pass), batch
+// item b is a plane of channel b / items_per_chan whose rows outside that
+// channel's footprint box are zero and are never read (nor written by the
+// row pass); the output is complete.
+bool fft_f32_two_pass(int nx, int ny);
 epic_status launch_fft2_f32(int nx, int ny, int64_t batch, const float2 *in, float2 *out,
-                            int device, hipStream_t stream, bool inverse = false);
+                            int device, hipStream_t stream, bool inverse = false,
+                            const ChanPlan *chan = nullptr, int items_per_chan = 1);
 
 epic_status launch_power(int n_pol, int npix, int n_chan, int nt, const float2 *field,
                          float2 *acc_sum, float2 *acc_comp, int finalize_n_time, float2 *image,

@@ -57,9 +57,15 @@ __global__ __launch_bounds__(BLOCK) void k_fft2_lds(const float2 *__restrict__ i
 
 // Row pass for large grids: ROWS consecutive rows of length NX per block.
 template <int NX, int ROWS, int BLOCK, bool INV>
+//
+// With chan set (the composed cadence), the rows of plane b outside channel
+// (b / items_per_chan)'s footprint box are zero: they are neither read nor
+// written (the column pass takes them as zero).
 __global__ __launch_bounds__(BLOCK) void k_fft_rows(const float2 *__restrict__ in,
                                                     float2 *__restrict__ out,
-                                                    const float2 *__restrict__ tw, int64_t n_rows)
+                                                    const float2 *__restrict__ tw, int64_t n_rows,
+                                                    const ChanPlan *__restrict__ chan,
+                                                    int items_per_chan, int ny)
 {
     constexpr int P = NX + 1;
     extern __shared__ float2 lds[];
@@ -67,6 +73,14 @@ __global__ __launch_bounds__(BLOCK) void k_fft_rows(const float2 *__restrict__ i
     float2 *t = lds + ROWS * P;
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * ROWS;
     const int nr = static_cast<int>(min<int64_t>(ROWS, n_rows - row0));
+    int ylo = 0, yhi = ROWS;                      // block rows inside the box
+    if (chan) {
+        const ChanPlan cp = chan[(row0 / ny) / items_per_chan];
+        const int yb = static_cast<int>(row0 % ny);
+        ylo = max(0, cp.y0 - yb);
+        yhi = min(ROWS, cp.y0 + cp.bh - yb);
+        if (ylo >= yhi) return;
+    }
     for (int i = threadIdx.x; i < NX; i += BLOCK) t[i] = tw[i];
     // every load of the rows in flight before the LDS writes
     constexpr int PER = (ROWS * NX + BLOCK - 1) / BLOCK;
@@ -74,7 +88,8 @@ __global__ __launch_bounds__(BLOCK) void k_fft_rows(const float2 *__restrict__ i
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
         const int i = threadIdx.x + r * BLOCK;
-        v[r] = i < nr * NX ? in[row0 * NX + i] : make_float2(0.f, 0.f);
+        const int y = i / NX;
+        v[r] = i < nr * NX && y >= ylo && y < yhi ? in[row0 * NX + i] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
@@ -83,13 +98,20 @@ __global__ __launch_bounds__(BLOCK) void k_fft_rows(const float2 *__restrict__ i
     }
     __syncthreads();
     fft_lines<NX, BLOCK, ROWS, false>(buf, LineMap{ROWS, 0, 0, P, 1}, nr, t);
-    for (int i = threadIdx.x; i < nr * NX; i += BLOCK) out[row0 * NX + i] = buf[(i / NX) * P + (i % NX)];
+    for (int i = threadIdx.x; i < nr * NX; i += BLOCK) {
+        const int y = i / NX;
+        if (y >= ylo && y < yhi) out[row0 * NX + i] = buf[y * P + (i % NX)];
+    }
 }
 
 // Column pass for large grids: COLS adjacent columns (length NY) per block.
+// With chan set, the rows outside the channel's footprint box are taken as
+// zero (not read); every row is written.
 template <int NX, int NY, int COLS, int BLOCK, bool INV>
 __global__ __launch_bounds__(BLOCK) void k_fft_cols(float2 *__restrict__ data,
-                                                    const float2 *__restrict__ tw)
+                                                    const float2 *__restrict__ tw,
+                                                    const ChanPlan *__restrict__ chan,
+                                                    int items_per_chan)
 {
     constexpr int P = COLS + 1;   // LDS holds the tile transposed-free: [y][col]
     extern __shared__ float2 lds[];
@@ -99,6 +121,12 @@ __global__ __launch_bounds__(BLOCK) void k_fft_cols(float2 *__restrict__ data,
     const int64_t item = blockIdx.x / TILES;
     const int c0 = (blockIdx.x % TILES) * COLS;
     float2 *base = data + item * (NX * NY) + c0;
+    int ylo = 0, yhi = NY;
+    if (chan) {
+        const ChanPlan cp = chan[item / items_per_chan];
+        ylo = cp.y0;
+        yhi = cp.y0 + cp.bh;
+    }
     for (int i = threadIdx.x; i < NY; i += BLOCK) t[i] = tw[i];
     // every load of the tile in flight before the LDS writes
     constexpr int PER = NY * COLS / BLOCK;
@@ -107,7 +135,8 @@ __global__ __launch_bounds__(BLOCK) void k_fft_cols(float2 *__restrict__ data,
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
         const int i = threadIdx.x + r * BLOCK;
-        v[r] = base[(i / COLS) * NX + (i % COLS)];
+        const int y = i / COLS;
+        v[r] = y >= ylo && y < yhi ? base[y * NX + (i % COLS)] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
@@ -124,6 +153,11 @@ __global__ __launch_bounds__(BLOCK) void k_fft_cols(float2 *__restrict__ data,
 }
 
 namespace {
+
+struct RowBox {               // footprint rows of the composed cadence (chan null: none)
+    const ChanPlan *chan;
+    int items_per_chan;
+};
 
 template <typename K>
 epic_status set_lds(K kernel, size_t bytes)
@@ -157,7 +191,7 @@ epic_status run_lds(int64_t batch, const float2 *in, float2 *out, const float2 *
 
 template <int NX, bool INV>
 epic_status run_rows(int64_t n_rows, const float2 *in, float2 *out, const float2 *tw,
-                     hipStream_t stream)
+                     hipStream_t stream, const RowBox &rb, int ny)
 {
     constexpr int ROWS = 16, BLOCK = 256;
     const size_t bytes = sizeof(float2) * (ROWS * (NX + 1) + NX);
@@ -167,13 +201,14 @@ epic_status run_rows(int64_t n_rows, const float2 *in, float2 *out, const float2
     const int64_t blocks = (n_rows + ROWS - 1) / ROWS;
     KernelTimer timer("fft_rows", stream);
     hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(blocks)), dim3(BLOCK), bytes, stream, in, out,
-                       tw, n_rows);
+                       tw, n_rows, rb.chan, rb.items_per_chan, ny);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }
 
 template <int NX, int NY, bool INV>
-epic_status run_cols(int64_t batch, float2 *data, const float2 *tw, hipStream_t stream)
+epic_status run_cols(int64_t batch, float2 *data, const float2 *tw, hipStream_t stream,
+                     const RowBox &rb)
 {
     constexpr int COLS = 16, BLOCK = 256;
     const size_t bytes = sizeof(float2) * (NY * (COLS + 1) + NY);
@@ -182,14 +217,15 @@ epic_status run_cols(int64_t batch, float2 *data, const float2 *tw, hipStream_t 
     if (s != EPIC_OK) return s;
     const int64_t blocks = batch * (NX / COLS);
     KernelTimer timer("fft_cols", stream);
-    hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(blocks)), dim3(BLOCK), bytes, stream, data, tw);
+    hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(blocks)), dim3(BLOCK), bytes, stream, data, tw,
+                       rb.chan, rb.items_per_chan);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }
 
 template <int NX, bool INV>
 epic_status dispatch_ny(int ny, int64_t batch, const float2 *in, float2 *out, const float2 *twx,
-                        const float2 *twy, hipStream_t stream)
+                        const float2 *twy, hipStream_t stream, const RowBox &rb)
 {
     if constexpr (NX <= 128) {
         switch (ny) {
@@ -208,23 +244,29 @@ epic_status dispatch_ny(int ny, int64_t batch, const float2 *in, float2 *out, co
         if (ny == 64) return run_lds<NX, 64, INV>(batch, in, out, twx, twy, stream);
     }
     // two passes through global memory
-    epic_status s = run_rows<NX, INV>(batch * ny, in, out, twx, stream);
+    epic_status s = run_rows<NX, INV>(batch * ny, in, out, twx, stream, rb, ny);
     if (s != EPIC_OK) return s;
     switch (ny) {
-    case 16: return run_cols<NX, 16, INV>(batch, out, twy, stream);
-    case 32: return run_cols<NX, 32, INV>(batch, out, twy, stream);
-    case 64: return run_cols<NX, 64, INV>(batch, out, twy, stream);
-    case 128: return run_cols<NX, 128, INV>(batch, out, twy, stream);
-    case 256: return run_cols<NX, 256, INV>(batch, out, twy, stream);
+    case 16: return run_cols<NX, 16, INV>(batch, out, twy, stream, rb);
+    case 32: return run_cols<NX, 32, INV>(batch, out, twy, stream, rb);
+    case 64: return run_cols<NX, 64, INV>(batch, out, twy, stream, rb);
+    case 128: return run_cols<NX, 128, INV>(batch, out, twy, stream, rb);
+    case 256: return run_cols<NX, 256, INV>(batch, out, twy, stream, rb);
     }
     return fail(EPIC_ERR_INTERNAL, "fft2: unexpected ny");
 }
 
 }  // namespace
 
+bool fft_f32_two_pass(int nx, int ny) { return ny == 256 || (ny == 128 && nx >= 128); }
+
 epic_status launch_fft2_f32(int nx, int ny, int64_t batch, const float2 *in, float2 *out,
-                            int device, hipStream_t stream, bool inverse)
+                            int device, hipStream_t stream, bool inverse, const ChanPlan *chan,
+                            int items_per_chan)
 {
+    if (chan && !fft_f32_two_pass(nx, ny))
+        return fail(EPIC_ERR_INTERNAL, "fft2: footprint rows on a one-pass grid");
+    const RowBox rb{chan, items_per_chan};
     const float2 *twx = nullptr, *twy = nullptr;
     epic_status s = get_twiddles(nx, device, &twx);
     if (s != EPIC_OK) return s;
@@ -233,11 +275,11 @@ epic_status launch_fft2_f32(int nx, int ny, int64_t batch, const float2 *in, flo
     auto go = [&](auto inv) -> epic_status {
         constexpr bool INV = decltype(inv)::value;
         switch (nx) {
-        case 16: return dispatch_ny<16, INV>(ny, batch, in, out, twx, twy, stream);
-        case 32: return dispatch_ny<32, INV>(ny, batch, in, out, twx, twy, stream);
-        case 64: return dispatch_ny<64, INV>(ny, batch, in, out, twx, twy, stream);
-        case 128: return dispatch_ny<128, INV>(ny, batch, in, out, twx, twy, stream);
-        case 256: return dispatch_ny<256, INV>(ny, batch, in, out, twx, twy, stream);
+        case 16: return dispatch_ny<16, INV>(ny, batch, in, out, twx, twy, stream, rb);
+        case 32: return dispatch_ny<32, INV>(ny, batch, in, out, twx, twy, stream, rb);
+        case 64: return dispatch_ny<64, INV>(ny, batch, in, out, twx, twy, stream, rb);
+        case 128: return dispatch_ny<128, INV>(ny, batch, in, out, twx, twy, stream, rb);
+        case 256: return dispatch_ny<256, INV>(ny, batch, in, out, twx, twy, stream, rb);
         }
         return fail(EPIC_ERR_INTERNAL, "fft2: unexpected nx");
     };

@@ -70,11 +70,16 @@ __global__ __launch_bounds__(256) void k_grid(StationDev sd, int n_time, int t0,
     const size_t vrow0 = (static_cast<size_t>(c) * n_time + t0 + tb) * sd.n_elem;
     float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
     if (region) {
-        // the tile region only, one cell per thread
-        int rx0, rtx, ry0, rty;
-        tile_span(cp.x0, cp.bw, nx, rx0, rtx);
-        tile_span(cp.y0, cp.bh, ny, ry0, rty);
-        const int rw = 16 * rtx, r_end = min(rw * 16 * rty, static_cast<int>(blockIdx.z + 1) * CB);
+        // the tile region (region 1) or the box's rows (region 2), one cell
+        // per thread
+        int rx0 = 0, rtx = nx / 16, ry0 = cp.y0, rh = cp.bh;
+        if (region == 1) {
+            int rty;
+            tile_span(cp.x0, cp.bw, nx, rx0, rtx);
+            tile_span(cp.y0, cp.bh, ny, ry0, rty);
+            rh = 16 * rty;
+        }
+        const int rw = 16 * rtx, r_end = min(rw * rh, static_cast<int>(blockIdx.z + 1) * CB);
         for (int i = blockIdx.z * CB + threadIdx.x; i < r_end; i += blockDim.x) {
             const int x = rx0 + i % rw, y = ry0 + i / rw;
             float2 a[TB][NP];
@@ -204,14 +209,17 @@ __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk
     const int npix = nx * ny;
     const float2 *src = tv + (static_cast<size_t>(c) * nblk + blk) * sd.n_elem * TB * NP;
     float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix;
-    // all cells, or (region set) the tile region only
+    // all cells, or the tile region (region 1), or the box's rows (region 2)
     int rx0 = 0, rw = nx, ry0 = 0, n_cells = npix;
-    if (region) {
+    if (region == 1) {
         int rtx, rty;
         tile_span(cp.x0, cp.bw, nx, rx0, rtx);
         tile_span(cp.y0, cp.bh, ny, ry0, rty);
         rw = 16 * rtx;
         n_cells = rw * 16 * rty;
+    } else if (region == 2) {
+        ry0 = cp.y0;
+        n_cells = nx * cp.bh;
     }
     const int i_end = min(n_cells, (zb + 1) * CB);
     // one cell per thread: large stations have many taps per cell, and the
@@ -316,11 +324,13 @@ __global__ __launch_bounds__(256) void k_grid_pol(StationDev sd, const int32_t *
 static int grid_cell_blocks(const StationDev &sd, int region)
 {
     int cells = sd.nx * sd.ny;
-    if (region) {
+    if (region == 1) {
         int r0, tx, ty;
         tile_span(0, sd.max_bw, sd.nx, r0, tx);
         tile_span(0, sd.max_bh, sd.ny, r0, ty);
         cells = 256 * tx * ty;
+    } else if (region == 2) {
+        cells = sd.nx * sd.max_bh;
     }
     return (cells + kGridCellBlock - 1) / kGridCellBlock;
 }
