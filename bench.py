@@ -287,11 +287,20 @@ def main():
                 "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": dom_chunk,
                 "flop_per_pixel_sample": round(flop_px, 2)}
     elif dom_name == "grid_gather" and args.precision == "fp32":
-        # the composed path's gather gridding (full planes): HBM-bound; the
-        # voltages read once and every grid cell written once per sample
+        # the composed path's gather gridding: HBM-bound; the voltages read
+        # once and every written cell once per sample (on the two-pass grids,
+        # 256 wide or 128 x 128, only the footprint box's rows are written)
         bv = 2 if cfg.volt_type == W.CI8 else 8
-        bytes_step = sum(cfg.n_chan * cfg.n_time * cfg.n_pol * (s.n_elem * bv + s.nx * s.ny * 8)
-                         for s in cfg.stations)
+        bytes_step = 0
+        for s in cfg.stations:
+            two_pass = s.ny == 256 or (s.ny == 128 and s.nx >= 128)
+            h = (s.support - 1) // 2
+            for lam in cfg.wavelengths_m:
+                rows = s.ny
+                if two_pass:
+                    cj = np.floor(s.pos_m[:, 1] / (W.GRID_SPACING_WL * lam) + s.ny // 2 + 0.5)
+                    rows = int(cj.max() - cj.min()) + 2 * h + 1
+                bytes_step += cfg.n_time * cfg.n_pol * (s.n_elem * bv + s.nx * rows * 8)
         achieved = bytes_step / launches_per_step / (dom_avg_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,

@@ -194,13 +194,32 @@ __device__ __forceinline__ void grid_cell_tb(const ChanPlan &cp, const gptr<int3
 }
 
 template <int NP, int TB>
-__global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk,
+//
+// Work items (channel, sample block, cell block of CB cells) on a 1-D grid.
+// By default the sample blocks run fastest (blk, channel, cell block).  With
+// zfirst set (stations whose sample block of voltages is large next to an
+// XCD's L2) the cell blocks run fastest and each XCD takes a contiguous range
+// of items (work-group ids go to the 8 XCDs round-robin), so the work-groups
+// that gather from one sample block run together on one XCD.
+__global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk, int n_chan, int nz,
+                                                 int CB, int zfirst,
                                                  const float2 *__restrict__ tv,
                                                  float2 *__restrict__ grid, int region)
 {
-    constexpr int CB = kGridCellBlock;
-    const int blk = blockIdx.x, tb = blk * TB;
-    const int c = blockIdx.y, zb = blockIdx.z;
+    const int64_t total = static_cast<int64_t>(nblk) * n_chan * nz;
+    const int64_t id = blockIdx.x;
+    int blk, c, zb;
+    if (zfirst) {
+        const int64_t item = total % 8 == 0 ? (id % 8) * (total / 8) + id / 8 : id;
+        zb = static_cast<int>(item % nz);
+        blk = static_cast<int>((item / nz) % nblk);
+        c = static_cast<int>(item / nz / nblk);
+    } else {
+        blk = static_cast<int>(id % nblk);
+        c = static_cast<int>((id / nblk) % n_chan);
+        zb = static_cast<int>(id / nblk / n_chan);
+    }
+    const int tb = blk * TB;
     const int nts = min(TB, nt - tb);
     const ChanPlan cp = sd.chan[c];
     const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
@@ -319,9 +338,10 @@ __global__ __launch_bounds__(256) void k_grid_pol(StationDev sd, const int32_t *
     }
 }
 
-// Cell blocks per (channel, sample block): the whole plane, or the largest
-// tile region over the channels (a box w cells wide spans ceil(w / 16) tiles)
-static int grid_cell_blocks(const StationDev &sd, int region)
+// Cell blocks of cb cells per (channel, sample block): the whole plane, or the
+// largest tile region over the channels (a box w cells wide spans
+// ceil(w / 16) tiles), or the largest box's rows
+static int grid_cell_blocks(const StationDev &sd, int region, int cb = kGridCellBlock)
 {
     int cells = sd.nx * sd.ny;
     if (region == 1) {
@@ -332,7 +352,7 @@ static int grid_cell_blocks(const StationDev &sd, int region)
     } else if (region == 2) {
         cells = sd.nx * sd.max_bh;
     }
-    return (cells + kGridCellBlock - 1) / kGridCellBlock;
+    return (cells + cb - 1) / cb;
 }
 
 epic_status launch_grid_pol(const StationDev &sd, const int32_t *elem_cell, const float2 *kernels,
@@ -374,12 +394,21 @@ epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_ti
             hipLaunchKernelGGL((k_volts_tb<2, EPIC_CF32, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
         EPIC_HIP_TRY(hipGetLastError());
     }
-    const dim3 blocks(nblk, n_chan, grid_cell_blocks(sd, region));
+    // a sample block of voltages of 1 MB or more (a quarter of an XCD's L2):
+    // one-row cell blocks, run block after block of one sample block per XCD
+    const bool zfirst = static_cast<size_t>(sd.n_elem) * TB * n_pol * sizeof(float2) >= (size_t{1} << 20);
+    const int cb = zfirst ? 256 : kGridCellBlock;
+    const int nz = grid_cell_blocks(sd, region, cb);
+    const int64_t n_wg = static_cast<int64_t>(nblk) * n_chan * nz;
+    if (n_wg > 0x7fffffff) return fail(EPIC_ERR_UNSUPPORTED, "gridding launch too large");
+    const dim3 blocks(static_cast<unsigned>(n_wg));
     KernelTimer timer("grid_gather", stream);
     if (n_pol == 1)
-        hipLaunchKernelGGL((k_grid_tb<1, TB>), blocks, threads, 0, stream, sd, nt, nblk, tv, grid, region);
+        hipLaunchKernelGGL((k_grid_tb<1, TB>), blocks, threads, 0, stream, sd, nt, nblk, n_chan, nz, cb,
+                           zfirst ? 1 : 0, tv, grid, region);
     else
-        hipLaunchKernelGGL((k_grid_tb<2, TB>), blocks, threads, 0, stream, sd, nt, nblk, tv, grid, region);
+        hipLaunchKernelGGL((k_grid_tb<2, TB>), blocks, threads, 0, stream, sd, nt, nblk, n_chan, nz, cb,
+                           zfirst ? 1 : 0, tv, grid, region);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }
