@@ -72,7 +72,25 @@ __global__ __launch_bounds__(256) void k_power(int npix, int n_chan, int nt,
         }
     }
     const float2 *f = field + static_cast<size_t>(c) * nt * NP * npix + k;
-    for (int t = 0; t < nt; ++t) {
+    // U samples' loads in flight at once, then summed in sample order (the
+    // same additions in the same order as one sample at a time)
+    constexpr int U = 4;
+    int t = 0;
+    for (; t + U <= nt; t += U) {
+        float2 v[U][NP];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) v[u][p] = f[(static_cast<size_t>(t + u) * NP + p) * npix];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float q[NQ];
+            products<NP>(v[u], q);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) two_sum_acc(s[i], cc[i], q[i]);
+        }
+    }
+    for (; t < nt; ++t) {
         float2 v[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) v[p] = f[(static_cast<size_t>(t) * NP + p) * npix];
