@@ -380,8 +380,9 @@ __global__ __launch_bounds__(256) void k_dft2_plane(const float2 *__restrict__ i
 
 // acc[w][t] = sum over K tiles 0 .. nks - 1 of the 128-point DFT table's
 // M-tile mt0 + mt_step w times the LDS operand's column tile col0 + t
-// (t < ncols <= TMAX; operand pitch jp words per column), both split parts.  The table fragments are double-buffered:
-// step s + 1's loads are in flight while step s's products run.
+// (t < ncols <= TMAX; operand pitch jp words per column), both split parts.
+// The table fragments are double-buffered: step s + 1's loads are in flight
+// while step s's products run.
 template <int PREC, int MTW, int TMAX>
 __device__ __forceinline__ void tile_products128(floatx4_t (&acc)[MTW][TMAX],
                                                  const typename Split<PREC>::vec8 *__restrict__ tab,
@@ -430,8 +431,8 @@ __device__ __forceinline__ void tile_products128(floatx4_t (&acc)[MTW][TMAX],
 // box of its non-zero cells only.  The box comes from the channel's footprint
 // (chan set: only the box is read) or, for a dense call, from the plane itself
 // (every cell is read).  The sums run over 16-cell tiles counted from the
-// box's first cell (x0, y0), moved left or down where the tiles would pass
-// the plane's edge, so a box w cells wide takes ceil(w / 16) tiles; by the
+// box's first cell (x0, y0), moved back where the tiles would pass the
+// plane's edge, so a box w cells wide takes ceil(w / 16) tiles; by the
 // shift theorem the transform of the shifted operand times
 // exp(+2 pi i (kx x0 + ky y0) / 128) is the transform of the plane (the
 // factors from an FP64 table).  The longer side (ka tiles) is transformed
@@ -450,12 +451,11 @@ __device__ __forceinline__ void tile_products128(floatx4_t (&acc)[MTW][TMAX],
 // tiles in the first pass, and the two column halves in two rounds in the
 // second, each stored as it ends.
 template <int PREC, int NW>
-__global__ __launch_bounds__(64 * NW, NW == 8 ? 4 : 1) void k_dft2_tiles128(const float2 *__restrict__ in,
-                                                           float2 *__restrict__ out,
-                                                           const typename Split<PREC>::vec8 *__restrict__ tab,
-                                                           const float2 *__restrict__ phase,
-                                                           const ChanPlan *__restrict__ chan, int64_t item0,
-                                                           int items_per_chan, int lds_words)
+__global__ __launch_bounds__(64 * NW, NW == 8 ? 4 : 1)
+void k_dft2_tiles128(const float2 *__restrict__ in, float2 *__restrict__ out,
+                     const typename Split<PREC>::vec8 *__restrict__ tab,
+                     const float2 *__restrict__ phase, const ChanPlan *__restrict__ chan,
+                     int64_t item0, int items_per_chan, int lds_words)
 {
     static_assert(NW == 16 || NW == 8, "16 or 8 waves");
     using S = Split<PREC>;
