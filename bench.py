@@ -176,9 +176,9 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the path shards by channel "
-                          "with no exchange, and only the single-GPU figure is measured",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only: the path would shard "
+                          "by channel with no exchange between GPUs, and only the single-GPU "
+                          "throughput is measured", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
