@@ -382,6 +382,29 @@ def test_image_cadence_split(torch, case):
         assert np.array_equal(imgs[s][:, 2], np.conj(imgs[s][:, 1]))
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_image_cadence_split_wide_box(torch, prec):
+    # C3's lattice stretched to twice its extent along y: the footprint box
+    # (about 68 x 70 cells) is more than 4 tiles on both sides, so the 128 x 128
+    # split transform runs its 16-wave form on the footprint's tiles
+    p = W.FP16_SPLIT if prec == "fp16" else W.BF16_SPLIT
+    cfg = W.make_config(3, chan_subset=[0, 255], n_time=6, precision=p)
+    st = cfg.stations[0]
+    st.pos_m = st.pos_m * np.array([1.0, 2.0])
+    bw = bh = 0                                  # the largest box over the channels
+    for lam in cfg.wavelengths_m:
+        cj = np.floor(st.pos_m[:, 1] / (W.GRID_SPACING_WL * lam) + st.ny // 2 + 0.5)
+        ci = np.floor(st.pos_m[:, 0] / (W.GRID_SPACING_WL * lam) + st.nx // 2 + 0.5)
+        bw = max(bw, int(np.ptp(ci)) + st.support)
+        bh = max(bh, int(np.ptp(cj)) + st.support)
+    assert min(-(-bw // 16), -(-bh // 16)) > 4 and max(bw, bh) < st.nx, (bw, bh)
+    say(f"image_cadence C3 {prec}, largest footprint {bw} x {bh} cells")
+    volts, imgs, _ = run_cadence(cfg)
+    err = oracle.image_error(imgs[0], oracle_image(cfg, 0, volts[0]), cfg.n_pol)
+    say(f"  worst error {err.max():.2e}")
+    assert err.max() <= SPLIT_TOL[prec], err
+
+
 @pytest.mark.parametrize("idx,prec", [(3, "fp16"), (5, "bf16"), (5, "fp32")])
 def test_composed_cadence_in_chunks(torch, monkeypatch, idx, prec):
     # a field budget of 2 MB splits the composed cadence into chunks of a few
