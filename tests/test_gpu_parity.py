@@ -405,6 +405,30 @@ def test_image_cadence_split_wide_box(torch, prec):
     assert err.max() <= SPLIT_TOL[prec], err
 
 
+def test_fp32_footprint_rows_small_station(torch, monkeypatch):
+    # every 20th element of the C5 lattice (under 1024 elements: the per-row
+    # gather) on the 256 x 256 grid, in chunks of 2 samples: only the
+    # footprint box's rows are gridded and transformed, and the rows outside
+    # it hold the previous chunk's output, which nothing may read
+    from paper_2411_17804_amd import epic
+    cfg = W.make_config(5, chan_subset=[64], n_time=5, precision=W.FP32_FFT)
+    st = cfg.stations[0]
+    st.pos_m = st.pos_m[::20]
+    assert st.n_elem < 1024
+    say(f"image_cadence fp32 256x256, {st.n_elem} elements, chunks of 2 samples")
+    v = W.station_volts(cfg, 0)
+    monkeypatch.setenv("EPIC_FIELD_BUDGET_MB", "2")
+    epic.cache_clear()
+    common, (station,) = station_objects(cfg, [to_device_volts(v)])
+    epic.image_cadence(common, (station,))
+    torch.cuda.synchronize()
+    err = oracle.image_error(to_complex(station.image), oracle_image(cfg, 0, v), cfg.n_pol)
+    say(f"  worst error {err.max():.2e}")
+    assert err.max() <= FP32_TOL, err
+    monkeypatch.delenv("EPIC_FIELD_BUDGET_MB")
+    epic.cache_clear()
+
+
 @pytest.mark.parametrize("idx,prec", [(3, "fp16"), (5, "bf16"), (5, "fp32")])
 def test_composed_cadence_in_chunks(torch, monkeypatch, idx, prec):
     # a field budget of 2 MB splits the composed cadence into chunks of a few
