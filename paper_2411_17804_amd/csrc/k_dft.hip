@@ -477,9 +477,10 @@ void k_dft2_tiles128(const float2 *__restrict__ in, float2 *__restrict__ out,
     float2 *dst = out + b * N * N;
     if (tid < N) ph[tid] = phase[tid];    // read after the barriers below
 
+    // block-wide max; each use is separated from the previous one's reads of
+    // red[] by a barrier of the caller's (the one before the first pass)
     auto block_max = [&](float mx) {
         for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-        __syncthreads();                  // red[] of an earlier use has been read
         if (lane == 0) red[wave] = mx;
         __syncthreads();
         float m = red[0];
@@ -609,10 +610,12 @@ void k_dft2_tiles128(const float2 *__restrict__ in, float2 *__restrict__ out,
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) mx = fmaxf(mx, fabsf(acc1[w][t][e]));
+        // its barrier also comes after every pass-1 operand read
         const float m = block_max(mx) / s1;           // largest |P| component
         s2 = pow2_scale(m) / s1;                      // exact: powers of two
+    } else {
+        __syncthreads();                              // every pass-1 operand read
     }
-    __syncthreads();                                  // every pass-1 operand read
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
         const int k1 = (pair + 8 * w) * 8 + 2 * g;
