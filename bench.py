@@ -143,6 +143,33 @@ def tiles128_mfma_flops(cfg):
     return total
 
 
+def pass_mfma_flops(cfg):
+    """Matrix-core flops of the two-pass split-precision transform for one
+    cadence (square grids of 256): per sample, pol and channel, the first pass
+    (along y) runs 2N/16 M-tiles x 2 column tiles x (the footprint's 16-row
+    tiles) for each 32-column block that meets the footprint, the second
+    (along x) the same M-tiles x 2 column tiles x (the footprint's 16-column
+    tiles) for all N/32 blocks; three split products of 16x16x32 each.  Tiles
+    are aligned to the grid, as the passes read them."""
+    total = 0
+    for st in cfg.stations:
+        if st.nx != 256 or st.ny != 256:
+            continue
+        n, h = st.nx, (st.support - 1) // 2
+        for lam in cfg.wavelengths_m:
+            d = W.GRID_SPACING_WL * lam
+            ci = np.floor(st.pos_m[:, 0] / d + n // 2 + 0.5)
+            cj = np.floor(st.pos_m[:, 1] / d + n // 2 + 0.5)
+            x0, x1 = int(ci.min()) - h, int(ci.max()) + h
+            y0, y1 = int(cj.min()) - h, int(cj.max()) + h
+            ks_y, ks_x = (y1 >> 4) - (y0 >> 4) + 1, (x1 >> 4) - (x0 >> 4) + 1
+            nblk_x = (x1 >> 5) - (x0 >> 5) + 1
+            mt = 2 * n // 16
+            mfma = 3 * mt * 2 * (ks_y * nblk_x + ks_x * (n // 32))
+            total += mfma * 16 * 16 * 32 * 2 * cfg.n_time * cfg.n_pol
+    return total
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,7 +348,8 @@ def main():
                 "bytes_per_step": int(bytes_step)}
     else:
         fl = {"fused_dft_cadence": split_mfma_flops,
-              "dft2_tiles128": tiles128_mfma_flops}.get(dom_name, lambda c: None)(cfg)
+              "dft2_tiles128": tiles128_mfma_flops,
+              "dft_gemm_pass": pass_mfma_flops}.get(dom_name, lambda c: None)(cfg)
         achieved = fl / launches_per_step / (dom_avg_ms / 1e3) / 1e12 if fl else None
         roof = {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
                 "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
