@@ -56,6 +56,12 @@ What each pin is tied to:
 * pin_golden_two_element  -- the hand-derived 4-cell example in tests/golden.
 * pin_weights_closed_form -- the Gaussian weights' closed forms in tests/golden.
 * pin_numpy_crosscheck    -- the separately written numpy oracle.
+* pin_image_error         -- the per-image error metric that every GPU parity
+                             gate uses, against hand-computed values in
+                             tests/golden/image_error_cases.json (auto
+                             products scaled by their own maximum, cross
+                             products by the Cauchy-Schwarz bound
+                             sqrt(max XX * max YY), maximum over pixels).
 """
 from __future__ import annotations
 
@@ -87,6 +93,7 @@ PIN_TOL = {
     "golden_two_element": 1e-13,
     "weights_closed_form": 1e-14,
     "numpy_crosscheck": 1e-12,
+    "image_error": 1e-15,
 }
 
 
@@ -494,6 +501,28 @@ def pin_numpy_crosscheck(lib):
     return max(_rel(a, b), _rel(c, d))
 
 
+def _golden_complex(a):
+    a = np.asarray(a, np.float64)
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def pin_image_error(lib, err_fn=None):
+    """The error metric against hand-computed values (no imaging involved:
+    lib is unused and kept for the common pin signature)."""
+    err_fn = err_fn or oracle.image_error
+    g = json.load(open(os.path.join(GOLDEN, "image_error_cases.json")))
+    worst = 0.0
+    for case in g["cases"]:
+        ref = _golden_complex(case["ref"])
+        img = ref + _golden_complex(case["delta"])
+        want = np.asarray(case["expected"], np.float64)
+        got = np.asarray(err_fn(img, ref, case["n_pol"]), np.float64)
+        if got.shape != want.shape or not np.all(np.isfinite(got)):
+            return float("inf")
+        worst = max(worst, float(np.max(np.abs(got - want))))
+    return worst
+
+
 ALL_PINS = {
     "fft_vs_bruteforce": pin_fft_vs_bruteforce,
     "bf_equivalence": pin_bf_equivalence,
@@ -512,4 +541,5 @@ ALL_PINS = {
     "golden_two_element": pin_golden_two_element,
     "weights_closed_form": pin_weights_closed_form,
     "numpy_crosscheck": pin_numpy_crosscheck,
+    "image_error": pin_image_error,
 }

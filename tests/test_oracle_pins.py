@@ -193,3 +193,56 @@ def test_every_plausible_mistake_fails_a_pin(mutant):
                            capture_output=True, text=True, timeout=300)
         caught = "FAILED" in r.stdout or r.returncode != 0
         assert caught, f"mutant {mutant} passes every paper/maths pin"
+
+
+def _image_error_mutants():
+    # plausible slips in the per-image error metric, planted on the CPU
+    def autos(ref, n_pol):
+        return [np.abs(ref[..., a * n_pol + a, :, :]).max(axis=(-1, -2)) for a in range(n_pol)]
+
+    def with_scale(scale_fn, reduce_axes=(-1, -2), reducer=np.max):
+        def fn(img, ref, n_pol):
+            diff = reducer(np.abs(np.asarray(img) - np.asarray(ref)), axis=reduce_axes)
+            return diff / scale_fn(np.asarray(ref), n_pol, diff.shape)
+        return fn
+
+    def sqrt_scale(ref, n_pol, shape):
+        au = autos(ref, n_pol)
+        return np.stack([np.sqrt(au[a] * au[b]) for a in range(n_pol) for b in range(n_pol)], -1)
+
+    def largest_of_all(ref, n_pol, shape):
+        m = np.abs(ref).max(axis=(-1, -2)).max(axis=-1, keepdims=True)
+        return np.broadcast_to(m, shape)
+
+    def no_sqrt(ref, n_pol, shape):
+        au = autos(ref, n_pol)
+        return np.stack([au[a] * au[b] for a in range(n_pol) for b in range(n_pol)], -1)
+
+    def own_max(ref, n_pol, shape):
+        return np.abs(ref).max(axis=(-1, -2))
+
+    def other_auto(ref, n_pol, shape):
+        au = autos(ref, n_pol)
+        return np.stack([np.sqrt(au[n_pol - 1 - a] * au[n_pol - 1 - b])
+                         for a in range(n_pol) for b in range(n_pol)], -1)
+
+    def per_pixel(img, ref, n_pol):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return (np.abs(img - ref) / np.abs(ref)).max(axis=(-1, -2))
+
+    return {"largest_of_all_four": with_scale(largest_of_all),
+            "dropped_sqrt": with_scale(no_sqrt),
+            "cross_scaled_by_itself": with_scale(own_max),
+            "autos_swapped": with_scale(other_auto),
+            "wrong_axes": with_scale(sqrt_scale, reduce_axes=(-3, -1)),
+            "mean_not_max": with_scale(sqrt_scale, reducer=np.mean),
+            "per_pixel_relative": per_pixel}
+
+
+@pytest.mark.parametrize("mutant", sorted(_image_error_mutants()))
+def test_image_error_pin_catches_mistakes(lib, mutant):
+    try:
+        err = P.pin_image_error(lib, err_fn=_image_error_mutants()[mutant])
+    except (ValueError, IndexError):
+        err = float("inf")
+    assert not err <= P.PIN_TOL["image_error"], mutant
