@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the EPIC imager hot path on one MI355X.
 
-A step is one whole cadence through image_cadence: every channel and every
+A step is one whole cadence through image_cadence: every station, channel and
 time sample of the workload is gridded, transformed, squared and averaged
-(Eq. 3 then Eq. 2).  The default workload is the station-scale layout: 256
-elements in a 38 m circle (1.5 m minimum spacing), 150 MHz, 64x64 grid at
-lambda/2, 3x3 Gaussian kernel, 2 pols, 1024 channels, 2048 samples per
-cadence, int8 complex voltages (sigma 16), FP32 FFT path.  Inputs are seeded,
-synthetic and already resident in HBM when the timed region starts.
+(Eq. 3 then Eq. 2).  The default workload is the hierarchical layout, the
+largest that fits one GPU: 96 stations of 64-1024 elements (uniform counts)
+at the density of an SKA-low-like station, each on a 32x32, 64x64 or 128x128
+grid chosen by its footprint, 3x3 Gaussian kernel, 2 pols, 64 channels, 1024
+samples per cadence, int8 complex voltages (sigma 16).  It is timed with the
+FP16-split DFT-GEMM transform (its own precision) and with the FP32 FFT, in
+the same run, on the same resident voltages.  Inputs are seeded, synthetic
+and already resident in HBM when the timed region starts.
 
 Prints one JSON line: grid pixel-samples/s (sum over stations of
-nx*ny*n_chan*n_time per cadence, divided by the cadence time), the roofline
-of the dominant kernel (timed live with HIP events on its own stream), and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+nx*ny*n_chan*n_time per cadence, divided by the cadence time) of the first
+precision, the other under "precisions", the roofline of each precision's
+dominant kernel (algorithmic work per launch over its launch duration, timed
+live with HIP events on its launch stream), the worst error of each against
+the FP64 CPU oracle on a bounded sample, and that oracle's own throughput.
 """
 from __future__ import annotations
 
@@ -79,95 +84,214 @@ def measured_traffic(kernel: str, workload: str, chunk):
     return int(m_b.group(1)) if h.hexdigest()[:16] == m_h.group(1) else None
 
 
-def flops_per_pixel_sample(cfg, st, with_grid=True):
-    """Algorithmic FP32 work per grid pixel-sample of the FFT path.
+def box_sides(cfg, st):
+    """Footprint box sides (bw, bh) in cells of one station at every channel,
+    placed exactly as the plan places them: nearest cell floor(u + 1/2) of
+    every element, widened by the kernel's half support."""
+    h = (st.support - 1) // 2
+    out = []
+    for lam in cfg.wavelengths_m:
+        d = W.GRID_SPACING_WL * lam
+        ci = np.floor(st.pos_m[:, 0] / d + st.nx // 2 + 0.5)
+        cj = np.floor(st.pos_m[:, 1] / d + st.ny // 2 + 0.5)
+        out.append((int(ci.max() - ci.min()) + 2 * h + 1, int(cj.max() - cj.min()) + 2 * h + 1))
+    return out
 
-    transform: 5 N log2 N per complex N-point transform, per pol;
-    gridding: 4 flops (complex x real weight, complex add) per tap per pol;
-    products: XX and YY 3 flops each, XY 6 (YX is its conjugate); accumulation:
-    one add per real component (4 for two pols, 1 for one)."""
+
+def fft_flops_per_pixel_sample(cfg, st, with_grid=True):
+    """Algorithmic FP32 work per grid pixel-sample of the FFT path, with the
+    paper's FLOP constants (a complex multiply 6, a complex add 2, Sec. 3):
+    transform 5 log2(N^2) per pol (5 N log2 N per N-point transform), squaring
+    6 n_p^2 and accumulation 2 n_p^2 per pixel (Table 2), gridding 4 per tap
+    and pol (complex value times real weight, added).  C2: 156.5."""
     npix = st.nx * st.ny
     fft = cfg.n_pol * 5.0 * math.log2(npix)
     grid = 4.0 * st.n_elem * st.support ** 2 * cfg.n_pol / npix if with_grid else 0.0
-    prod = 12.0 + 4.0 if cfg.n_pol == 2 else 3.0 + 1.0
-    return fft + grid + prod
+    return fft + grid + 8.0 * cfg.n_pol ** 2
 
 
-def split_mfma_flops(cfg):
-    """Matrix-core flops of the fused split-precision kernel for one cadence
-    (stations with square grids up to 64): per sample, pol and channel, each of
-    the n/16 waves (16 output rows each) runs my*mx stage-1 and (n/16)*mx
-    stage-2 16x16x32 tiles for the real and imaginary outputs, three split
-    products each, where mx, my are the footprint box sides in 16-cell tiles.
-    The box follows the element cells and kernel support exactly as the plan
-    places them."""
+def split_flops_per_sample_pol(cfg, st):
+    """Algorithmic matrix-core work of the split-precision 2-D DFT-GEMM of one
+    station, per (sample, pol), summed over the channels: Z = F_y X F_x^T
+    pruned to the footprint (the y stage reads the f_y footprint rows, the x
+    stage the f_x columns), complex entries as 2 x 2 real blocks (8 flop per
+    complex multiply-add), three split products per stage:
+    24 N f_x (f_y + N) for an N x N grid (48 N^3 dense)."""
+    n = st.nx
+    return sum(24.0 * n * bw * (bh + n) for bw, bh in box_sides(cfg, st))
+
+
+# Kernels the bench can put on a roofline: timer name -> (bound, stations the
+# kernel serves, algorithmic work of one cadence over those stations).
+def _fft_work(cfg, stations, with_grid=True):
+    return sum(fft_flops_per_pixel_sample(cfg, s, with_grid) * s.nx * s.ny * cfg.n_chan * cfg.n_time
+               for s in stations)
+
+
+def _split_work(cfg, stations):
+    return sum(split_flops_per_sample_pol(cfg, s) * cfg.n_time * cfg.n_pol for s in stations)
+
+
+def _grid_bytes(cfg, stations, rows_only=False):
+    """Gridding: voltages read once, every written cell once per (sample, pol)."""
+    bv = 2 if cfg.volt_type == W.CI8 else 8
     total = 0
-    for st in cfg.stations:
-        if st.nx != st.ny or st.nx > 64:
-            continue
-        h = (st.support - 1) // 2
-        for lam in cfg.wavelengths_m:
-            d = W.GRID_SPACING_WL * lam
-            ci = np.floor(st.pos_m[:, 0] / d + st.nx // 2 + 0.5)
-            cj = np.floor(st.pos_m[:, 1] / d + st.ny // 2 + 0.5)
-            bw = int(ci.max() - ci.min()) + 2 * h + 1
-            bh = int(cj.max() - cj.min()) + 2 * h + 1
-            mx, my = -(-bw // 16), -(-bh // 16)
-            tiles = (st.nx // 16) * 2 * 3 * (my * mx + (st.nx // 16) * mx)
-            total += tiles * 16 * 16 * 32 * 2 * cfg.n_time * cfg.n_pol
+    for s in stations:
+        for bw, bh in box_sides(cfg, s):
+            cells = s.nx * bh if rows_only else s.nx * s.ny
+            total += cfg.n_time * cfg.n_pol * (s.n_elem * bv + cells * 8)
     return total
 
 
-def tiles128_mfma_flops(cfg):
-    """Matrix-core flops of the 128 x 128 split-precision plane transform for
-    one cadence (stations with 128 x 128 grids): per sample, pol and channel,
-    16 M-tiles (16 output rows each) times ka x cb tiles in the first pass and
-    cb x 8 in the second, three split products of 16x16x32 each, where ka >= cb
-    are the footprint box's sides in 16-cell tiles counted from its first cell
-    (the longer side is transformed first).  The box follows the element cells and kernel support
-    exactly as the plan places them."""
-    total = 0
-    for st in cfg.stations:
-        if st.nx != 128 or st.ny != 128:
-            continue
-        h = (st.support - 1) // 2
-        for lam in cfg.wavelengths_m:
-            d = W.GRID_SPACING_WL * lam
-            ci = np.floor(st.pos_m[:, 0] / d + st.nx // 2 + 0.5)
-            cj = np.floor(st.pos_m[:, 1] / d + st.ny // 2 + 0.5)
-            bw = int(ci.max() - ci.min()) + 2 * h + 1
-            bh = int(cj.max() - cj.min()) + 2 * h + 1
-            sx, sy = -(-bw // 16), -(-bh // 16)
-            ka, cb = max(sx, sy), min(sx, sy)
-            total += 3 * 16 * 16 * 32 * 2 * 16 * cb * (ka + 8) * cfg.n_time * cfg.n_pol
-    return total
+def _power_bytes(cfg, stations, launches):
+    acc = sum(cfg.n_chan * cfg.n_pol ** 2 * s.nx * s.ny * 8 for s in stations)
+    field = sum(cfg.n_chan * cfg.n_time * cfg.n_pol * s.nx * s.ny * 8 for s in stations)
+    return field + launches * 4 * acc / max(1, len(stations)) + acc
 
 
-def pass_mfma_flops(cfg):
-    """Matrix-core flops of the two-pass split-precision transform for one
-    cadence (square grids of 256): per sample, pol and channel, the first pass
-    (along y) runs 2N/16 M-tiles x 2 column tiles x (the footprint's 16-row
-    tiles) for each 32-column block that meets the footprint, the second
-    (along x) the same M-tiles x 2 column tiles x (the footprint's 16-column
-    tiles) for all N/32 blocks; three split products of 16x16x32 each.  Tiles
-    are aligned to the grid, as the passes read them."""
-    total = 0
-    for st in cfg.stations:
-        if st.nx != 256 or st.ny != 256:
-            continue
-        n, h = st.nx, (st.support - 1) // 2
-        for lam in cfg.wavelengths_m:
-            d = W.GRID_SPACING_WL * lam
-            ci = np.floor(st.pos_m[:, 0] / d + n // 2 + 0.5)
-            cj = np.floor(st.pos_m[:, 1] / d + n // 2 + 0.5)
-            x0, x1 = int(ci.min()) - h, int(ci.max()) + h
-            y0, y1 = int(cj.min()) - h, int(cj.max()) + h
-            ks_y, ks_x = (y1 >> 4) - (y0 >> 4) + 1, (x1 >> 4) - (x0 >> 4) + 1
-            nblk_x = (x1 >> 5) - (x0 >> 5) + 1
-            mt = 2 * n // 16
-            mfma = 3 * mt * 2 * (ks_y * nblk_x + ks_x * (n // 32))
-            total += mfma * 16 * 16 * 32 * 2 * cfg.n_time * cfg.n_pol
-    return total
+ROOFLINE_KERNELS = {
+    # FP32 path, fused: gridding, transform, products and accumulation in one kernel
+    "fused_fft_cadence": ("alu", lambda s: s.nx <= 64, lambda c, st, n: _fft_work(c, st)),
+    "fused_cadence": ("alu", lambda s: s.nx <= 128, lambda c, st, n: _fft_work(c, st)),
+    # FP32 128 x 128 transform-and-square over gridded boxes (gridding in grid_box)
+    "fused_fft128_cadence": ("alu", lambda s: s.nx == 128,
+                             lambda c, st, n: _fft_work(c, st, with_grid=False)),
+    # split precision, fused (N <= 64) and the 128 x 128 plane transform
+    "fused_dft_cadence": ("mfma", lambda s: s.nx <= 64, lambda c, st, n: _split_work(c, st)),
+    "fused_dft128_cadence": ("mfma", lambda s: s.nx == 128, lambda c, st, n: _split_work(c, st)),
+    "dft2_tiles128": ("mfma", lambda s: s.nx == 128, lambda c, st, n: _split_work(c, st)),
+    "dft_gemm_pass": ("mfma", lambda s: s.nx == 256, lambda c, st, n: _split_work(c, st)),
+    # HBM-bound stages of the composed path
+    "grid_gather": ("hbm", lambda s: True,
+                    lambda c, st, n: _grid_bytes(c, st, rows_only=all(s.nx >= 128 for s in st))),
+    "square_accumulate": ("hbm", lambda s: True, lambda c, st, n: _power_bytes(c, st, n)),
+}
+
+PEAKS = {"alu": (PEAK_FP32_VALU_TFLOPS, "TFLOP/s"), "mfma": (PEAK_FP16_MFMA_TFLOPS, "TFLOP/s"),
+         "hbm": (PEAK_HBM_GBS, "GB/s")}
+
+
+def roofline(cfg, kern, steps, prec, chunks, traffic_ok):
+    """Roofline of the kernel that takes the most time per step: its
+    algorithmic work per launch (the work of the stations it serves per
+    cadence, divided by its launches per cadence) over its average launch
+    duration, both measured with HIP events on its launch stream."""
+    dom_name, (dom_count, dom_ms) = max(kern.items(), key=lambda kv: kv[1][1])
+    avg_ms = dom_ms / dom_count
+    per_step = dom_count / steps
+    out = {"kernel": dom_name, "avg_launch_ms": round(avg_ms, 4),
+           "launches_per_step": round(per_step, 2)}
+    if dom_name not in ROOFLINE_KERNELS:
+        out.update({"bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                    "traffic": None})
+        return out
+    bound, serves, work_fn = ROOFLINE_KERNELS[dom_name]
+    served = [s for s in cfg.stations if serves(s)] or cfg.stations
+    work = work_fn(cfg, served, per_step) / per_step
+    peak, unit = PEAKS[bound]
+    scale = 1e9 if unit == "GB/s" else 1e12
+    achieved = work / (avg_ms / 1e3) / scale
+    prefix = {"fused_fft_cadence": "fft_", "fused_dft_cadence": "dft_"}.get(dom_name)
+    cls = sorted(v for k, v in chunks.items() if prefix and k.startswith(prefix))
+    chunk = cls[0] if cls and len(set(cls)) == 1 else None
+    out.update({"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": unit,
+                "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(dom_name, f"C{cfg.index}", chunk) if traffic_ok else None,
+                "work_per_launch": work, "chunk": chunk})
+    if bound == "alu":
+        out["flop_per_pixel_sample"] = round(
+            work * per_step / sum(s.nx * s.ny * cfg.n_chan * cfg.n_time for s in served), 2)
+        out["peak_note"] = ("FP32 vector FMA without packed FP32 (256 CU x 64 lanes x 2 flop x "
+                            "2.4 GHz); the published 157.3 TFLOP/s counts packed FP32, which "
+                            "this library is built without")
+        out["frac_of_157_3"] = round(achieved / 157.3, 4)
+    return out
+
+
+def time_precision(cfg, prec_name, common, stations, steps, warmup, autotune):
+    """Autotune, warm up, then time `steps` whole cadences (graph replays as
+    the library runs them); then the same steps again with every kernel
+    bracketed by HIP events on its launch stream, for per-kernel durations."""
+    import torch
+    from paper_2411_17804_amd import epic
+    tune_file = os.environ["EPIC_TUNE_CACHE"]
+    chunks = {}
+    if autotune:
+        t_tune = time.time()
+        epic.autotune(common, stations)
+        log(f"{prec_name}: autotune done in {time.time() - t_tune:.1f} s")
+        if os.path.exists(tune_file):
+            for line in open(tune_file):
+                parts = line.split()
+                if len(parts) == 2:
+                    chunks[parts[0]] = int(parts[1])
+    for _ in range(warmup):
+        epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    epic.timing_reset()
+    epic.timing_enable(True)
+    for _ in range(steps):
+        epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    epic.timing_enable(False)
+    kern = epic.timing_report()
+    log(f"{prec_name}: {ms:.2f} ms/step; kernels {kern}")
+    return ms, kern, chunks
+
+
+def cpu_sample(cfg):
+    """The bounded sample the oracle is timed and checked on: for one station,
+    a spread of channels sized to ~10-30 s of host work; for a hierarchical
+    layout, 8 stations spanning its grid sizes and element counts, 8 channels
+    each.  Every sample of the cadence is kept (the image is its mean)."""
+    if len(cfg.stations) == 1:
+        n = {1: 4, 2: 192, 3: 12, 5: 4}.get(cfg.index, 4)
+        chans = np.unique(np.linspace(0, cfg.n_chan - 1, min(n, cfg.n_chan)).astype(int))
+        return [(0, chans)]
+    picks = []
+    for grid, k in ((128, 3), (64, 3), (32, 2)):
+        idx = sorted((i for i, s in enumerate(cfg.stations) if s.nx == grid),
+                     key=lambda i: cfg.stations[i].n_elem)
+        if idx:
+            picks += [idx[int(round(j))] for j in np.linspace(0, len(idx) - 1, min(k, len(idx)))]
+    chans = np.unique(np.linspace(0, cfg.n_chan - 1, min(8, cfg.n_chan)).astype(int))
+    return [(s, chans) for s in dict.fromkeys(picks)]
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(aff, int(omp)) if omp and omp.isdigit() and int(omp) > 0 else aff
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "omp_num_threads": omp,
+            "cpu_model": model, "threads": threads}
+
+
+def source_info():
+    import hashlib
+    import subprocess
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2411_17804_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    try:
+        git = subprocess.run(["git", "-C", ROOT, "rev-parse", "HEAD"], capture_output=True,
+                             text=True, timeout=10).stdout.strip() or None
+    except (OSError, subprocess.SubprocessError):
+        git = None
+    return {"git_head": git, "csrc_sha256_16": h.hexdigest()[:16]}
 
 
 def main():
@@ -175,15 +299,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--precision", choices=sorted(PREC_NAMES), default="fp32")
+    ap.add_argument("--config", type=int, default=4,
+                    help="workload C1..C5 (default C4, the hierarchical layout: the largest "
+                         "that fits one GPU)")
+    ap.add_argument("--precision", choices=sorted(PREC_NAMES) + ["both", "all"], default="both",
+                    help="both: the workload's own precision and the other of fp32/fp16-split "
+                         "(the metric's comparison); all: fp32, fp16 and bf16 split")
     ap.add_argument("--n-chan", type=int, default=None, help="shrink the band (testing)")
     ap.add_argument("--n-time", type=int, default=None, help="shrink the cadence (testing)")
-    ap.add_argument("--cpu-channels", type=int, default=192,
-                    help="channels of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default time-chunk length of the fused kernels")
+                    help="keep the default tile parameters of the fused kernels")
     ap.add_argument("--no-stages", action="store_true",
                     help="skip the per-stage (unfused) roofline measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -216,195 +342,128 @@ def main():
     torch.cuda.set_device(dev)
     epic.load()
 
-    cfg = W.make_config(args.config, n_chan=args.n_chan, n_time=args.n_time,
-                        precision=PREC_NAMES[args.precision])
+    cfg = W.make_config(args.config, n_chan=args.n_chan, n_time=args.n_time)
+    own = {W.FP32_FFT: "fp32", W.FP16_SPLIT: "fp16", W.BF16_SPLIT: "bf16"}[cfg.precision]
+    if args.precision == "both":
+        precs = [own, "fp16" if own == "fp32" else "fp32"]
+    elif args.precision == "all":
+        precs = [own] + [p for p in ("fp32", "fp16", "bf16") if p != own]
+    else:
+        precs = [args.precision]
     log(f"workload C{cfg.index}: {len(cfg.stations)} station(s), {cfg.n_chan} channels x "
-        f"{cfg.n_time} samples, precision {args.precision}")
+        f"{cfg.n_time} samples, precisions {precs}")
     t_gen = time.time()
-    stations = []
-    host_volts = []
-    for s, st in enumerate(cfg.stations):
-        v = W.station_volts(cfg, s, threads=16)
-        host_volts.append(v if not args.no_cpu_baseline else None)
-        if v.dtype == np.int8:
-            vd = torch.from_numpy(v).to(dev)
-        else:
-            vd = torch.from_numpy(v.view(np.float32)).to(dev)
-        img = torch.zeros((cfg.n_chan, cfg.n_pol * cfg.n_pol, st.ny, st.nx, 2),
-                          dtype=torch.float32, device=dev)
-        stations.append(epic.Station(st.pos_m, st.nx, st.ny, st.kernel_type, st.support,
-                                     st.sigma_cells, volts=vd, image=img))
-    common = epic.Common(cfg.n_pol, cfg.wavelengths_m, W.GRID_SPACING_WL, cfg.n_time,
-                         cfg.volt_type, cfg.precision)
+    vdev = []
+    sample = cpu_sample(cfg) if not args.no_cpu_baseline else []
+    host_volts = {}
+    want = {s for s, _ in sample}
+    hi = host_info()
+    for s in range(len(cfg.stations)):
+        v = W.station_volts(cfg, s, threads=hi["threads"])
+        if s in want:
+            host_volts[s] = v
+        vdev.append(torch.from_numpy(v if v.dtype == np.int8 else v.view(np.float32)).to(dev))
+        del v
     torch.cuda.synchronize()
     log(f"inputs generated and resident in HBM ({cfg.volt_bytes() / 1e9:.2f} GB) "
         f"in {time.time() - t_gen:.1f} s")
 
-    # the tuned chunk lengths come back through the library's tune-cache file
-    # ("class chunk" lines); without autotuning every class uses 32
     tune_file = os.environ.get("EPIC_TUNE_CACHE")
     if not tune_file:
         import tempfile
         tune_file = os.path.join(tempfile.mkdtemp(prefix="epic_bench_"), "tune.txt")
         os.environ["EPIC_TUNE_CACHE"] = tune_file
-    chunks = {}
-    if not args.no_autotune:
-        t_tune = time.time()
-        epic.autotune(common, stations)
-        log(f"autotune done in {time.time() - t_tune:.1f} s")
-        if os.path.exists(tune_file):
-            for line in open(tune_file):
-                parts = line.split()
-                if len(parts) == 2:
-                    chunks[parts[0]] = int(parts[1])
-        log(f"tuned chunks {chunks}")
-    for i in range(args.warmup):
-        epic.image_cadence(common, stations)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
 
-    # timed region: the cadence as the library runs it (graph replays)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        epic.image_cadence(common, stations)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-
-    # the same steps again with every kernel bracketed by HIP events on its
-    # own stream (eager launches), for the per-kernel durations
-    epic.timing_reset()
-    epic.timing_enable(True)
-    for i in range(args.steps):
-        epic.image_cadence(common, stations)
-    torch.cuda.synchronize()
-    epic.timing_enable(False)
-    kern = epic.timing_report()
     pix = cfg.pixel_samples()
-    value = pix / (ms_per_step / 1e3)
-    log(f"{args.steps} steps: {ms_per_step:.2f} ms/step, {value:.3e} px-samples/s; kernels {kern}")
+    full = cfg.n_chan == W.make_config(cfg.index).n_chan and args.n_time is None
+    results = {}
+    images = {}
+    for p in precs:
+        common = epic.Common(cfg.n_pol, cfg.wavelengths_m, W.GRID_SPACING_WL, cfg.n_time,
+                             cfg.volt_type, PREC_NAMES[p])
+        stations = []
+        for s, st in enumerate(cfg.stations):
+            img = torch.zeros((cfg.n_chan, cfg.n_pol * cfg.n_pol, st.ny, st.nx, 2),
+                              dtype=torch.float32, device=dev)
+            stations.append(epic.Station(st.pos_m, st.nx, st.ny, st.kernel_type, st.support,
+                                         st.sigma_cells, volts=vdev[s], image=img))
+        ms, kern, chunks = time_precision(cfg, p, common, stations, args.steps, args.warmup,
+                                          not args.no_autotune)
+        value = pix / (ms / 1e3)
+        results[p] = {
+            "value": value, "ms_per_step": ms,
+            "realtime_factor": (cfg.n_time * 25e-6) / (ms / 1e3),
+            "roofline": roofline(cfg, kern, args.steps, p, chunks, full),
+            "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
+            "launches_per_step": round(sum(v[0] for v in kern.values()) / args.steps, 1),
+            "tuned": chunks,
+        }
+        # keep the sampled stations' images for the error check; free the rest
+        images[p] = {s: stations[s].image[torch.as_tensor(ch, device=dev)].cpu().numpy()
+                     for s, ch in sample}
+        del stations
+        epic.cache_clear()
+        torch.cuda.empty_cache()
 
-    # dominant kernel and its roofline
-    dom_name, (dom_count, dom_ms) = max(kern.items(), key=lambda kv: kv[1][1])
-    prefix = {"fused_fft_cadence": "fft_", "fused_dft_cadence": "dft_",
-              "fused_fft128_cadence": "fft128_"}.get(dom_name)
-    cls = sorted(v for k, v in chunks.items() if prefix and k.startswith(prefix))
-    dom_chunk = cls[0] if len(set(cls)) == 1 else (32 if args.no_autotune else None)
-    dom_avg_ms = dom_ms / dom_count
-    launches_per_step = dom_count / args.steps
-    st0 = cfg.stations[0]
-    if args.precision == "fp32" and dom_name != "grid_gather":
-        # the stations the dominant kernel serves (grids up to 64: the fused
-        # FFT kernels with their gridding; 128: the 128 x 128 transform kernel,
-        # whose gridding runs in k_grid_box)
-        served = [s for s in cfg.stations if (s.nx == 128) == (dom_name == "fused_fft128_cadence")]
-        served = served or cfg.stations
-        with_grid = dom_name != "fused_fft128_cadence"
-        work_step = sum(flops_per_pixel_sample(cfg, s, with_grid) * s.nx * s.ny * cfg.n_chan * cfg.n_time
-                        for s in served)
-        flop_px = work_step / sum(s.nx * s.ny * cfg.n_chan * cfg.n_time for s in served)
-        work = work_step / launches_per_step
-        achieved = work / (dom_avg_ms / 1e3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3),
-                "peak": round(PEAK_FP32_VALU_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
-                "traffic": measured_traffic(dom_name, f"C{cfg.index}", dom_chunk)
-                if cfg.n_chan == W.make_config(cfg.index).n_chan and args.n_time is None else None,
-                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": dom_chunk,
-                "flop_per_pixel_sample": round(flop_px, 2)}
-    elif dom_name == "grid_gather" and args.precision == "fp32":
-        # the composed path's gather gridding: HBM-bound; the voltages read
-        # once and every written cell once per sample (on the two-pass grids,
-        # 256 wide or 128 x 128, only the footprint box's rows are written)
-        bv = 2 if cfg.volt_type == W.CI8 else 8
-        bytes_step = 0
-        for s in cfg.stations:
-            two_pass = s.ny == 256 or (s.ny == 128 and s.nx >= 128)
-            h = (s.support - 1) // 2
-            for lam in cfg.wavelengths_m:
-                rows = s.ny
-                if two_pass:
-                    cj = np.floor(s.pos_m[:, 1] / (W.GRID_SPACING_WL * lam) + s.ny // 2 + 0.5)
-                    rows = int(cj.max() - cj.min()) + 2 * h + 1
-                bytes_step += cfg.n_time * cfg.n_pol * (s.n_elem * bv + s.nx * rows * 8)
-        achieved = bytes_step / launches_per_step / (dom_avg_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": None,
-                "bytes_per_step": int(bytes_step)}
-    elif dom_name == "square_accumulate":
-        # the composed path's squaring and compensated accumulation: HBM-bound;
-        # per launch it reads a chunk of transformed planes and reads and
-        # writes the (sum, compensation) accumulators, and the last launch of
-        # each station writes its image
-        acc_b = sum(cfg.n_chan * cfg.n_pol ** 2 * s.nx * s.ny * 8 for s in cfg.stations)
-        field_b = sum(cfg.n_chan * cfg.n_time * cfg.n_pol * s.nx * s.ny * 8 for s in cfg.stations)
-        bytes_step = field_b + launches_per_step * 4 * acc_b / len(cfg.stations) + acc_b
-        achieved = bytes_step / launches_per_step / (dom_avg_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": None,
-                "bytes_per_step": int(bytes_step)}
-    else:
-        fl = {"fused_dft_cadence": split_mfma_flops,
-              "dft2_tiles128": tiles128_mfma_flops,
-              "dft_gemm_pass": pass_mfma_flops}.get(dom_name, lambda c: None)(cfg)
-        achieved = fl / launches_per_step / (dom_avg_ms / 1e3) / 1e12 if fl else None
-        roof = {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
-                "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP16_MFMA_TFLOPS, 4) if achieved else None,
-                "traffic": measured_traffic(dom_name, f"C{cfg.index}", dom_chunk)
-                if cfg.n_chan == W.make_config(cfg.index).n_chan and args.n_time is None else None,
-                "kernel": dom_name, "avg_launch_ms": round(dom_avg_ms, 4), "chunk": dom_chunk,
-                "flop_per_step": fl}
-
+    dtype_name = {"fp32": "f32", "fp16": "f16x3+f32acc", "bf16": "bf16x3+f32acc"}
+    head = results[precs[0]]
+    workload = {
+        1: "C1: 64 el in a 16 m square, 32x32 grid, nearest, 1 pol, cf32, 4 ch x 256",
+        2: "C2: station of 256 el in a 38 m circle, 64x64 grid, 3x3 Gaussian, 2 pols, ci8, 1024 ch x 2048",
+        3: "C3: dense 64x32 lattice, 128x128 grid, 3x3 Gaussian, 2 pols, cf32, 256 ch x 4096",
+        4: "C4: 96 stations of 64-1024 el, 32/64/128 grids by footprint, 3x3 Gaussian, 2 pols, ci8, 64 ch x 1024",
+        5: "C5: 128x128 lattice less 5%, 256x256 grid, 5x5 Gaussian, 2 pols, cf32, 128 ch x 512"}[cfg.index]
     out = {
         "metric": "grid pixel-samples/s per GPU",
-        "value": value,
+        "value": head["value"],
         "unit": "pixel-samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f16x3+f32acc", "bf16": "bf16x3+f32acc"}[args.precision],
+        "dtype": dtype_name[precs[0]],
         "data": "synthetic (seeded layouts and voltages shaped like the paper's arrays)",
-        "config": {"workload": f"C{cfg.index}: " + {
-            1: "64 el, 32x32 grid, nearest, 1 pol, cf32",
-            2: "station: 256 el in 38 m circle, 64x64 grid, 3x3 Gaussian, 2 pols, ci8",
-            3: "dense 64x32 lattice, 128x128 grid, 3x3 Gaussian, 2 pols, cf32",
-            4: "96 stations of 64-1024 el, 32/64/128 grids, 2 pols, ci8",
-            5: "128x128 lattice -5%, 256x256 grid, 5x5 Gaussian, 2 pols, cf32"}[cfg.index],
-            "n_chan": cfg.n_chan, "n_time": cfg.n_time, "n_stations": len(cfg.stations),
-            "precision": args.precision, "pixel_samples_per_step": pix,
-            "realtime_factor": (cfg.n_time * 25e-6) / (ms_per_step / 1e3)},
-        "roofline": roof,
-        "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
+        "config": {"workload": workload, "n_chan": cfg.n_chan, "n_time": cfg.n_time,
+                   "n_stations": len(cfg.stations), "precision": precs[0],
+                   "pixel_samples_per_step": pix, "realtime_factor": head["realtime_factor"],
+                   "seed": cfg.seed},
+        "roofline": head["roofline"],
+        "precisions": {p: {k: v for k, v in r.items()} for p, r in results.items()},
     }
+    if "fp16" in results and "fp32" in results:
+        out["fp16_split_vs_fp32"] = round(results["fp16"]["value"] / results["fp32"]["value"], 4)
 
     if not args.no_stages:
+        s0 = next(i for i, s in enumerate(cfg.stations) if s.nx <= 128)
+        st0 = cfg.stations[s0]
         c0 = epic.Common(cfg.n_pol, cfg.wavelengths_m, W.GRID_SPACING_WL, cfg.n_time,
                          cfg.volt_type, cfg.precision)
-        out["stages"] = stage_rooflines(cfg, c0, stations[0])
+        station = epic.Station(st0.pos_m, st0.nx, st0.ny, st0.kernel_type, st0.support,
+                               st0.sigma_cells, volts=vdev[s0])
+        out["stages"] = stage_rooflines(cfg, c0, station, s0)
         if len(cfg.stations) == 1:
             out["stages"]["inter_station_epic"] = array_stage(cfg)
         log(f"stages: {out['stages']}")
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, stations, host_volts, args.cpu_channels)
+    if sample:
+        out["cpu_baseline"], errs = cpu_baseline(cfg, sample, host_volts, images, hi)
+        for p, e in errs.items():
+            out["precisions"][p]["worst_error_on_cpu_sample"] = e
+    out["host"] = hi
+    out["source"] = source_info()
     print(json.dumps(out), flush=True)
 
 
-def stage_rooflines(cfg, common, station, nt=64, reps=3):
-    """Each unfused stage on a block of nt samples of every channel of the
-    first station, timed with events on the current stream, against the
-    roofline that bounds it (algorithmic bytes for HBM-bound stages,
+def stage_rooflines(cfg, common, station, s_idx=0, nt=64, reps=3):
+    """Each unfused stage on a block of nt samples of every channel of one
+    station (index s_idx), timed with events on the current stream, against
+    the roofline that bounds it (algorithmic bytes for HBM-bound stages,
     algorithmic matrix-core flops for the DFT-matrix products)."""
     import torch
     from paper_2411_17804_amd import epic
-    st = cfg.stations[0]
+    st = cfg.stations[s_idx]
     npix = st.nx * st.ny
     nt = min(nt, cfg.n_time)
     batch = cfg.n_chan * nt * cfg.n_pol
@@ -492,14 +551,15 @@ def stage_rooflines(cfg, common, station, nt=64, reps=3):
                                 "achieved": round(b / ms / 1e6, 1), "unit": "GB/s",
                                 "frac": round(b / ms / 1e6 / PEAK_HBM_GBS, 4)}
     del kern
-    res.update(xfft_stages(cfg, common, station, timed))
-    res["_block"] = f"{cfg.n_chan} channels x {nt} samples x {cfg.n_pol} pols of {st.nx}x{st.ny}"
+    res.update(xfft_stages(cfg, common, station, timed, s_idx))
+    res["_block"] = (f"station {s_idx}: {cfg.n_chan} channels x {nt} samples x {cfg.n_pol} pols "
+                     f"of {st.nx}x{st.ny}")
     del grid, out, acc, img
     torch.cuda.empty_cache()
     return res
 
 
-def xfft_stages(cfg, common, station, timed):
+def xfft_stages(cfg, common, station, timed, s_idx=0):
     """The XFFT route (Sec. 5.4) on the whole cadence of the first station:
     the correlator of Eq. 4 against the matrix-core roofline of its dtype
     (algorithmic ops: 8 per complex product, over the R (R + 1) / 2 distinct
@@ -509,7 +569,7 @@ def xfft_stages(cfg, common, station, timed):
     image rate in the headline's unit (it returns the same image)."""
     import torch
     from paper_2411_17804_amd import epic
-    st = cfg.stations[0]
+    st = cfg.stations[s_idx]
     R = st.n_elem * cfg.n_pol
     vis_bytes = cfg.n_chan * R * R * 8
     if vis_bytes > (64 << 30):
@@ -544,10 +604,8 @@ def array_stage(cfg, reps=2):
     16 copies of the first station (centres in a 300 m circle, 45 m apart):
     4 channels x 256 samples, every beam pixel, array grid 32 x 32 at half the
     station diameter, nearest-cell gridding.  Station fields come from
-    grid_voltages + fft2_batched (timed as beam formation); array_cadence (the
-    EPIC route at array scale) and array_xfft (the XFFT route) are timed on
-    their own; the rate is array-grid pixel-samples per second of the EPIC
-    route."""
+    grid_voltages + fft2_batched (timed as beam formation); array_cadence is
+    timed on its own; the rate is array-grid pixel-samples per second."""
     import torch
     from paper_2411_17804_amd import epic
     st = cfg.stations[0]
@@ -598,44 +656,60 @@ def array_stage(cfg, reps=2):
 
     ms_b = timed(form)
     ms_a = timed(lambda: epic.array_cadence(common_a, arr, beams, st.nx, st.ny, pix))
-    ms_x = timed(lambda: epic.array_xfft(common_a, arr, beams, st.nx, st.ny, pix))
     problems = n_ch * pix.size
     out = {"stations": n_st, "channels": n_ch, "samples": nt, "beam_pixels": int(pix.size),
            "array_grid": na, "array_spacing_wl": round(dA, 3),
            "beam_formation_ms": round(ms_b, 3), "array_cadence_ms": round(ms_a, 3),
            "array_pixel_samples_per_s": problems * nt * na * na / ms_a * 1e3,
-           "array_xfft_ms": round(ms_x, 3),
            "voltage_bytes": n_st * n_ch * nt * st.n_elem * cfg.n_pol * bv}
     del beams, volts, img
     torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(cfg, stations, host_volts, n_sample_chan):
-    """Time the FP64 oracle on a bounded sample (the first station, a spread of
-    channels, every sample of the cadence) and check the GPU images there."""
+def cpu_baseline(cfg, sample, host_volts, images, hi):
+    """Time the FP64 oracle on the bounded sample (sample: [(station, channels)],
+    every sample of the cadence) with every thread the process may use, and
+    once more on one channel of the first sampled station with one thread;
+    check every precision's GPU images on the sample against it."""
     import oracle
-    import torch
-    threads = min(16, os.cpu_count() or 1)
-    s = 0
-    st = cfg.stations[s]
-    n = min(n_sample_chan, cfg.n_chan)
-    chans = np.unique(np.linspace(0, cfg.n_chan - 1, n).astype(int))
-    v = host_volts[s][chans]
-    log(f"cpu_baseline: oracle on {len(chans)} channels x {cfg.n_time} samples, {threads} threads")
+    threads = hi["threads"]
+    errs = {p: 0.0 for p in images}
+    px = 0
+    dt = 0.0
+    desc = []
+    for s, chans in sample:
+        st = cfg.stations[s]
+        v = host_volts[s][chans]
+        t0 = time.perf_counter()
+        ref = oracle.image(st.pos_m, cfg.wavelengths_m[chans], W.GRID_SPACING_WL, st.nx, st.ny,
+                           st.kernel_type, st.support, st.sigma_cells, v, n_threads=threads)
+        dt += time.perf_counter() - t0
+        px += st.nx * st.ny * len(chans) * cfg.n_time
+        desc.append(f"{s}({st.nx}x{st.ny}, {st.n_elem} el)")
+        for p, imgs in images.items():
+            a = imgs[s]
+            got = a[..., 0].astype(np.float64) + 1j * a[..., 1]
+            errs[p] = max(errs[p], float(oracle.image_error(got, ref, cfg.n_pol).max()))
+    s0, ch0 = sample[0]
+    st = cfg.stations[s0]
     t0 = time.perf_counter()
-    ref = oracle.image(st.pos_m, cfg.wavelengths_m[chans], W.GRID_SPACING_WL, st.nx, st.ny,
-                       st.kernel_type, st.support, st.sigma_cells, v, n_threads=threads)
-    dt = time.perf_counter() - t0
-    a = stations[s].image[torch.as_tensor(chans, device=stations[s].image.device)].cpu().numpy()
-    got = a[..., 0].astype(np.float64) + 1j * a[..., 1]
-    err = oracle.image_error(got, ref, cfg.n_pol)
-    px = st.nx * st.ny * len(chans) * cfg.n_time
-    log(f"cpu_baseline: {dt:.1f} s, worst GPU error on the sample {err.max():.2e}")
-    return {"value": px / dt, "unit": "pixel-samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"station 0, {len(chans)} of {cfg.n_chan} channels (evenly spread), all "
-                      f"{cfg.n_time} samples; C99 FP64 oracle, OpenMP over channels",
-            "seconds": round(dt, 2), "gpu_max_error_on_sample": float(err.max())}
+    oracle.image(st.pos_m, cfg.wavelengths_m[ch0[:1]], W.GRID_SPACING_WL, st.nx, st.ny,
+                 st.kernel_type, st.support, st.sigma_cells, host_volts[s0][ch0[:1]], n_threads=1)
+    dt1 = time.perf_counter() - t0
+    px1 = st.nx * st.ny * cfg.n_time
+    log(f"cpu_baseline: {dt:.1f} s on {threads} threads ({px / dt:.3e} px-samples/s), 1 thread "
+        f"{px1 / dt1:.3e}; worst GPU error on the sample {errs}")
+    n_ch = len(sample[0][1])
+    return ({"value": px / dt, "unit": "pixel-samples/s", "cores": threads, "kind": "oracle",
+             "sample": f"stations {', '.join(desc)} x {n_ch} of {cfg.n_chan} channels (evenly "
+                       f"spread) x all {cfg.n_time} samples; C99 FP64 oracle, OpenMP over "
+                       f"channels",
+             "seconds": round(dt, 2),
+             "one_thread": {"value": px1 / dt1, "seconds": round(dt1, 2),
+                            "sample": f"station {s0}, channel {int(ch0[0])}, all samples"},
+             "nproc": hi["nproc"], "affinity_cpus": hi["affinity_cpus"],
+             "cpu_model": hi["cpu_model"]}, errs)
 
 
 if __name__ == "__main__":

@@ -175,6 +175,51 @@ def _dptr(t):
     return t.data_ptr()
 
 
+# dtypes a device buffer may have: complex float32 data as complex64 or as
+# float32 (re, im) pairs; ci8 voltages as int8 (re, im) pairs
+_CF32 = ("complex64", "float32")
+_F32 = ("float32",)
+_I8 = ("int8",)
+
+
+def _dev(t, what: str, nbytes: int, dtypes=_CF32):
+    """Device address of buffer t after checking it against the size and type
+    the call implies.  The C ABI receives no device-buffer sizes, so this is
+    the one place a wrong tensor can be caught: it must be a contiguous GPU
+    tensor of one of the dtypes and exactly nbytes long.  Raw integer
+    addresses and None are passed through unchecked (the ABI rejects a null
+    pointer where one is required)."""
+    if t is None or isinstance(t, int):
+        return t
+    dt = str(t.dtype).replace("torch.", "")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: expected a GPU tensor, got one on {t.device}")
+    if dt not in dtypes:
+        raise ValueError(f"{what}: dtype {dt}, expected one of {', '.join(dtypes)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor is not contiguous (the kernels read it densely)")
+    got = t.numel() * t.element_size()
+    if got != nbytes:
+        raise ValueError(f"{what}: {got} bytes, the call implies {nbytes} "
+                         f"(shape {tuple(t.shape)}, dtype {dt})")
+    return t.data_ptr()
+
+
+def _volts(common: "Common", station: "Station", what: str = "volts"):
+    """Checked address of a station's voltages [n_chan][n_time][n_elem][n_pol]."""
+    n = len(np.atleast_1d(common.wavelength_m)) * common.n_time * np.asarray(station.pos_m).shape[0] \
+        * common.n_pol
+    if common.volt_type == CI8:
+        return _dev(station.volts, what, n * 2, _I8)
+    return _dev(station.volts, what, n * 8, _CF32)
+
+
+def _image(common: "Common", station: "Station", what: str = "image", planes: int = 1):
+    """Checked address of a station's image [n_chan][planes][n_pol^2][ny][nx] cf32."""
+    n = len(np.atleast_1d(common.wavelength_m)) * planes * common.n_pol ** 2 * station.nx * station.ny
+    return _dev(station.image, what, n * 8)
+
+
 @dataclasses.dataclass
 class Common:
     """Parameters shared by the stations of a call (epic_common)."""
@@ -204,40 +249,50 @@ class Station:
     volts: object = None       # torch tensor on the GPU
     image: object = None       # torch tensor on the GPU (complex64 or float32 pairs)
 
-    def to_c(self):
+    def to_c(self, volts=None, image=None):
+        """The epic_station struct; volts and image are the (checked) device
+        addresses to put in it, by default the tensors' own unchecked ones."""
         pos = np.ascontiguousarray(self.pos_m, dtype=np.float64)
         s = _Station(pos.shape[0], pos.ctypes.data, self.nx, self.ny,
                      _Kernel(self.kernel_type, self.support, float(self.sigma_cells)),
-                     _dptr(self.volts), _dptr(self.image))
+                     _dptr(self.volts) if volts is None else volts,
+                     _dptr(self.image) if image is None else image)
         return s, pos
 
 
 def grid_voltages(common: Common, station: Station, t0: int, nt: int, grid, stream=None):
     lib = load()
     c, keep1 = common.to_c()
-    s, keep2 = station.to_c()
-    _check(lib.grid_voltages(ctypes.byref(c), ctypes.byref(s), t0, nt, _dptr(grid),
-                             _stream(stream)))
+    s, keep2 = station.to_c(volts=_volts(common, station))
+    n_chan = len(np.atleast_1d(common.wavelength_m))
+    g = _dev(grid, "grid", n_chan * max(nt, 0) * common.n_pol * station.ny * station.nx * 8)
+    _check(lib.grid_voltages(ctypes.byref(c), ctypes.byref(s), t0, nt, g, _stream(stream)))
 
 
 def fft2_batched(nx: int, ny: int, batch: int, precision: int, inp, out, stream=None):
     lib = load()
-    _check(lib.fft2_batched(nx, ny, batch, precision, _dptr(inp), _dptr(out), _stream(stream)))
+    n = max(batch, 0) * nx * ny * 8
+    _check(lib.fft2_batched(nx, ny, batch, precision, _dev(inp, "in", n), _dev(out, "out", n),
+                            _stream(stream)))
 
 
 def accumulate_power(n_pol: int, nx: int, ny: int, n_chan: int, nt: int, field, acc_sum,
                      acc_comp, finalize_n_time: int = 0, image=None, stream=None):
     lib = load()
-    _check(lib.accumulate_power(n_pol, nx, ny, n_chan, nt, _dptr(field), _dptr(acc_sum),
-                                _dptr(acc_comp), finalize_n_time, _dptr(image), _stream(stream)))
+    plane = max(n_chan, 0) * n_pol * n_pol * nx * ny * 8
+    _check(lib.accumulate_power(n_pol, nx, ny, n_chan, nt,
+                                _dev(field, "field", max(n_chan, 0) * max(nt, 0) * n_pol * nx * ny * 8),
+                                _dev(acc_sum, "acc_sum", plane), _dev(acc_comp, "acc_comp", plane),
+                                finalize_n_time, _dev(image, "image", plane), _stream(stream)))
 
 
 def image_to_visibilities(n_pol: int, nx: int, ny: int, n_chan: int, image, vis, stream=None):
     """FFT-correlator output: the inverse transform of each product image
     (image, vis: device cf32 [n_chan][n_pol^2][ny][nx]; image is vis allowed)."""
     lib = load()
-    _check(lib.image_to_visibilities(n_pol, nx, ny, n_chan, _dptr(image), _dptr(vis),
-                                     _stream(stream)))
+    n = max(n_chan, 0) * n_pol * n_pol * nx * ny * 8
+    _check(lib.image_to_visibilities(n_pol, nx, ny, n_chan, _dev(image, "image", n),
+                                     _dev(vis, "vis", n), _stream(stream)))
 
 
 def combine_incoherent(n_pol: int, nx: int, ny: int, n_chan: int, images, out, weights=None,
@@ -246,9 +301,13 @@ def combine_incoherent(n_pol: int, nx: int, ny: int, n_chan: int, images, out, w
     device tensors cf32 [n_chan][n_pol^2][ny][nx]; weights: device float
     [n_stations][n_pol^2][ny][nx] or None for equal weights)."""
     lib = load()
-    ptrs = (ctypes.c_void_p * max(1, len(images)))(*[_dptr(t) for t in images])
+    plane = n_pol * n_pol * nx * ny
+    n = max(n_chan, 0) * plane * 8
+    ptrs = (ctypes.c_void_p * max(1, len(images)))(
+        *[_dev(t, f"images[{m}]", n) for m, t in enumerate(images)])
     _check(lib.combine_incoherent(n_pol, nx, ny, n_chan, len(images), ptrs if images else None,
-                                  _dptr(weights), _dptr(out), _stream(stream)))
+                                  _dev(weights, "weights", len(images) * plane * 4, _F32),
+                                  _dev(out, "out", n), _stream(stream)))
 
 
 def grid_voltages_pol(common: Common, station: Station, kernels, t0: int, nt: int, grid,
@@ -257,17 +316,24 @@ def grid_voltages_pol(common: Common, station: Station, kernels, t0: int, nt: in
     [n_chan][n_elem][n_pol][n_pol][K][K]) into grid [n_chan][nt][n_pol][ny][nx]."""
     lib = load()
     c, keep1 = common.to_c()
-    s, keep2 = station.to_c()
-    _check(lib.grid_voltages_pol(ctypes.byref(c), ctypes.byref(s), _dptr(kernels), t0, nt,
-                                 _dptr(grid), _stream(stream)))
+    s, keep2 = station.to_c(volts=_volts(common, station))
+    n_chan = len(np.atleast_1d(common.wavelength_m))
+    n_elem = np.asarray(station.pos_m).shape[0]
+    kn = n_chan * n_elem * common.n_pol ** 2 * station.support ** 2 * 8
+    g = _dev(grid, "grid", n_chan * max(nt, 0) * common.n_pol * station.ny * station.nx * 8)
+    _check(lib.grid_voltages_pol(ctypes.byref(c), ctypes.byref(s), _dev(kernels, "kernels", kn),
+                                 t0, nt, g, _stream(stream)))
 
 
 def image_cadence_pol(common: Common, station: Station, kernels, stream=None):
     """The cadence of one station with full polarimetric kernels into station.image."""
     lib = load()
     c, keep1 = common.to_c()
-    s, keep2 = station.to_c()
-    _check(lib.image_cadence_pol(ctypes.byref(c), ctypes.byref(s), _dptr(kernels),
+    s, keep2 = station.to_c(volts=_volts(common, station), image=_image(common, station))
+    n_chan = len(np.atleast_1d(common.wavelength_m))
+    n_elem = np.asarray(station.pos_m).shape[0]
+    kn = n_chan * n_elem * common.n_pol ** 2 * station.support ** 2 * 8
+    _check(lib.image_cadence_pol(ctypes.byref(c), ctypes.byref(s), _dev(kernels, "kernels", kn),
                                  _stream(stream)))
 
 
@@ -276,8 +342,11 @@ def xfft_correlate(common: Common, station: Station, vis, stream=None):
     [n_chan][n_elem][n_pol][n_elem][n_pol])."""
     lib = load()
     c, keep1 = common.to_c()
-    s, keep2 = station.to_c()
-    _check(lib.xfft_correlate(ctypes.byref(c), ctypes.byref(s), _dptr(vis), _stream(stream)))
+    s, keep2 = station.to_c(volts=_volts(common, station))
+    n_chan = len(np.atleast_1d(common.wavelength_m))
+    r = np.asarray(station.pos_m).shape[0] * common.n_pol
+    _check(lib.xfft_correlate(ctypes.byref(c), ctypes.byref(s), _dev(vis, "vis", n_chan * r * r * 8),
+                              _stream(stream)))
 
 
 def xfft_image(common: Common, station: Station, vis, gridded=None, stream=None):
@@ -286,9 +355,12 @@ def xfft_image(common: Common, station: Station, vis, gridded=None, stream=None)
     visibilities."""
     lib = load()
     c, keep1 = common.to_c()
-    s, keep2 = station.to_c()
-    _check(lib.xfft_image(ctypes.byref(c), ctypes.byref(s), _dptr(vis), _dptr(gridded),
-                          _stream(stream)))
+    s, keep2 = station.to_c(image=_image(common, station))
+    n_chan = len(np.atleast_1d(common.wavelength_m))
+    r = np.asarray(station.pos_m).shape[0] * common.n_pol
+    gn = n_chan * common.n_pol ** 2 * station.nx * station.ny * 8
+    _check(lib.xfft_image(ctypes.byref(c), ctypes.byref(s), _dev(vis, "vis", n_chan * r * r * 8),
+                          _dev(gridded, "gridded", gn), _stream(stream)))
 
 
 def array_cadence(common: Common, array: Station, beams, beam_nx: int, beam_ny: int, pixels,
@@ -299,9 +371,9 @@ def array_cadence(common: Common, array: Station, beams, beam_nx: int, beam_ny: 
     at the selected flat beam pixels."""
     lib = load()
     c, keep1 = common.to_c()
-    s, keep2 = array.to_c()
-    ptrs = (ctypes.c_void_p * max(1, len(beams)))(*[_dptr(t) for t in beams])
     pix = np.ascontiguousarray(pixels, dtype=np.int32)
+    s, keep2 = array.to_c(image=_image(common, array, planes=pix.size))
+    ptrs = _beam_ptrs(common, beams, beam_nx, beam_ny)
     _check(lib.array_cadence(ctypes.byref(c), ctypes.byref(s), ptrs if beams else None, beam_nx,
                              beam_ny, pix.size, pix.ctypes.data if pix.size else None,
                              _stream(stream)))
@@ -313,19 +385,32 @@ def array_xfft(common: Common, array: Station, beams, beam_nx: int, beam_ny: int
     array_cadence."""
     lib = load()
     c, keep1 = common.to_c()
-    s, keep2 = array.to_c()
-    ptrs = (ctypes.c_void_p * max(1, len(beams)))(*[_dptr(t) for t in beams])
     pix = np.ascontiguousarray(pixels, dtype=np.int32)
+    s, keep2 = array.to_c(image=_image(common, array, planes=pix.size))
+    ptrs = _beam_ptrs(common, beams, beam_nx, beam_ny)
     _check(lib.array_xfft(ctypes.byref(c), ctypes.byref(s), ptrs if beams else None, beam_nx,
                           beam_ny, pix.size, pix.ctypes.data if pix.size else None,
                           _stream(stream)))
 
 
-def _stations_c(stations):
+def _beam_ptrs(common: Common, beams, beam_nx: int, beam_ny: int):
+    """Checked addresses of the station fields [n_chan][n_time][n_pol][beam_ny][beam_nx]."""
+    n = len(np.atleast_1d(common.wavelength_m)) * common.n_time * common.n_pol * beam_nx * beam_ny * 8
+    return (ctypes.c_void_p * max(1, len(beams)))(
+        *[_dev(t, f"beams[{m}]", n) for m, t in enumerate(beams)])
+
+
+def _stations_c(stations, common: Common | None = None):
+    """The epic_station array of a call; with common given, each station's
+    voltages and image are checked against the shapes the call implies."""
     arr = (_Station * len(stations))()
     keep = []
     for i, st in enumerate(stations):
-        s, k = st.to_c()
+        if common is None:
+            s, k = st.to_c()
+        else:
+            s, k = st.to_c(volts=_volts(common, st, f"stations[{i}].volts"),
+                           image=_image(common, st, f"stations[{i}].image"))
         arr[i] = s
         keep.append(k)
     return arr, keep
@@ -342,7 +427,7 @@ def validate(common: Common, stations) -> None:
 def image_cadence(common: Common, stations, stream=None):
     lib = load()
     c, keep1 = common.to_c()
-    arr, keep = _stations_c(stations)
+    arr, keep = _stations_c(stations, common)
     _check(lib.image_cadence(ctypes.byref(c), arr, len(stations), _stream(stream)))
 
 
@@ -350,5 +435,5 @@ def autotune(common: Common, stations, stream=None):
     """Time the fused kernels' chunk lengths on these buffers and keep the best."""
     lib = load()
     c, keep1 = common.to_c()
-    arr, keep = _stations_c(stations)
+    arr, keep = _stations_c(stations, common)
     _check(lib.epic_autotune(ctypes.byref(c), arr, len(stations), _stream(stream)))

@@ -209,3 +209,82 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(epic._Common) == 40
     assert ctypes.sizeof(epic._Kernel) == 16
     assert ctypes.sizeof(epic._Station) == 56
+
+
+class _FakeDeviceTensor:
+    """Stands in for a GPU tensor on the host: the binding only looks at
+    is_cuda, dtype, contiguity, size and address."""
+
+    def __init__(self, shape, dtype="float32", contiguous=True, cuda=True):
+        import torch
+        self.shape = tuple(shape)
+        self.dtype = getattr(torch, dtype)
+        self._contig = contiguous
+        self.is_cuda = cuda
+        self.device = "cuda:0" if cuda else "cpu"
+        self._es = torch.empty((), dtype=self.dtype).element_size()
+
+    def is_contiguous(self):
+        return self._contig
+
+    def numel(self):
+        return int(np.prod(self.shape))
+
+    def element_size(self):
+        return self._es
+
+    def data_ptr(self):
+        return 0x7000
+
+
+def test_binding_checks_device_buffers_before_the_call():
+    n_chan, nt, n_pol, ny, nx = 2, 3, 2, 64, 64
+    good = (n_chan, nt, n_pol, ny, nx, 2)
+    # a correctly shaped buffer passes the checks (and then fails in the
+    # library only because no GPU is present: the fake address is never used)
+    common, station = _c2_like(n_chan=n_chan)
+    station.volts = _FakeDeviceTensor((n_chan, common.n_time, 256, 2, 2), "int8")
+    cases = {
+        "host tensor": _FakeDeviceTensor(good, cuda=False),
+        "wrong dtype": _FakeDeviceTensor(good, "float64"),
+        "not contiguous": _FakeDeviceTensor(good, contiguous=False),
+        "too small": _FakeDeviceTensor((n_chan, nt, n_pol, ny, nx - 1, 2)),
+        "too large": _FakeDeviceTensor((n_chan, nt + 1, n_pol, ny, nx, 2)),
+    }
+    for name, grid in cases.items():
+        with pytest.raises(ValueError):
+            epic.grid_voltages(common, station, 0, nt, grid, stream=0)
+    # complex64 of the same bytes is accepted by the checks
+    ok = _FakeDeviceTensor((n_chan, nt, n_pol, ny, nx), "complex64")
+    with pytest.raises(epic.EpicError):
+        epic.grid_voltages(common, station, 0, nt, ok, stream=0)
+
+
+def test_binding_checks_voltage_type_and_size():
+    common, station = _c2_like(n_chan=2)
+    station.image = _FakeDeviceTensor((2, 4, 64, 64, 2))
+    for v in (_FakeDeviceTensor((2, common.n_time, 256, 2, 2), "float32"),     # ci8 config
+              _FakeDeviceTensor((2, common.n_time, 255, 2, 2), "int8"),
+              _FakeDeviceTensor((2, common.n_time, 256, 2, 2), "int8", contiguous=False)):
+        station.volts = v
+        with pytest.raises(ValueError):
+            epic.image_cadence(common, [station], stream=0)
+    station.volts = _FakeDeviceTensor((2, common.n_time, 256, 2, 2), "int8")
+    station.image = _FakeDeviceTensor((2, 1, 64, 64, 2))                       # n_pol 2 needs 4 products
+    with pytest.raises(ValueError):
+        epic.image_cadence(common, [station], stream=0)
+
+
+def test_binding_checks_unfused_call_buffers():
+    n = (3, 64, 64, 2)
+    with pytest.raises(ValueError):
+        epic.fft2_batched(64, 64, 3, epic.FP32_FFT, _FakeDeviceTensor(n), _FakeDeviceTensor((2, 64, 64, 2)),
+                          stream=0)
+    shape = (2, 4, 32, 16, 2)
+    with pytest.raises(ValueError):
+        epic.accumulate_power(2, 16, 32, 2, 5, _FakeDeviceTensor((2, 5, 2, 32, 16, 2)),
+                              _FakeDeviceTensor(shape), _FakeDeviceTensor((2, 4, 32, 16)), 5,
+                              _FakeDeviceTensor(shape), stream=0)
+    with pytest.raises(ValueError):
+        epic.combine_incoherent(2, 16, 32, 2, [_FakeDeviceTensor(shape)] * 2, _FakeDeviceTensor(shape),
+                                _FakeDeviceTensor((2, 4, 32, 16), "float64"), stream=0)
