@@ -192,7 +192,7 @@ def roofline(cfg, kern, steps, prec, chunks, traffic_ok):
     scale = 1e9 if unit == "GB/s" else 1e12
     achieved = work / (avg_ms / 1e3) / scale
     prefix = {"fused_fft_cadence": "fft_", "fused_dft_cadence": "dft_"}.get(dom_name)
-    cls = sorted(v for k, v in chunks.items() if prefix and k.startswith(prefix))
+    cls = sorted(v for k, v in chunks.items() if prefix and k.startswith(prefix) and ":" not in k)
     chunk = cls[0] if cls and len(set(cls)) == 1 else None
     out.update({"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": unit,
                 "frac": round(achieved / peak, 4),
@@ -221,10 +221,12 @@ def time_precision(cfg, prec_name, common, stations, steps, warmup, autotune):
         epic.autotune(common, stations)
         log(f"{prec_name}: autotune done in {time.time() - t_tune:.1f} s")
         if os.path.exists(tune_file):
+            # "class variant chunk" lines
             for line in open(tune_file):
                 parts = line.split()
-                if len(parts) == 2:
-                    chunks[parts[0]] = int(parts[1])
+                if len(parts) == 3:
+                    chunks[parts[0]] = int(parts[2])
+                    chunks[parts[0] + ":variant"] = int(parts[1])
     for _ in range(warmup):
         epic.image_cadence(common, stations)
     torch.cuda.synchronize()
@@ -240,7 +242,7 @@ def time_precision(cfg, prec_name, common, stations, steps, warmup, autotune):
     torch.cuda.synchronize()
     epic.timing_enable(False)
     kern = epic.timing_report()
-    log(f"{prec_name}: {ms:.2f} ms/step; kernels {kern}")
+    log(f"{prec_name}: {ms:.2f} ms/step; tuned {chunks}; kernels {kern}")
     return ms, kern, chunks
 
 
@@ -441,8 +443,10 @@ def main():
         st0 = cfg.stations[s0]
         c0 = epic.Common(cfg.n_pol, cfg.wavelengths_m, W.GRID_SPACING_WL, cfg.n_time,
                          cfg.volt_type, cfg.precision)
+        img0 = torch.zeros((cfg.n_chan, cfg.n_pol * cfg.n_pol, st0.ny, st0.nx, 2),
+                           dtype=torch.float32, device=dev)
         station = epic.Station(st0.pos_m, st0.nx, st0.ny, st0.kernel_type, st0.support,
-                               st0.sigma_cells, volts=vdev[s0])
+                               st0.sigma_cells, volts=vdev[s0], image=img0)
         out["stages"] = stage_rooflines(cfg, c0, station, s0)
         if len(cfg.stations) == 1:
             out["stages"]["inter_station_epic"] = array_stage(cfg)

@@ -135,7 +135,9 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
     if (st != EPIC_OK) return st;
     float2 *acc_sum = static_cast<float2 *>(ws_acc);
     float2 *acc_comp = acc_sum + acc_bytes / 8;
-    EPIC_HIP_TRY(hipMemsetAsync(ws_acc, 0, 2 * acc_bytes, stream));
+    // a fill kernel, not a memset: the cadence may be captured into a graph
+    st = launch_zero(ws_acc, 2 * acc_bytes, stream);
+    if (st != EPIC_OK) return st;
     const StationDev sd = make_station_dev(s, p);
     float2 *field = static_cast<float2 *>(ws_field);
     // the transform's footprint mode reads only each plane's tile region

@@ -1,27 +1,35 @@
 // cadence.cpp -- the image_cadence driver.
 //
-// Stations of one call are sorted into kernel classes: the fused FP32 kernel
-// (square grids up to 64, one class per grid size), the fused split-precision
-// kernel (square grids up to 64, one class per grid size and footprint tile
-// count, split further if the LDS would overflow) and the FP32 path for
-// 128 x 128 grids.  Each of the first two runs as ONE launch over its work
-// items (station, channel, time chunk), ordered largest station first so the
-// longest items start first.  The 128 x 128 class runs per time block: a
-// gridding launch into footprint boxes, then the fused transform-and-square
-// launch, for each batch of (station, channel) pairs whose boxes fit the box
-// buffer.  Each fused station then gets its ordered, compensated chunk
-// reduction.  Stations outside every class take the composed path (grid ->
-// transform -> square and accumulate, in time chunks).
+// Stations of one call are sorted into kernel classes: the fused FP32 kernels
+// (square grids up to 64, one class per grid size, split where the LDS of
+// the class's largest station would not fit the fast kernel), the fused
+// split-precision kernel (square grids up to 64, per grid size and footprint
+// tile count, split where the LDS would overflow) and the FP32 path for
+// 128 x 128 grids.  The first two are persistent kernels: one launch per
+// class takes its (station, channel) items from a work queue (queue.hpp)
+// whose lists are balanced over the XCDs and ordered longest first, and each
+// item images its pair over the whole cadence, keeping FP64 running sums in
+// the caller's image buffer until it writes the mean products (accum.hpp).
+// The 128 x 128 class runs per time block: a gridding launch into footprint
+// boxes, then the fused transform-and-square launch, for each batch of
+// (station, channel) pairs whose boxes fit the box buffer.  Stations outside
+// every class take the composed path (grid -> transform -> square and
+// accumulate, in time chunks).
 //
-// The class tables, item lists and partial-sum buffers are built once per
-// distinct call (same geometry, buffers and stream) and kept; when every
-// station is fused the whole cadence is captured into a hipGraph on first use
-// and replayed afterwards.
+// The class tables, item lists and queue counters are built once per distinct
+// call (same geometry, buffers and stream) and kept.  The first call runs
+// eagerly (kernel attributes are set and every library buffer is allocated);
+// later calls replay the whole cadence, the queue reset included, from a
+// captured hipGraph.
 //
-// The time-chunk length of each class (16, 32, 64 or 128 samples) is a tile
-// parameter: epic_autotune times the candidates on the caller's data and keeps
+// Each class has tile parameters: the number of samples summed in FP32
+// before they go to the FP64 running sums (8 or 16; both keep the error of
+// the mean within 16 units in the last place of FP32) and, where the class
+// has more than one kernel shape, the shape (for the 64 x 64 FP32 class the
+// 1024-thread kernel with one pol per thread or the 512-thread kernel with
+// both).  epic_autotune times every candidate on the caller's data and keeps
 // the fastest, in memory and, if EPIC_TUNE_CACHE names a file, on disk
-// ("key chunk" lines).
+// ("key variant flush" lines).
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -41,6 +49,22 @@ StationDev make_station_dev(const epic_station *s, const PlanHandle &p);
 epic_status cadence_composed(const epic_common *c, const epic_station *s, const PlanHandle &p,
                              int device, hipStream_t stream, const float2 *pol_kernels = nullptr);
 
+int persistent_grid(const void *kernel, int block, size_t lds, int n_items)
+{
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop{};
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            n_cu = prop.multiProcessorCount;
+        if (n_cu <= 0) n_cu = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return std::max(1, std::min(n_items, per_cu * n_cu));
+}
+
 namespace {
 
 constexpr int kPathFft = 0, kPathDft = 1, kPathFft128 = 2;
@@ -52,32 +76,38 @@ size_t box_budget()
     const long mb = e ? std::atol(e) : 0;
     return mb > 0 ? static_cast<size_t>(mb) << 20 : size_t(2) << 30;
 }
-constexpr int kDefaultChunk = 32;
-// Chunk lengths the autotuner tries.  Each chunk is a plain FP32 sum (its
-// rounding error grows at most linearly, 128 * 2^-24 < 1e-5 relative), and
-// the chunks are then added with compensation.
-const int kChunkCandidates[] = {16, 32, 64, 128};
+// Samples summed in FP32 before the FP64 running sums (the bound of the
+// plain block sum, (B - 1) units in the last place, is what limits the error
+// of the mean), and the time block of the 128 x 128 class (box buffer).
+constexpr int kDefaultFlush = 16;
+const int kFlushCandidates[] = {8, 16};
+constexpr int kBlock128 = 64;
+
+struct Tile {
+    int variant = 0;
+    int flush = kDefaultFlush;
+};
 
 struct Group {
     int path = kPathFft;
     int n = 0;
     int tiles = 0;
-    int chunk = kDefaultChunk;
+    Tile tile;
     std::vector<int> members;     // station indices of the call
     FusedBatch batch;             // device pointers set after upload
     std::vector<std::pair<int, int>> pair_batches;   // 128 x 128 class: (first item, count)
     std::vector<StationDev> host_sds;
     std::vector<int4> host_items;
+    int queue_slot = 0;           // first of this group's kXcds counters
 };
 
 struct CadencePlan {
     std::vector<Group> groups;
     std::vector<int> composed;
-    std::vector<int64_t> part_off;   // per station, floats (fused stations)
-    std::vector<int> chunk;          // per station chunk length (fused stations)
     void *dev_tables = nullptr;
-    float *partials = nullptr;
     float2 *boxes = nullptr;         // footprint boxes of one batch (128 x 128 class)
+    int *counters = nullptr;         // queue counters, kXcds per persistent group
+    int n_counters = 0;
     const float2 *twiddles[257] = {};
     const uint32_t *rows[257] = {};
     hipGraph_t graph = nullptr;
@@ -88,18 +118,30 @@ struct CadencePlan {
 
 std::mutex g_mu;
 std::map<std::string, CadencePlan *> g_plans;
-std::map<std::string, int> g_tuned;   // class key -> chunk
+std::map<std::string, Tile> g_tuned;   // class key -> tile
 int g_tune_generation = 0;
 bool g_tune_loaded = false;
 
 int tiles_for_side(int side, int n) { return std::max((side + 15) / 16, n == 64 ? 2 : 1); }
 
-std::string class_key(int path, int n, int tiles, const epic_common *c)
+std::string class_key(const Group &g, const epic_common *c)
 {
     std::ostringstream o;
-    o << (path == kPathFft ? "fft" : path == kPathDft ? "dft" : "fft128") << "_n" << n << "_t" << tiles << "_p" << c->n_pol << "_v"
-      << c->volt_type << "_q" << c->precision;
+    o << (g.path == kPathFft ? "fft" : g.path == kPathDft ? "dft" : "fft128") << "_n" << g.n << "_t"
+      << g.tiles << "_p" << c->n_pol << "_v" << c->volt_type << "_q" << c->precision;
     return o.str();
+}
+
+// Kernel shapes a class can run (variant numbers the launcher understands).
+std::vector<int> variants_of(const Group &g, const epic_common *c)
+{
+    if (g.path == kPathFft && g.n == 64 && c->n_pol == 2) {
+        std::vector<int> v;
+        for (int k = 0; k < 2; ++k)
+            if (fft64_fits(g.batch, c->n_pol, c->volt_type, k)) v.push_back(k);
+        if (!v.empty()) return v;
+    }
+    return {0};
 }
 
 void load_tune_file()
@@ -109,10 +151,16 @@ void load_tune_file()
     const char *path = std::getenv("EPIC_TUNE_CACHE");
     if (!path) return;
     std::ifstream f(path);
-    std::string key;
-    int chunk = 0;
-    while (f >> key >> chunk)
-        if (chunk == 16 || chunk == 32 || chunk == 64 || chunk == 128) g_tuned[key] = chunk;
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string key;
+        Tile t;
+        if (!(in >> key >> t.variant >> t.flush)) continue;
+        if (std::find(std::begin(kFlushCandidates), std::end(kFlushCandidates), t.flush) !=
+                std::end(kFlushCandidates) && t.variant >= 0 && t.variant < 4)
+            g_tuned[key] = t;
+    }
 }
 
 void save_tune_file()
@@ -120,13 +168,7 @@ void save_tune_file()
     const char *path = std::getenv("EPIC_TUNE_CACHE");
     if (!path) return;
     std::ofstream f(path, std::ios::trunc);
-    for (auto &kv : g_tuned) f << kv.first << " " << kv.second << "\n";
-}
-
-int tuned_chunk(const std::string &key)
-{
-    auto it = g_tuned.find(key);
-    return it == g_tuned.end() ? kDefaultChunk : it->second;
+    for (auto &kv : g_tuned) f << kv.first << " " << kv.second.variant << " " << kv.second.flush << "\n";
 }
 
 void free_plan(CadencePlan *p)
@@ -134,13 +176,12 @@ void free_plan(CadencePlan *p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->dev_tables) (void)hipFree(p->dev_tables);
-    if (p->partials) (void)hipFree(p->partials);
     if (p->boxes) (void)hipFree(p->boxes);
     delete p;
 }
 
 std::string call_key(const epic_common *c, const epic_station *st, int n, const PlanHandle *plans,
-                     int device, hipStream_t stream, const std::vector<int> &chunks_override)
+                     int device, hipStream_t stream, const std::vector<Tile> &tiles_override)
 {
     std::string k;
     auto put = [&k](const void *p, size_t b) { k.append(static_cast<const char *>(p), b); };
@@ -157,8 +198,46 @@ std::string call_key(const epic_common *c, const epic_station *st, int n, const 
         put(&st[i].volts, sizeof st[i].volts);
         put(&st[i].image, sizeof st[i].image);
     }
-    for (int v : chunks_override) put(&v, sizeof v);
+    for (const Tile &t : tiles_override) {
+        put(&t.variant, sizeof t.variant);
+        put(&t.flush, sizeof t.flush);
+    }
     return k;
+}
+
+// The batch maxima of one station.
+FusedBatch station_batch(const StationDev &sd, int n)
+{
+    FusedBatch b;
+    b.n = n;
+    b.max_elem = sd.n_elem;
+    b.max_cells = sd.max_cells;
+    b.max_cell_taps = sd.max_cell_taps;
+    b.max_ktaps = sd.ktaps;
+    b.max_side = std::max(sd.max_bw, sd.max_bh);
+    return b;
+}
+
+FusedBatch merged(const FusedBatch &a, const FusedBatch &b)
+{
+    FusedBatch m = a;
+    m.max_elem = std::max(a.max_elem, b.max_elem);
+    m.max_cells = std::max(a.max_cells, b.max_cells);
+    m.max_cell_taps = std::max(a.max_cell_taps, b.max_cell_taps);
+    m.max_ktaps = std::max(a.max_ktaps, b.max_ktaps);
+    m.max_side = std::max(a.max_side, b.max_side);
+    return m;
+}
+
+// Whether one launch of the group's kernel covers stations with these
+// combined maxima (the LDS and register layouts are sized by the maxima).
+bool group_fits(int path, const FusedBatch &b, int max_bw, int max_bh, const epic_common *c)
+{
+    if (path == kPathDft) return fused_dft_supported(b, c->n_pol, c->volt_type);
+    if (path == kPathFft128)
+        return fused128_supported(128, max_bw, max_bh, b.max_elem, c->n_pol, c->volt_type, b.max_ktaps,
+                                  b.max_cell_taps);
+    return true;   // the generic FP32 kernel takes any batch; see below for 64
 }
 
 // Sort the call's stations into groups (no device work).
@@ -177,13 +256,7 @@ void classify(const epic_common *c, const epic_station *st, int n, const PlanHan
         } else if (square && c->precision == EPIC_FP32_FFT) {
             path = kPathFft;
         } else if (square) {
-            FusedBatch one;
-            one.n = st[i].nx;
-            one.max_elem = sd.n_elem;
-            one.max_cells = sd.max_cells;
-            one.max_cell_taps = sd.max_cell_taps;
-            one.max_ktaps = sd.ktaps;
-            one.max_side = std::max(sd.max_bw, sd.max_bh);
+            const FusedBatch one = station_batch(sd, st[i].nx);
             const int64_t vbytes = static_cast<int64_t>(sd.n_elem) * c->n_pol * (c->volt_type == EPIC_CI8 ? 2 : 8);
             if (vbytes % 4 == 0 && fused_dft_supported(one, c->n_pol, c->volt_type)) {
                 path = kPathDft;
@@ -194,22 +267,23 @@ void classify(const epic_common *c, const epic_station *st, int n, const PlanHan
             composed.push_back(i);
             continue;
         }
-        const std::string key = class_key(path, st[i].nx, tiles, c);
+        Group probe;
+        probe.path = path;
+        probe.n = st[i].nx;
+        probe.tiles = tiles;
+        const std::string key = class_key(probe, c);
         auto it = index.find(key);
         if (it == index.end()) {
-            Group g;
-            g.path = path;
-            g.n = st[i].nx;
-            g.tiles = tiles;
-            g.chunk = tuned_chunk(key);
             index[key] = static_cast<int>(groups.size());
-            groups.push_back(g);
+            groups.push_back(probe);
             it = index.find(key);
         }
         groups[it->second].members.push_back(i);
     }
-    // largest stations first inside each group; split split-precision groups
-    // whose combined maxima would overflow the LDS
+    // largest stations first inside each group; split groups whose combined
+    // maxima would overflow the kernel's LDS (or, for the 64 x 64 FP32 class,
+    // push the fast kernels' LDS over the limit: the stations that break it
+    // start a group of their own)
     std::vector<Group> out;
     for (auto &g : groups) {
         std::sort(g.members.begin(), g.members.end(),
@@ -218,71 +292,102 @@ void classify(const epic_common *c, const epic_station *st, int n, const PlanHan
         cur.members.clear();
         FusedBatch acc;
         acc.n = g.n;
+        int bw = 0, bh = 0;
         for (int i : g.members) {
             const StationDev sd = make_station_dev(&st[i], plans[i]);
-            FusedBatch next = acc;
-            next.max_elem = std::max(next.max_elem, sd.n_elem);
-            next.max_cells = std::max(next.max_cells, sd.max_cells);
-            next.max_cell_taps = std::max(next.max_cell_taps, sd.max_cell_taps);
-            next.max_ktaps = std::max(next.max_ktaps, sd.ktaps);
-            next.max_side = std::max(next.max_side, std::max(sd.max_bw, sd.max_bh));
-            const bool fits = g.path != kPathDft || fused_dft_supported(next, c->n_pol, c->volt_type);
+            const FusedBatch one = station_batch(sd, g.n);
+            const FusedBatch next = cur.members.empty() ? one : merged(acc, one);
+            const int nbw = std::max(bw, sd.max_bw), nbh = std::max(bh, sd.max_bh);
+            bool fits = group_fits(g.path, next, nbw, nbh, c);
+            if (g.path == kPathFft && g.n == 64 && !cur.members.empty()) {
+                // a group either fits the fastest kernel (the two-pol one for
+                // two pols) or runs the next one that does
+                const int v0 = c->n_pol == 2 ? 0 : 1;
+                const bool f_acc = fft64_fits(acc, c->n_pol, c->volt_type, v0);
+                const bool f_one = fft64_fits(one, c->n_pol, c->volt_type, v0);
+                fits = f_acc ? fft64_fits(next, c->n_pol, c->volt_type, v0) : !f_one;
+            }
             if (!fits && !cur.members.empty()) {
+                cur.batch = acc;
                 out.push_back(cur);
                 cur.members.clear();
-                next = FusedBatch();
-                next.n = g.n;
-                next.max_elem = sd.n_elem;
-                next.max_cells = sd.max_cells;
-                next.max_cell_taps = sd.max_cell_taps;
-                next.max_ktaps = sd.ktaps;
-                next.max_side = std::max(sd.max_bw, sd.max_bh);
+                acc = one;
+                bw = sd.max_bw;
+                bh = sd.max_bh;
+            } else {
+                acc = next;
+                bw = nbw;
+                bh = nbh;
             }
             cur.members.push_back(i);
-            acc = next;
         }
         cur.batch = acc;
         out.push_back(cur);
     }
     groups.swap(out);
+    for (Group &g : groups) {
+        auto it = g_tuned.find(class_key(g, c));
+        g.tile = it == g_tuned.end() ? Tile{} : it->second;
+        const std::vector<int> vs = variants_of(g, c);
+        if (std::find(vs.begin(), vs.end(), g.tile.variant) == vs.end()) g.tile.variant = 0;
+    }
+}
+
+// Relative cost of an item of `nt` samples of one station (for ordering).
+double item_cost(const StationDev &sd, int n_pol, int nt)
+{
+    const double npix = static_cast<double>(sd.nx) * sd.ny;
+    return nt * (npix * sd.log2n * 2.0 * n_pol + 4.0 * sd.n_elem * sd.ktaps * n_pol);
+}
+
+// The persistent group's (station, channel) items in kXcds lists: longest
+// first onto the least loaded list, and each list ordered longest first.
+void build_queue_lists(Group &g, int n_chan, int n_time, int n_pol)
+{
+    struct Item {
+        double cost;
+        int4 it;
+    };
+    std::vector<Item> all;
+    for (size_t k = 0; k < g.host_sds.size(); ++k)
+        for (int ch = 0; ch < n_chan; ++ch)
+            all.push_back({item_cost(g.host_sds[k], n_pol, n_time), make_int4(static_cast<int>(k), ch, 0, 0)});
+    std::stable_sort(all.begin(), all.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+    double load[kXcds] = {};
+    std::vector<int4> lists[kXcds];
+    for (const Item &i : all) {
+        const int x = static_cast<int>(std::min_element(load, load + kXcds) - load);
+        load[x] += i.cost;
+        lists[x].push_back(i.it);
+    }
+    g.host_items.clear();
+    for (int x = 0; x < kXcds; ++x) {
+        g.batch.q.start[x] = static_cast<int>(g.host_items.size());
+        g.host_items.insert(g.host_items.end(), lists[x].begin(), lists[x].end());
+    }
+    g.batch.q.start[kXcds] = static_cast<int>(g.host_items.size());
 }
 
 epic_status build_plan(const epic_common *c, const epic_station *st, int n, const PlanHandle *plans,
-                       int device, const std::vector<int> &chunks_override, CadencePlan *p)
+                       int device, const std::vector<Tile> &tiles_override, CadencePlan *p)
 {
     classify(c, st, n, plans, p->groups, p->composed);
-    p->part_off.assign(n, -1);
-    p->chunk.assign(n, 0);
-    const int nq = c->n_pol == 2 ? 4 : 1;
-    int64_t part = 0;
     size_t n_sds = 0, n_items = 0, box_floats = 0;
+    int n_counters = 0;
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         Group &g = p->groups[gi];
-        if (gi < chunks_override.size() && chunks_override[gi] > 0) g.chunk = chunks_override[gi];
-        const int n_chunks = (c->n_time + g.chunk - 1) / g.chunk;
-        for (size_t k = 0; k < g.members.size(); ++k) {
-            const int i = g.members[k];
-            StationDev sd = make_station_dev(&st[i], plans[i]);
-            sd.part_off = part;
-            p->part_off[i] = part;
-            p->chunk[i] = g.chunk;
-            part += static_cast<int64_t>(c->n_chan) * n_chunks * nq * sd.nx * sd.ny;
-            g.host_sds.push_back(sd);
-            if (g.path == kPathFft128) {
-                for (int ch = 0; ch < c->n_chan; ++ch) g.host_items.push_back(make_int4(static_cast<int>(k), ch, 0, 0));
-            } else {
-                for (int ch = 0; ch < c->n_chan; ++ch)
-                    for (int ck = 0; ck < n_chunks; ++ck)
-                        g.host_items.push_back(make_int4(static_cast<int>(k), ch, ck, 0));
-            }
-        }
-        g.batch.n_items = static_cast<int>(g.host_items.size());
+        if (gi < tiles_override.size() && tiles_override[gi].flush > 0) g.tile = tiles_override[gi];
+        g.batch.variant = g.tile.variant;
+        for (int i : g.members) g.host_sds.push_back(make_station_dev(&st[i], plans[i]));
         if (g.path == kPathFft128) {
+            for (size_t k = 0; k < g.host_sds.size(); ++k)
+                for (int ch = 0; ch < c->n_chan; ++ch) g.host_items.push_back(make_int4(static_cast<int>(k), ch, 0, 0));
             // batches of pairs whose boxes for one time block fit the budget;
             // box offsets restart at 0 in every batch (one buffer serves all)
+            const int block = std::min(kBlock128, c->n_time);
             size_t pair_floats = 0;
             for (const StationDev &sd : g.host_sds)
-                pair_floats = std::max(pair_floats, static_cast<size_t>(g.chunk) * c->n_pol * sd.max_bw * sd.max_bh);
+                pair_floats = std::max(pair_floats, static_cast<size_t>(block) * c->n_pol * sd.max_bw * sd.max_bh);
             const int n_pairs = static_cast<int>(g.host_items.size());
             int per = static_cast<int>(std::max<size_t>(1, box_budget() / (sizeof(float2) * pair_floats)));
             if (per > 256 && per < n_pairs) per = per / 256 * 256;   // whole waves of work-groups
@@ -294,7 +399,12 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
                 g.pair_batches.emplace_back(first, cnt);
             }
             box_floats = std::max(box_floats, static_cast<size_t>(per) * pair_floats);
+        } else {
+            build_queue_lists(g, c->n_chan, c->n_time, c->n_pol);
+            g.queue_slot = n_counters;
+            n_counters += kXcds;
         }
+        g.batch.n_items = static_cast<int>(g.host_items.size());
         n_sds += g.host_sds.size();
         n_items += g.host_items.size();
         if (g.path != kPathDft && !p->twiddles[g.n]) {
@@ -307,18 +417,21 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
         }
     }
     if (p->groups.empty()) return EPIC_OK;
-    const size_t sds_bytes = (sizeof(StationDev) * n_sds + 255) & ~static_cast<size_t>(255);
-    hipError_t e = hipMalloc(&p->dev_tables, sds_bytes + sizeof(int4) * n_items);
+    auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+    const size_t b_sds = up(sizeof(StationDev) * n_sds);
+    const size_t b_items = up(sizeof(int4) * n_items);
+    const size_t b_cnt = up(sizeof(int) * std::max(1, n_counters));
+    hipError_t e = hipMalloc(&p->dev_tables, b_sds + b_items + b_cnt);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc (cadence tables)");
-    e = hipMalloc(reinterpret_cast<void **>(&p->partials), sizeof(float) * std::max<int64_t>(part, 1));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc (chunk partial sums)");
     if (box_floats) {
         e = hipMalloc(reinterpret_cast<void **>(&p->boxes), sizeof(float2) * box_floats);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc (footprint boxes)");
     }
     char *base = static_cast<char *>(p->dev_tables);
     StationDev *dsds = reinterpret_cast<StationDev *>(base);
-    int4 *ditems = reinterpret_cast<int4 *>(base + sds_bytes);
+    int4 *ditems = reinterpret_cast<int4 *>(base + b_sds);
+    p->counters = reinterpret_cast<int *>(base + b_sds + b_items);
+    p->n_counters = n_counters;
     for (auto &g : p->groups) {
         EPIC_HIP_TRY(hipMemcpy(dsds, g.host_sds.data(), sizeof(StationDev) * g.host_sds.size(),
                                hipMemcpyHostToDevice));
@@ -326,6 +439,8 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
                                hipMemcpyHostToDevice));
         g.batch.sds = dsds;
         g.batch.items = ditems;
+        g.batch.q.items = ditems;
+        g.batch.q.counters = p->counters + g.queue_slot;
         dsds += g.host_sds.size();
         ditems += g.host_items.size();
         g.host_items.clear();
@@ -336,45 +451,45 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
 
 epic_status launch_group(const epic_common *c, const CadencePlan *p, const Group &g, hipStream_t stream)
 {
+    const int flush = g.tile.flush;
     if (g.path == kPathFft)
-        return launch_fused_fft_partials(g.batch, c->n_pol, c->n_time, c->volt_type, g.chunk,
-                                         p->partials, p->twiddles[g.n], stream);
+        return launch_fused_fft(g.batch, c->n_pol, c->n_time, c->volt_type, flush, p->twiddles[g.n], stream);
     if (g.path == kPathFft128) {
-        const int n_blocks = (c->n_time + g.chunk - 1) / g.chunk;
+        const int block = std::min(kBlock128, c->n_time);
+        const int n_blocks = (c->n_time + block - 1) / block;
         for (int blk = 0; blk < n_blocks; ++blk)
             for (const auto &pb : g.pair_batches) {
                 FusedBatch sub = g.batch;
                 sub.items = g.batch.items + pb.first;
                 sub.n_items = pb.second;
-                epic_status s = launch_grid_box(sub, c->n_pol, c->n_time, c->volt_type, g.chunk, blk,
+                epic_status s = launch_grid_box(sub, c->n_pol, c->n_time, c->volt_type, block, blk,
                                                 p->boxes, stream);
                 if (s != EPIC_OK) return s;
-                s = launch_fused_fft128_partials(sub, c->n_pol, c->n_time, g.chunk, blk, p->boxes,
-                                                 p->partials, p->twiddles[g.n], stream);
+                s = launch_fused_fft128(sub, c->n_pol, c->n_time, block, blk, flush, p->boxes,
+                                        p->twiddles[g.n], stream);
                 if (s != EPIC_OK) return s;
             }
         return EPIC_OK;
     }
-    return launch_fused_dft_partials(g.batch, c->n_pol, c->n_time, c->volt_type, c->precision,
-                                     g.chunk, p->partials, p->rows[g.n], stream);
+    return launch_fused_dft(g.batch, c->n_pol, c->n_time, c->volt_type, c->precision, flush,
+                            p->rows[g.n], stream);
 }
 
-epic_status enqueue_fused(const epic_common *c, const epic_station *st, const CadencePlan *p,
-                          hipStream_t stream)
+// The whole cadence: queue reset, the class kernels (which write the fused
+// stations' images), then the composed stations.
+epic_status enqueue_all(const epic_common *c, const epic_station *st, const PlanHandle *plans,
+                        const CadencePlan *p, int device, hipStream_t stream)
 {
+    epic_status s = launch_queue_reset(p->counters, p->n_counters, stream);
+    if (s != EPIC_OK) return s;
     for (const Group &g : p->groups) {
-        epic_status s = launch_group(c, p, g, stream);
+        s = launch_group(c, p, g, stream);
         if (s != EPIC_OK) return s;
     }
-    const float inv = static_cast<float>(1.0 / static_cast<double>(c->n_time));
-    for (const Group &g : p->groups)
-        for (int i : g.members) {
-            const int n_chunks = (c->n_time + p->chunk[i] - 1) / p->chunk[i];
-            epic_status s = launch_reduce_partials(c->n_pol, st[i].nx * st[i].ny, c->n_chan, n_chunks,
-                                                   p->partials + p->part_off[i], inv,
-                                                   static_cast<float2 *>(st[i].image), stream);
-            if (s != EPIC_OK) return s;
-        }
+    for (int i : p->composed) {
+        s = cadence_composed(c, &st[i], plans[i], device, stream);
+        if (s != EPIC_OK) return s;
+    }
     return EPIC_OK;
 }
 
@@ -385,10 +500,10 @@ bool graphs_enabled()
 }
 
 epic_status get_or_build(const epic_common *c, const epic_station *st, int n, const PlanHandle *plans,
-                         int device, hipStream_t stream, const std::vector<int> &chunks_override,
+                         int device, hipStream_t stream, const std::vector<Tile> &tiles_override,
                          CadencePlan **out)
 {
-    const std::string key = call_key(c, st, n, plans, device, stream, chunks_override);
+    const std::string key = call_key(c, st, n, plans, device, stream, tiles_override);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         *out = it->second;
@@ -401,7 +516,7 @@ epic_status get_or_build(const epic_common *c, const epic_station *st, int n, co
         g_plans.clear();
     }
     CadencePlan *p = new CadencePlan();
-    epic_status s = build_plan(c, st, n, plans, device, chunks_override, p);
+    epic_status s = build_plan(c, st, n, plans, device, tiles_override, p);
     if (s != EPIC_OK) {
         free_plan(p);
         return s;
@@ -409,6 +524,16 @@ epic_status get_or_build(const epic_common *c, const epic_station *st, int n, co
     g_plans[key] = p;
     *out = p;
     return EPIC_OK;
+}
+
+void drop_plan(CadencePlan *p)
+{
+    for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
+        if (it->second == p) {
+            free_plan(p);
+            g_plans.erase(it);
+            return;
+        }
 }
 
 }  // namespace
@@ -421,14 +546,13 @@ epic_status run_cadence(const epic_common *c, const epic_station *st, int n, con
     CadencePlan *p = nullptr;
     epic_status s = get_or_build(c, st, n, plans, device, stream, {}, &p);
     if (s != EPIC_OK) return s;
-    const bool all_fused = p->composed.empty() && !p->groups.empty();
-    // first call eager (sets kernel attributes, checks launches); afterwards a
-    // captured graph when every station is fused
-    if (all_fused && graphs_enabled() && !p->graph_failed && p->runs > 0) {
+    // first call eager (sets kernel attributes, allocates the composed path's
+    // workspaces, checks launches); afterwards the captured graph
+    if (graphs_enabled() && !p->graph_failed && p->runs > 0) {
         if (!p->exec) {
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed);
-            epic_status es = e == hipSuccess ? enqueue_fused(c, st, p, stream) : EPIC_ERR_DEVICE;
+            epic_status es = e == hipSuccess ? enqueue_all(c, st, plans, p, device, stream) : EPIC_ERR_DEVICE;
             hipError_t e2 = hipStreamEndCapture(stream, &graph);
             hipGraphExec_t exec = nullptr;
             if (e == hipSuccess && es == EPIC_OK && e2 == hipSuccess && graph &&
@@ -448,13 +572,7 @@ epic_status run_cadence(const epic_common *c, const epic_station *st, int n, con
         }
     }
     ++p->runs;
-    s = enqueue_fused(c, st, p, stream);
-    if (s != EPIC_OK) return s;
-    for (int i : p->composed) {
-        s = cadence_composed(c, &st[i], plans[i], device, stream);
-        if (s != EPIC_OK) return s;
-    }
-    return EPIC_OK;
+    return enqueue_all(c, st, plans, p, device, stream);
 }
 
 epic_status tune_cadence(const epic_common *c, const epic_station *st, int n,
@@ -462,54 +580,53 @@ epic_status tune_cadence(const epic_common *c, const epic_station *st, int n,
 {
     std::lock_guard<std::mutex> lock(g_mu);
     load_tune_file();
-    // the group layout does not depend on the chunk: classify once
+    // the group layout does not depend on the tiles: classify once
     std::vector<Group> groups;
     std::vector<int> composed;
     classify(c, st, n, plans, groups, composed);
-    std::vector<int> best(groups.size(), kDefaultChunk);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     EPIC_HIP_TRY(hipEventCreate(&e0));
     EPIC_HIP_TRY(hipEventCreate(&e1));
+    std::vector<Tile> best(groups.size());
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         float best_ms = 1e30f;
-        for (int chunk : kChunkCandidates) {
-            std::vector<int> over(groups.size(), 0);
-            over[gi] = chunk;
-            CadencePlan *p = nullptr;
-            epic_status s = get_or_build(c, st, n, plans, device, stream, over, &p);
-            if (s != EPIC_OK) return s;
-            // one untimed launch, then the better of two timed ones
-            s = launch_group(c, p, p->groups[gi], stream);
-            if (s != EPIC_OK) return s;
-            float ms = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
-                EPIC_HIP_TRY(hipEventRecord(e0, stream));
-                s = launch_group(c, p, p->groups[gi], stream);
+        for (int variant : variants_of(groups[gi], c))
+            for (int flush : kFlushCandidates) {
+                std::vector<Tile> over(groups.size(), Tile{0, 0});
+                over[gi] = Tile{variant, flush};
+                CadencePlan *p = nullptr;
+                epic_status s = get_or_build(c, st, n, plans, device, stream, over, &p);
                 if (s != EPIC_OK) return s;
-                EPIC_HIP_TRY(hipEventRecord(e1, stream));
-                EPIC_HIP_TRY(hipEventSynchronize(e1));
-                float t = 0.f;
-                EPIC_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-                ms = std::min(ms, t);
-            }
-            if (ms < best_ms) {
-                best_ms = ms;
-                best[gi] = chunk;
-            }
-            // trial plans can be large (chunk partial sums): free each at once
-            EPIC_HIP_TRY(hipStreamSynchronize(stream));
-            for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
-                if (it->second == p) {
-                    free_plan(p);
-                    g_plans.erase(it);
-                    break;
+                // one untimed launch, then the better of two timed ones
+                s = launch_queue_reset(p->counters, p->n_counters, stream);
+                if (s == EPIC_OK) s = launch_group(c, p, p->groups[gi], stream);
+                if (s != EPIC_OK) return s;
+                float ms = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    s = launch_queue_reset(p->counters, p->n_counters, stream);
+                    if (s != EPIC_OK) return s;
+                    EPIC_HIP_TRY(hipEventRecord(e0, stream));
+                    s = launch_group(c, p, p->groups[gi], stream);
+                    if (s != EPIC_OK) return s;
+                    EPIC_HIP_TRY(hipEventRecord(e1, stream));
+                    EPIC_HIP_TRY(hipEventSynchronize(e1));
+                    float t = 0.f;
+                    EPIC_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+                    ms = std::min(ms, t);
                 }
-        }
-        g_tuned[class_key(groups[gi].path, groups[gi].n, groups[gi].tiles, c)] = best[gi];
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best[gi] = Tile{variant, flush};
+                }
+                // free each trial plan at once
+                EPIC_HIP_TRY(hipStreamSynchronize(stream));
+                drop_plan(p);
+            }
+        g_tuned[class_key(groups[gi], c)] = best[gi];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // drop the trial plans; the next image_cadence builds with the tuned chunks
+    // drop the trial plans; the next image_cadence builds with the tuned tiles
     EPIC_HIP_TRY(hipStreamSynchronize(stream));
     for (auto &kv : g_plans) free_plan(kv.second);
     g_plans.clear();

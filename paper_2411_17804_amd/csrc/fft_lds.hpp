@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "lds_sync.hpp"
+
 namespace epic {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -162,7 +164,7 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const LineMap m, int 
             Dft<R>::run(v[i]);
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int b = threadIdx.x + i * BLOCK;
@@ -175,7 +177,7 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const LineMap m, int 
             for (int r = 0; r < R; ++r) dst[(d0 + r * NS) * m.elem_stride] = v[i][r];
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // Both passes of a length-N transform over the lines described by m.

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "epic.h"
+#include "queue.hpp"
 
 namespace epic {
 
@@ -61,11 +62,17 @@ struct StationDev {
     int64_t part_off;         // first float of this station's chunk partial sums
 };
 
-// A batch of fused work: items (station index, channel, time chunk, 0) over a
-// device table of stations, plus the class-wide maxima the LDS layout uses.
+// A batch of fused work: items (station index, channel, time chunk, band or
+// 0) over a device table of stations, plus the class-wide maxima the LDS
+// layout uses.  Persistent kernels take their items from the queue q with
+// `grid` work-groups; the 128 x 128 FP32 pair of kernels reads items[] by
+// work-group index.
 struct FusedBatch {
     const StationDev *sds = nullptr;   // device [n_stations]
     const int4 *items = nullptr;       // device [n_items]
+    ItemQueue q{};
+    int grid = 0;
+    int variant = 0;                   // tile choice of the class (autotuned)
     int n_items = 0;
     int max_elem = 0;                  // max n_elem over the batch's stations
     int max_cells = 0;                 // max footprint-box cells
@@ -158,13 +165,14 @@ epic_status get_dft_tables(int n, int precision, int device, const void **out);
 // DFT matrix rows [n][n] as packed (re, im) hi parts, then lo parts (k_dft.hip).
 epic_status get_dft_rows(int n, int precision, int device, const uint32_t **out);
 
-// Fused split-precision cadence for square grids n in {16, 32, 64} (partial sums
-// per (channel, time chunk), like launch_fused_fft_partials).
-epic_status launch_fused_dft_partials(const FusedBatch &b, int n_pol, int n_time, int volt_type,
-                                      int precision, int chunk, float *partials,
-                                      const uint32_t *dft_rows, hipStream_t stream);
+// Fused split-precision cadence for square grids n in {16, 32, 64}: one
+// work-group per (station, channel) item over the whole cadence, block sums of
+// `flush` samples added to FP64 running sums in the image buffer (accum.hpp),
+// which finally receives the mean products.
+epic_status launch_fused_dft(const FusedBatch &b, int n_pol, int n_time, int volt_type,
+                             int precision, int flush, const uint32_t *dft_rows, hipStream_t stream);
 
-// Whether launch_fused_dft_partials covers a batch with these maxima.
+// Whether launch_fused_dft covers a batch with these maxima.
 bool fused_dft_supported(const FusedBatch &b, int n_pol, int volt_type);
 
 // Library-owned device workspace, per (device, stream, slot); grows on demand.
@@ -245,26 +253,43 @@ epic_status launch_dft2_split(int nx, int ny, int64_t batch, int precision, cons
                               const ChanPlan *chan = nullptr, int items_per_chan = 1,
                               int max_bw = 0, int max_bh = 0);
 
-// Fused FP32 cadence for square grids n in {16, 32, 64}: partial sums of the
-// four real product components per (station, channel, time chunk) item.
-epic_status launch_fused_fft_partials(const FusedBatch &b, int n_pol, int n_time, int volt_type,
-                                      int chunk, float *partials, const float2 *twiddles,
-                                      hipStream_t stream);
+// Work-groups of a persistent launch of `kernel` (block threads, lds bytes of
+// dynamic LDS): as many as the GPU holds at once, at most n_items.
+int persistent_grid(const void *kernel, int block, size_t lds, int n_items);
+
+// Queue counters of a cadence: k_queue_reset clears n ints before the class
+// kernels of every cadence run (a kernel, so that a captured graph holds no
+// memset node).
+epic_status launch_queue_reset(int *counters, int n, hipStream_t stream);
+// Zero fill of n bytes (multiple of 4) by a kernel, for the same reason.
+epic_status launch_zero(void *p, size_t bytes, hipStream_t stream);
+
+// Whether a register-resident 64 x 64 FP32 kernel covers a batch: variant 0
+// the two-pol kernel (n_pol 2), variant 1 the one with both pols per thread
+// (any n_pol); the generic kernel runs where neither does.
+bool fft64_fits(const FusedBatch &b, int n_pol, int volt_type, int variant);
+
+// Fused FP32 cadence for square grids n in {16, 32, 64}, items and sums as
+// launch_fused_dft.
+epic_status launch_fused_fft(const FusedBatch &b, int n_pol, int n_time, int volt_type, int flush,
+                             const float2 *twiddles, hipStream_t stream);
 // Whether the fused FP32 kernels cover a batch with these maxima.
 bool fused_fft_supported(const FusedBatch &b, int n_pol, int volt_type);
 
-// The FP32 cadence for 128 x 128 grids (k_fused128.hip), per time block:
-// launch_grid_box grids the block's samples of every (station, channel) pair
-// of the batch (items: station index, channel, 0, box offset in float2) into
-// footprint boxes [t][pol][max_bh][max_bw]; launch_fused_fft128_partials
-// transforms them and writes the block's partial sums (one item per pair).
+// The FP32 cadence for 128 x 128 grids (k_fused128.hip), per time block of
+// `chunk` samples: launch_grid_box grids the block's samples of every
+// (station, channel) pair of the batch (items: station index, channel, 0, box
+// offset in float2) into footprint boxes [t][pol][max_bh][max_bw];
+// launch_fused_fft128 transforms them and adds block sums of `flush` samples
+// to the pair's FP64 running sums in the image buffer (one item per pair; the
+// last time block writes the mean products).
 bool fused128_supported(int n, int max_bw, int max_bh, int n_elem, int n_pol, int volt_type,
                         int ktaps, int max_cell_taps);
 epic_status launch_grid_box(const FusedBatch &b, int n_pol, int n_time, int volt_type, int chunk,
                             int block, float2 *boxes, hipStream_t stream);
-epic_status launch_fused_fft128_partials(const FusedBatch &b, int n_pol, int n_time, int chunk,
-                                         int block, const float2 *boxes, float *partials,
-                                         const float2 *twiddles, hipStream_t stream);
+epic_status launch_fused_fft128(const FusedBatch &b, int n_pol, int n_time, int chunk, int block,
+                                int flush, const float2 *boxes, const float2 *twiddles,
+                                hipStream_t stream);
 
 // Incoherent combination of station images (k_combine.hip): device pointers
 // of up to kMaxCombine station images, passed by value as a kernel argument.
@@ -282,11 +307,5 @@ epic_status launch_combine(const StationImages &imgs, int n_stations, int plane,
 epic_status launch_gather_beams(const StationImages &beams, int n_st, int n_pol, int n_time,
                                 int npix_b, int n_sel, const int32_t *pix, int64_t item0,
                                 int64_t n_items, float2 *out, hipStream_t stream);
-
-// Ordered, compensated reduction of the partial sums of every chunk, then the
-// mean, written as the n_pol^2 complex products.
-epic_status launch_reduce_partials(int n_pol, int npix, int n_chan, int n_chunks,
-                                   const float *partials, float inv_n_time, float2 *image,
-                                   hipStream_t stream);
 
 }  // namespace epic

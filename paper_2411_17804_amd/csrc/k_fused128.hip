@@ -22,8 +22,10 @@
 // and stores, and after both passes position p holds frequency
 // (p >> 3) + 16 (p & 7).  Rows use this along x, columns along y; the
 // pixel's frequency order is undone when the partial sums are written.
+#include "accum.hpp"
 #include "fft_lds.hpp"
 #include "internal.hpp"
+#include "lds_sync.hpp"
 #include "volts.hpp"
 
 namespace epic {
@@ -162,9 +164,9 @@ __global__ __launch_bounds__(kGridBoxBlock) void k_grid_box(const StationDev *__
         // every unrolled address live across the sample loop
         int tid;
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(static_cast<int>(threadIdx.x)));
-        __syncthreads();          // previous sample's gather done (and taps written)
+        lds_barrier();          // previous sample's gather done (and taps written)
         stash(tid);
-        __syncthreads();
+        lds_barrier();
         if (t + 1 < t_end) fetch(t + 1, tid);
         float2 *out = boxes + item.w + static_cast<size_t>(t - tb0) * NP * plane;
         // cells in groups of G with the tap index outermost, so the G cells'
@@ -230,8 +232,8 @@ template <int NP>
 __global__ __launch_bounds__(kF128Block) void k_fused_fft128(const StationDev *__restrict__ sds,
                                                              const int4 *__restrict__ items,
                                                              int n_time, int chunk, int block,
+                                                             int flush,
                                                              const float2 *__restrict__ boxes,
-                                                             float *__restrict__ partials,
                                                              const float2 *__restrict__ twg)
 {
     constexpr int N = 128;
@@ -243,9 +245,9 @@ __global__ __launch_bounds__(kF128Block) void k_fused_fft128(const StationDev *_
     const StationDev sd = sds[item.x];
     const int c = item.y;
     const ChanPlan cp = sd.chan[c];
-    const int n_chunks = (n_time + chunk - 1) / chunk;
     const int tb0 = block * chunk;
     const int t_end = min(n_time, tb0 + chunk);
+    const ItemSums sums = item_sums(sd.image, NP, PLANE, c);
     const size_t bplane = static_cast<size_t>(sd.max_bh) * sd.max_bw;
     const float2 *box = boxes + item.w;
 
@@ -293,7 +295,7 @@ __global__ __launch_bounds__(kF128Block) void k_fused_fft128(const StationDev *_
                     for (int k1 = 0; k1 < 16; ++k1) lds[pl(y, j + 8 * k1)] = v[k1];
                 }
             }
-            __syncthreads();
+            lds_barrier();
             // RB: twiddle and 8-point DFTs along x, in place
 #pragma unroll 1
             for (int r = 0; r < 4; ++r) {
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(kF128Block) void k_fused_fft128(const StationDev *_
                     for (int k2 = 0; k2 < 8; ++k2) lds[pl(y, 8 * rb_k1 + k2)] = v[k2];
                 }
             }
-            __syncthreads();
+            lds_barrier();
             // CA: 16-point DFTs along y of column position p_col, rows j' + 8m
             // (zero outside the box), output k1' stored back at row j' + 8 k1'
 #pragma unroll 1
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(kF128Block) void k_fused_fft128(const StationDev *_
 #pragma unroll
                 for (int k1 = 0; k1 < 16; ++k1) lds[pl(jc + 8 * k1, p_col)] = v[k1];
             }
-            __syncthreads();
+            lds_barrier();
             // CB: twiddle and 8-point DFTs along y; output k2' is pixel
             // (ky = k1' + 16 k2', kx = kx_of_p)
 #pragma unroll
@@ -365,21 +367,39 @@ __global__ __launch_bounds__(kF128Block) void k_fused_fft128(const StationDev *_
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
+        }
+        // a block of samples ends (or this launch's time block does): its
+        // sums go to the FP64 running sums, a few entries at a time
+        if (block_ends(t, n_time, flush) || t + 1 == t_end) {
+            int lt;
+            asm volatile("v_mov_b32 %0, %1" : "=v"(lt) : "v"(tid));
+            const int p_col = lt & 127;
+            const int kx_of_p = (p_col >> 3) + 16 * (p_col & 7);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int pix = (cgrp + 4 * r + 16 * k) * N + kx_of_p;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        sums_add(sums, q, pix, acc[r][k][q], t < flush);
+                        acc[r][k][q] = 0.f;
+                    }
+                    asm volatile("" ::: "memory");
+                }
         }
     }
-    const int p_col = tid & 127;
-    const int kx_of_p = (p_col >> 3) + 16 * (p_col & 7);
-    float *out = partials + sd.part_off + (static_cast<size_t>(c) * n_chunks + block) * NQ * PLANE;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int k1 = cgrp + 4 * r;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int pix = (k1 + 16 * k) * N + kx_of_p;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) out[q * PLANE + pix] = acc[r][k][q];
-        }
+    // the last time block turns the running sums into the mean products
+    if (t_end == n_time) {
+        sums_settle();
+        const int p_col = tid & 127;
+        const int kx_of_p = (p_col >> 3) + 16 * (p_col & 7);
+        const double inv = 1.0 / static_cast<double>(n_time);
+#pragma unroll 1
+        for (int r = 0; r < 4; ++r)
+#pragma unroll 1
+            for (int k = 0; k < 8; ++k) sums_finish<NP>(sums, (cgrp + 4 * r + 16 * k) * N + kx_of_p, inv);
     }
 }
 
@@ -420,8 +440,8 @@ epic_status launch_grid_box(const FusedBatch &b, int n_pol, int n_time, int volt
     return go(k_grid_box<1, EPIC_CF32>);
 }
 
-epic_status launch_fused_fft128_partials(const FusedBatch &b, int n_pol, int n_time, int chunk,
-                                         int block, const float2 *boxes, float *partials,
+epic_status launch_fused_fft128(const FusedBatch &b, int n_pol, int n_time, int chunk, int block,
+                                int flush, const float2 *boxes,
                                          const float2 *twiddles, hipStream_t stream)
 {
     auto k = n_pol == 2 ? k_fused_fft128<2> : k_fused_fft128<1>;
@@ -431,7 +451,7 @@ epic_status launch_fused_fft128_partials(const FusedBatch &b, int n_pol, int n_t
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
     KernelTimer timer("fused_fft128_cadence", stream);
     hipLaunchKernelGGL(k, dim3(b.n_items), dim3(kF128Block), kF128Lds, stream, b.sds, b.items,
-                       n_time, chunk, block, boxes, partials, twiddles);
+                       n_time, chunk, block, flush, boxes, twiddles);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }

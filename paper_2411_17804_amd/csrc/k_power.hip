@@ -5,6 +5,8 @@
 // Products are kept as four real components per pixel: XX, Re XY, Im XY, YY
 // (n_pol = 2) or XX (n_pol = 1).  XX and YY are formed as re^2 + im^2, so their
 // imaginary parts are exactly zero; YX is written as the exact conjugate of XY.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace epic {
@@ -138,46 +140,33 @@ epic_status launch_power(int n_pol, int npix, int n_chan, int nt, const float2 *
     return EPIC_OK;
 }
 
-// Partial sums [n_chan][n_chunks][NQ][npix] -> mean products.  The chunks are
-// added in time order with the two-sum, so the result does not depend on how
-// work-groups were scheduled.
-template <int NP>
-__global__ __launch_bounds__(256) void k_reduce(int npix, int n_chan, int n_chunks,
-                                                const float *__restrict__ partials, float inv_n,
-                                                float2 *__restrict__ image)
+__global__ __launch_bounds__(256) void k_queue_reset(int *__restrict__ counters, int n)
 {
-    constexpr int NQ = NP == 2 ? 4 : 1;
-    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= static_cast<int64_t>(n_chan) * npix) return;
-    const int c = static_cast<int>(gid / npix);
-    const int k = static_cast<int>(gid - static_cast<int64_t>(c) * npix);
-    float s[NQ], cc[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) s[i] = cc[i] = 0.f;
-    const float *p = partials + static_cast<size_t>(c) * n_chunks * NQ * npix + k;
-    for (int ch = 0; ch < n_chunks; ++ch) {
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) two_sum_acc(s[i], cc[i], p[(static_cast<size_t>(ch) * NQ + i) * npix]);
-    }
-    float m[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) m[i] = (s[i] + cc[i]) * inv_n;
-    store_products<NP>(image + static_cast<size_t>(c) * NP * NP * npix, npix, k, m);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0;
 }
 
-epic_status launch_reduce_partials(int n_pol, int npix, int n_chan, int n_chunks,
-                                   const float *partials, float inv_n_time, float2 *image,
-                                   hipStream_t stream)
+epic_status launch_queue_reset(int *counters, int n, hipStream_t stream)
 {
-    const int64_t n = static_cast<int64_t>(n_chan) * npix;
-    const dim3 blocks(static_cast<unsigned>((n + 255) / 256)), threads(256);
-    KernelTimer timer("reduce_chunks", stream);
-    if (n_pol == 2)
-        hipLaunchKernelGGL(k_reduce<2>, blocks, threads, 0, stream, npix, n_chan, n_chunks, partials,
-                           inv_n_time, image);
-    else
-        hipLaunchKernelGGL(k_reduce<1>, blocks, threads, 0, stream, npix, n_chan, n_chunks, partials,
-                           inv_n_time, image);
+    if (n <= 0) return EPIC_OK;
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(256), 0, stream, counters, n);
+    EPIC_HIP_TRY(hipGetLastError());
+    return EPIC_OK;
+}
+
+__global__ __launch_bounds__(256) void k_zero(uint32_t *__restrict__ p, size_t n)
+{
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        p[i] = 0u;
+}
+
+epic_status launch_zero(void *p, size_t bytes, hipStream_t stream)
+{
+    const size_t n = bytes / 4;
+    if (n == 0) return EPIC_OK;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       static_cast<uint32_t *>(p), n);
     EPIC_HIP_TRY(hipGetLastError());
     return EPIC_OK;
 }
