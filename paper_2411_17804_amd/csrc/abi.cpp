@@ -9,10 +9,6 @@
 
 #include "internal.hpp"
 
-namespace epic {
-const char *last_error_cstr();
-}
-
 using namespace epic;
 
 namespace epic {
@@ -28,55 +24,11 @@ epic_status array_run(const epic_common *common, const epic_station *array,
 
 namespace {
 
-bool is_pow2_grid(int n) { return n >= 16 && n <= 256 && (n & (n - 1)) == 0; }
-
 int ilog2(int n)
 {
     int l = 0;
     while ((1 << l) < n) ++l;
     return l;
-}
-
-epic_status check_common(const epic_common *c)
-{
-    if (!c) return fail(EPIC_ERR_INVALID_ARG, "common is NULL");
-    if (c->n_pol != 1 && c->n_pol != 2) return fail(EPIC_ERR_INVALID_ARG, "n_pol must be 1 or 2");
-    if (c->n_chan < 1) return fail(EPIC_ERR_INVALID_ARG, "n_chan must be >= 1");
-    if (!c->wavelength_m) return fail(EPIC_ERR_INVALID_ARG, "wavelength_m is NULL");
-    for (int i = 0; i < c->n_chan; ++i)
-        if (!std::isfinite(c->wavelength_m[i]) || !(c->wavelength_m[i] > 0.0))
-            return fail(EPIC_ERR_INVALID_ARG, "wavelength_m[" + std::to_string(i) + "] must be finite and > 0");
-    if (!std::isfinite(c->grid_spacing_wl) || !(c->grid_spacing_wl > 0.0))
-        return fail(EPIC_ERR_INVALID_ARG, "grid_spacing_wl must be finite and > 0");
-    if (c->n_time < 1) return fail(EPIC_ERR_INVALID_ARG, "n_time must be >= 1");
-    if (c->volt_type != EPIC_CI8 && c->volt_type != EPIC_CF32)
-        return fail(EPIC_ERR_INVALID_ARG, "unknown volt_type");
-    if (c->precision != EPIC_FP32_FFT && c->precision != EPIC_FP16_SPLIT &&
-        c->precision != EPIC_BF16_SPLIT)
-        return fail(EPIC_ERR_INVALID_ARG, "unknown precision");
-    return EPIC_OK;
-}
-
-epic_status check_station(const epic_station *s, int idx, bool need_volts = true)
-{
-    const std::string who = "station " + std::to_string(idx) + ": ";
-    if (s->n_elem < 1) return fail(EPIC_ERR_INVALID_ARG, who + "n_elem must be >= 1");
-    if (!s->pos_m) return fail(EPIC_ERR_INVALID_ARG, who + "pos_m is NULL");
-    for (int64_t i = 0; i < 2LL * s->n_elem; ++i)
-        if (!std::isfinite(s->pos_m[i])) return fail(EPIC_ERR_INVALID_ARG, who + "non-finite position");
-    if (!is_pow2_grid(s->nx) || !is_pow2_grid(s->ny))
-        return fail(EPIC_ERR_INVALID_ARG, who + "nx, ny must be powers of two in 16..256");
-    const epic_kernel &k = s->kernel;
-    if (k.type != EPIC_KERNEL_NEAREST && k.type != EPIC_KERNEL_GAUSSIAN)
-        return fail(EPIC_ERR_INVALID_ARG, who + "unknown kernel type");
-    if (k.support < 1 || k.support > 7 || (k.support % 2) == 0)
-        return fail(EPIC_ERR_INVALID_ARG, who + "kernel support must be odd, 1..7");
-    if (k.type == EPIC_KERNEL_NEAREST && k.support != 1)
-        return fail(EPIC_ERR_INVALID_ARG, who + "NEAREST kernel needs support 1");
-    if (k.type == EPIC_KERNEL_GAUSSIAN && (!std::isfinite(k.sigma_cells) || !(k.sigma_cells > 0.0)))
-        return fail(EPIC_ERR_INVALID_ARG, who + "Gaussian sigma_cells must be finite and > 0");
-    if (need_volts && !s->volts) return fail(EPIC_ERR_INVALID_ARG, who + "volts is NULL");
-    return EPIC_OK;
 }
 
 epic_status current_device(int *dev)

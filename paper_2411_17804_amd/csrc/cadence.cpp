@@ -421,11 +421,11 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
     const size_t b_sds = up(sizeof(StationDev) * n_sds);
     const size_t b_items = up(sizeof(int4) * n_items);
     const size_t b_cnt = up(sizeof(int) * std::max(1, n_counters));
-    hipError_t e = hipMalloc(&p->dev_tables, b_sds + b_items + b_cnt);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc (cadence tables)");
+    epic_status as = dev_alloc(&p->dev_tables, b_sds + b_items + b_cnt);
+    if (as != EPIC_OK) return as;
     if (box_floats) {
-        e = hipMalloc(reinterpret_cast<void **>(&p->boxes), sizeof(float2) * box_floats);
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc (footprint boxes)");
+        as = dev_alloc(reinterpret_cast<void **>(&p->boxes), sizeof(float2) * box_floats);
+        if (as != EPIC_OK) return as;
     }
     char *base = static_cast<char *>(p->dev_tables);
     StationDev *dsds = reinterpret_cast<StationDev *>(base);

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "epic.h"
+#include "plan_host.hpp"
 #include "queue.hpp"
 
 namespace epic {
@@ -21,18 +22,7 @@ namespace epic {
 // owns the list of (element, weight) taps that land on it, in ascending
 // element order, so each cell's sum has a fixed order and needs no atomics.
 // ---------------------------------------------------------------------------
-struct Tap {
-    int32_t elem;
-    float w;
-};
-
-struct ChanPlan {
-    int32_t x0, y0, bw, bh;   // footprint box of this channel
-    int64_t cell_off;         // first entry of this channel in cell_start[]
-    int64_t tap_off;          // first entry of this channel in taps[]
-    float wsum_max;           // max over cells of the sum of |weight| of its taps
-    int32_t pad_;
-};
+// Tap and ChanPlan: plan_host.hpp.
 
 // The cells along one axis (n cells) that the 128 x 128 split-precision
 // transform reads of a plane whose non-zero cells lie in [lo, lo + len): the
@@ -85,9 +75,12 @@ struct FusedBatch {
 // ---------------------------------------------------------------------------
 // Error reporting (thread-local detail string).
 // ---------------------------------------------------------------------------
-void set_error(const std::string &msg);
-epic_status fail(epic_status st, const std::string &msg);
 epic_status hip_fail(hipError_t e, const char *what);
+
+// Every library-owned device allocation goes through here.  Test hook: with
+// EPIC_TEST_FAIL_ALLOC=1 in the environment every one of them fails with
+// EPIC_ERR_OUT_OF_MEMORY (and nothing is allocated).
+epic_status dev_alloc(void **p, size_t bytes);
 
 #define EPIC_HIP_TRY(call)                                   \
     do {                                                     \
@@ -148,9 +141,6 @@ struct XfftPlanHandle {
 
 epic_status get_xfft_plan(const epic_common *common, const epic_station *st, int device,
                           XfftPlanHandle *out);
-
-// Host-only geometry check (no device needed).
-epic_status check_geometry(const epic_common *common, const epic_station *st);
 
 // Validates the geometry and returns the (cached) device plan of one station.
 epic_status get_plan(const epic_common *common, const epic_station *st, int device,

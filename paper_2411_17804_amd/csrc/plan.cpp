@@ -1,11 +1,6 @@
-// plan.cpp -- host-side plan builder (FP64) and the library's device caches.
-//
-// For every (station, channel) the plan holds the kernel taps of Eq. 3's
-// gridding: each element a lands on the K x K cells around its nearest cell
-// with separable weights evaluated at its true sub-cell position (Sec. 5.2:
-// the kernel W~ is centred on r_a; the grid r_j is fixed in wavelengths so
-// the geometry is recomputed per channel).  Everything is computed in double
-// precision and rounded once to FP32 when stored.
+// plan.cpp -- the library's device caches: station plans (built on the host
+// by host.cpp, uploaded once per geometry), transform tables, workspaces and
+// the XFFT route's plans, and the one device allocator they all use.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -22,23 +17,11 @@
 namespace epic {
 
 // ----------------------------------------------------------------- errors --
-static thread_local std::string g_last_error;
-
-void set_error(const std::string &msg) { g_last_error = msg; }
-
-epic_status fail(epic_status st, const std::string &msg)
-{
-    g_last_error = msg;
-    return st;
-}
-
 epic_status hip_fail(hipError_t e, const char *what)
 {
-    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? EPIC_ERR_OUT_OF_MEMORY : EPIC_ERR_DEVICE;
 }
-
-const char *last_error_cstr() { return g_last_error.c_str(); }
 
 // Test hook: EPIC_TEST_FAIL_ALLOC=1 makes every library-owned allocation fail.
 static bool alloc_fail_forced()
@@ -47,7 +30,7 @@ static bool alloc_fail_forced()
     return e && e[0] == '1';
 }
 
-static epic_status dev_alloc(void **p, size_t bytes)
+epic_status dev_alloc(void **p, size_t bytes)
 {
     if (alloc_fail_forced()) return fail(EPIC_ERR_OUT_OF_MEMORY, "allocation refused (EPIC_TEST_FAIL_ALLOC)");
     hipError_t e = hipMalloc(p, bytes == 0 ? 16 : bytes);
@@ -84,41 +67,6 @@ static void append(std::string &k, const void *p, size_t n)
     k.append(static_cast<const char *>(p), n);
 }
 
-// Geometry of one element at one channel: nearest cell and separable weights.
-// Returns false if the footprint leaves the grid.
-static bool element_taps(double x, double y, double delta, int nx, int ny, const epic_kernel &kn,
-                         int *ci, int *cj, double *wx, double *wy)
-{
-    const double u = x / delta + static_cast<double>(nx / 2);
-    const double v = y / delta + static_cast<double>(ny / 2);
-    const double fi = std::floor(u + 0.5);
-    const double fj = std::floor(v + 0.5);
-    const int K = kn.support;
-    const int h = (K - 1) / 2;
-    if (fi - h < 0 || fi + h > nx - 1 || fj - h < 0 || fj + h > ny - 1) return false;
-    *ci = static_cast<int>(fi);
-    *cj = static_cast<int>(fj);
-    if (kn.type == EPIC_KERNEL_NEAREST) {
-        wx[0] = wy[0] = 1.0;
-        return true;
-    }
-    const double du = u - fi, dv = v - fj;
-    double sx = 0.0, sy = 0.0;
-    for (int d = -h; d <= h; ++d) {
-        const double ex = (static_cast<double>(d) - du) / kn.sigma_cells;
-        const double ey = (static_cast<double>(d) - dv) / kn.sigma_cells;
-        wx[d + h] = std::exp(-0.5 * ex * ex);
-        wy[d + h] = std::exp(-0.5 * ey * ey);
-        sx += wx[d + h];
-        sy += wy[d + h];
-    }
-    for (int d = 0; d < K; ++d) {
-        wx[d] /= sx;
-        wy[d] /= sy;
-    }
-    return true;
-}
-
 // Cache key of a station's geometry on one device (everything a plan depends on).
 static std::string geometry_key(const epic_common *common, const epic_station *st, int device)
 {
@@ -141,31 +89,9 @@ static std::string geometry_key(const epic_common *common, const epic_station *s
     return key;
 }
 
-epic_status check_geometry(const epic_common *common, const epic_station *st)
-{
-    const int K = st->kernel.support;
-    std::vector<double> wx(K), wy(K);
-    for (int c = 0; c < common->n_chan; ++c) {
-        const double delta = common->grid_spacing_wl * common->wavelength_m[c];
-        for (int a = 0; a < st->n_elem; ++a) {
-            int ci = 0, cj = 0;
-            if (!element_taps(st->pos_m[2 * a], st->pos_m[2 * a + 1], delta, st->nx, st->ny,
-                              st->kernel, &ci, &cj, wx.data(), wy.data()))
-                return fail(EPIC_ERR_INVALID_ARG,
-                            "element " + std::to_string(a) + " kernel footprint leaves the " +
-                                std::to_string(st->nx) + "x" + std::to_string(st->ny) +
-                                " grid at channel " + std::to_string(c));
-        }
-    }
-    return EPIC_OK;
-}
-
 epic_status get_plan(const epic_common *common, const epic_station *st, int device,
                      PlanHandle *out)
 {
-    const int n_chan = common->n_chan;
-    const int n_elem = st->n_elem;
-    const int K = st->kernel.support;
     std::string key = geometry_key(common, st, device);
 
     std::lock_guard<std::mutex> lock(g_mu);
@@ -175,87 +101,18 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
         return EPIC_OK;
     }
 
-    // Build on the host in FP64.
-    const int nx = st->nx, ny = st->ny, h = (K - 1) / 2;
-    std::vector<ChanPlan> chans(n_chan);
-    std::vector<int32_t> cell_start;
-    std::vector<int32_t> cell_order;   // per channel: box cells by descending tap count
-    std::vector<int32_t> elem_cell(static_cast<size_t>(n_chan) * n_elem);   // ci | cj << 16
-    std::vector<Tap> taps;
-    std::vector<int> ci(n_elem), cj(n_elem);
-    std::vector<double> wx(static_cast<size_t>(n_elem) * K), wy(static_cast<size_t>(n_elem) * K);
+    HostPlan hp;
+    epic_status bs = build_host_plan(common, st, &hp);
+    if (bs != EPIC_OK) return bs;
+    const std::vector<ChanPlan> &chans = hp.chans;
+    const std::vector<int32_t> &cell_start = hp.cell_start, &cell_order = hp.cell_order,
+                               &elem_cell = hp.elem_cell;
+    const std::vector<Tap> &taps = hp.taps;
     PlanHandle hd;
-    for (int c = 0; c < n_chan; ++c) {
-        const double delta = common->grid_spacing_wl * common->wavelength_m[c];
-        int x_lo = nx, x_hi = -1, y_lo = ny, y_hi = -1;
-        for (int a = 0; a < n_elem; ++a) {
-            if (!element_taps(st->pos_m[2 * a], st->pos_m[2 * a + 1], delta, nx, ny, st->kernel,
-                              &ci[a], &cj[a], &wx[static_cast<size_t>(a) * K],
-                              &wy[static_cast<size_t>(a) * K])) {
-                return fail(EPIC_ERR_INVALID_ARG,
-                            "element " + std::to_string(a) + " kernel footprint leaves the " +
-                                std::to_string(nx) + "x" + std::to_string(ny) +
-                                " grid at channel " + std::to_string(c));
-            }
-            x_lo = std::min(x_lo, ci[a] - h);
-            x_hi = std::max(x_hi, ci[a] + h);
-            y_lo = std::min(y_lo, cj[a] - h);
-            y_hi = std::max(y_hi, cj[a] + h);
-        }
-        for (int a = 0; a < n_elem; ++a)
-            elem_cell[static_cast<size_t>(c) * n_elem + a] = ci[a] | (cj[a] << 16);
-        ChanPlan &cp = chans[c];
-        cp.x0 = x_lo;
-        cp.y0 = y_lo;
-        cp.bw = x_hi - x_lo + 1;
-        cp.bh = y_hi - y_lo + 1;
-        cp.cell_off = static_cast<int64_t>(cell_start.size());
-        cp.tap_off = static_cast<int64_t>(taps.size());
-        const int ncell = cp.bw * cp.bh;
-        hd.max_box = std::max(hd.max_box, ncell);
-        hd.max_bw = std::max(hd.max_bw, cp.bw);
-        hd.max_bh = std::max(hd.max_bh, cp.bh);
-        // counting sort of taps by cell; elements visited in ascending order
-        std::vector<int32_t> count(static_cast<size_t>(ncell) + 1, 0);
-        for (int a = 0; a < n_elem; ++a)
-            for (int dy = -h; dy <= h; ++dy)
-                for (int dx = -h; dx <= h; ++dx)
-                    ++count[static_cast<size_t>(cj[a] + dy - y_lo) * cp.bw + (ci[a] + dx - x_lo) + 1];
-        for (int i = 0; i < ncell; ++i) count[i + 1] += count[i];
-        const size_t base = taps.size();
-        taps.resize(base + static_cast<size_t>(count[ncell]));
-        std::vector<int32_t> fillp(count.begin(), count.end() - 1);
-        for (int a = 0; a < n_elem; ++a)
-            for (int dy = -h; dy <= h; ++dy)
-                for (int dx = -h; dx <= h; ++dx) {
-                    const size_t cell = static_cast<size_t>(cj[a] + dy - y_lo) * cp.bw + (ci[a] + dx - x_lo);
-                    const double w = wx[static_cast<size_t>(a) * K + dx + h] * wy[static_cast<size_t>(a) * K + dy + h];
-                    taps[base + fillp[cell]++] = Tap{a, static_cast<float>(w)};
-                }
-        for (int i = 0; i < ncell; ++i) hd.max_cell_taps = std::max(hd.max_cell_taps, count[i + 1] - count[i]);
-        {
-            std::vector<double> wsum(ncell, 0.0);
-            for (int a = 0; a < n_elem; ++a)
-                for (int dy = -h; dy <= h; ++dy)
-                    for (int dx = -h; dx <= h; ++dx)
-                        wsum[static_cast<size_t>(cj[a] + dy - y_lo) * cp.bw + (ci[a] + dx - x_lo)] +=
-                            std::fabs(wx[static_cast<size_t>(a) * K + dx + h] * wy[static_cast<size_t>(a) * K + dy + h]);
-            double m = 0.0;
-            for (double v : wsum) m = std::max(m, v);
-            cp.wsum_max = static_cast<float>(m * (1.0 + 1e-6));   // rounded up
-            cp.pad_ = 0;
-        }
-        cell_start.insert(cell_start.end(), count.begin(), count.end());
-        // cells sorted by tap count (ties by index) so that neighbouring lanes of a
-        // gathering wave walk lists of about the same length
-        std::vector<int32_t> order(ncell);
-        for (int i = 0; i < ncell; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            return count[a + 1] - count[a] > count[b + 1] - count[b];
-        });
-        cell_order.insert(cell_order.end(), order.begin(), order.end());
-        cell_order.push_back(-1);
-    }
+    hd.max_box = hp.max_box;
+    hd.max_bw = hp.max_bw;
+    hd.max_bh = hp.max_bh;
+    hd.max_cell_taps = hp.max_cell_taps;
     hd.n_taps_total = static_cast<int64_t>(taps.size());
 
     // Upload: one allocation, three 256-byte aligned sections.
