@@ -163,6 +163,27 @@ epic_status image_cadence(const epic_common *common, const epic_station *station
                           int32_t n_stations, hipStream_t stream);
 
 /*
+ * image_cadence for callers that cannot allocate device memory: code under
+ * hipGraph stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, layouts and results as image_cadence (the same
+ * kernels run), but the call allocates nothing: every table it needs (the
+ * stations' kernel cells and weights, the transform tables, the work lists
+ * and queue counters) is written into one fixed device array of 64 MiB that
+ * the library holds on each GPU until the process ends, and the images
+ * themselves carry the running sums.  Covered: stations with square grids up
+ * to 64 x 64 (FP32 or split precision); anything else, or a call whose tables
+ * exceed the 64 MiB (a 256-element station with a 3 x 3 kernel on a 64 x 64
+ * grid needs about 37 KB per channel), returns EPIC_ERR_UNSUPPORTED before any
+ * launch.  The tables are
+ * rebuilt on the host and copied on every call (nothing is cached).  The call
+ * first waits for the earlier work on `stream`, which may still read the
+ * array; calls on one GPU share the array, so calls that overlap on one GPU
+ * (different streams or threads) race and must not be made.
+ */
+epic_status image_cadence_noalloc(const epic_common *common, const epic_station *stations,
+                                  int32_t n_stations, hipStream_t stream);
+
+/*
  * FFT-correlator output (Sec. 6.2: an FFT correlator obtains the visibilities
  * by one more, inverse, transform of the polarised intensities; Eq. 4 defines
  * the visibilities and Eq. 6 their gridding with the cross-correlated element

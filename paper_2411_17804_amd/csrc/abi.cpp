@@ -524,6 +524,24 @@ epic_status image_cadence(const epic_common *common, const epic_station *station
     return run_cadence(common, stations, n_stations, plans.data(), dev, stream);
 }
 
+epic_status image_cadence_noalloc(const epic_common *common, const epic_station *stations,
+                                  int32_t n_stations, hipStream_t stream)
+{
+    set_error("");
+    epic_status st = check_common(common);
+    if (st != EPIC_OK) return st;
+    if (!stations || n_stations < 1) return fail(EPIC_ERR_INVALID_ARG, "need >= 1 station");
+    for (int i = 0; i < n_stations; ++i) {
+        st = check_station(&stations[i], i);
+        if (st != EPIC_OK) return st;
+        if (!stations[i].image) return fail(EPIC_ERR_INVALID_ARG, "station image is NULL");
+    }
+    int dev = 0;
+    st = current_device(&dev);
+    if (st != EPIC_OK) return st;
+    return run_cadence_noalloc(common, stations, n_stations, dev, stream);
+}
+
 epic_status epic_autotune(const epic_common *common, const epic_station *stations,
                           int32_t n_stations, hipStream_t stream)
 {

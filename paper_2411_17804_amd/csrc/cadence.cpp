@@ -635,6 +635,142 @@ epic_status tune_cadence(const epic_common *c, const epic_station *st, int n,
     return EPIC_OK;
 }
 
+// ------------------------------------------------------------------------
+// The cadence without allocating: every table a call needs (the stations'
+// plans, the transform tables, the class tables, item lists and queue
+// counters) goes into one file-scope device array instead of library
+// allocations.  The image buffers carry the running sums as in run_cadence.
+// Each GPU holds its own copy of the array (its address, taken once per
+// device with hipGetSymbolAddress, is kept per device); calls on one GPU
+// share it, so calls that overlap on one GPU race (the call waits for its own
+// stream's earlier work before it overwrites the array).
+// ------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch;   // device -> address of its scratch
+
+epic_status scratch_of(int device, unsigned char **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(device);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return EPIC_OK;
+    }
+    void *ptr = nullptr;
+    EPIC_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch[device] = static_cast<unsigned char *>(ptr);
+    *out = static_cast<unsigned char *>(ptr);
+    return EPIC_OK;
+}
+
+// Sub-ranges of the scratch array, 256-byte aligned, with their host sources.
+struct ScratchLayout {
+    size_t used = 0;
+    std::vector<std::pair<size_t, std::pair<const void *, size_t>>> copies;
+    size_t put(const void *src, size_t bytes)
+    {
+        const size_t off = used;
+        used = (used + bytes + 255) & ~static_cast<size_t>(255);
+        if (src && bytes) copies.push_back({off, {src, bytes}});
+        return off;
+    }
+};
+
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return kScratchBytes; }
+
+epic_status run_cadence_noalloc(const epic_common *c, const epic_station *st, int n, int device,
+                                hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_tune_file();
+    unsigned char *base = nullptr;
+    epic_status s = scratch_of(device, &base);
+    if (s != EPIC_OK) return s;
+
+    // host tables of every station
+    std::vector<HostPlan> hps(n);
+    for (int i = 0; i < n; ++i) {
+        s = build_host_plan(c, &st[i], &hps[i]);
+        if (s != EPIC_OK) return fail(s, "station " + std::to_string(i) + ": " + last_error_cstr());
+    }
+    ScratchLayout lay;
+    std::vector<PlanHandle> plans(n);
+    for (int i = 0; i < n; ++i) {
+        const HostPlan &h = hps[i];
+        PlanHandle &ph = plans[i];
+        ph.chan = reinterpret_cast<const ChanPlan *>(base + lay.put(h.chans.data(), sizeof(ChanPlan) * h.chans.size()));
+        ph.cell_start = reinterpret_cast<const int32_t *>(base + lay.put(h.cell_start.data(), sizeof(int32_t) * h.cell_start.size()));
+        ph.taps = reinterpret_cast<const Tap *>(base + lay.put(h.taps.data(), sizeof(Tap) * h.taps.size()));
+        ph.cell_order = reinterpret_cast<const int32_t *>(base + lay.put(h.cell_order.data(), sizeof(int32_t) * h.cell_order.size()));
+        ph.elem_cell = nullptr;   // the fused kernels do not read it
+        ph.max_box = h.max_box;
+        ph.max_bw = h.max_bw;
+        ph.max_bh = h.max_bh;
+        ph.max_cell_taps = h.max_cell_taps;
+        ph.n_taps_total = static_cast<int64_t>(h.taps.size());
+    }
+    CadencePlan p;
+    classify(c, st, n, plans.data(), p.groups, p.composed);
+    if (!p.composed.empty())
+        return fail(EPIC_ERR_UNSUPPORTED, "image_cadence_noalloc: station " + std::to_string(p.composed.front()) +
+                                              " needs the composed path's workspaces; only square grids up to 64 "
+                                              "(FP32 or split precision) run without allocating");
+    std::vector<std::vector<float2>> tw_host;
+    std::vector<std::vector<unsigned char>> rows_host;
+    for (Group &g : p.groups) {
+        if (g.path == kPathFft128)
+            return fail(EPIC_ERR_UNSUPPORTED, "image_cadence_noalloc: 128 x 128 FP32 stations need the footprint-box "
+                                              "buffer; only square grids up to 64 run without allocating");
+        g.batch.variant = g.tile.variant;
+        for (int i : g.members) g.host_sds.push_back(make_station_dev(&st[i], plans[i]));
+        build_queue_lists(g, c->n_chan, c->n_time, c->n_pol);
+        g.batch.n_items = static_cast<int>(g.host_items.size());
+        if (g.path == kPathFft && !p.twiddles[g.n]) {
+            tw_host.emplace_back(g.n);
+            fill_twiddles(g.n, tw_host.back().data());
+            p.twiddles[g.n] = reinterpret_cast<const float2 *>(base + lay.put(tw_host.back().data(), sizeof(float2) * g.n));
+        }
+        if (g.path == kPathDft && !p.rows[g.n]) {
+            rows_host.emplace_back(static_cast<size_t>(g.n) * g.n * 8);
+            fill_rows_any(g.n, c->precision, rows_host.back().data());
+            p.rows[g.n] = reinterpret_cast<const uint32_t *>(base + lay.put(rows_host.back().data(), rows_host.back().size()));
+        }
+    }
+    int n_counters = 0;
+    for (Group &g : p.groups) {
+        g.batch.sds = reinterpret_cast<const StationDev *>(base + lay.put(g.host_sds.data(), sizeof(StationDev) * g.host_sds.size()));
+        g.batch.items = reinterpret_cast<const int4 *>(base + lay.put(g.host_items.data(), sizeof(int4) * g.host_items.size()));
+        g.batch.q.items = g.batch.items;
+        g.queue_slot = n_counters;
+        n_counters += kXcds;
+    }
+    p.counters = reinterpret_cast<int *>(base + lay.put(nullptr, sizeof(int) * std::max(1, n_counters)));
+    p.n_counters = n_counters;
+    for (Group &g : p.groups) g.batch.q.counters = p.counters + g.queue_slot;
+    if (lay.used > kScratchBytes)
+        return fail(EPIC_ERR_UNSUPPORTED, "image_cadence_noalloc: the call needs " + std::to_string(lay.used) +
+                                              " bytes of tables, the allocation-free scratch holds " +
+                                              std::to_string(kScratchBytes) + " (fewer channels or stations per call)");
+    // the previous call on this stream may still read the scratch
+    EPIC_HIP_TRY(hipStreamSynchronize(stream));
+    for (const auto &cp : lay.copies)
+        EPIC_HIP_TRY(hipMemcpy(base + cp.first, cp.second.first, cp.second.second, hipMemcpyHostToDevice));
+    s = launch_queue_reset(p.counters, p.n_counters, stream);
+    if (s != EPIC_OK) return s;
+    for (const Group &g : p.groups) {
+        s = launch_group(c, &p, g, stream);
+        if (s != EPIC_OK) return s;
+    }
+    return EPIC_OK;
+}
+
 void clear_cadence_cache()
 {
     std::lock_guard<std::mutex> lock(g_mu);

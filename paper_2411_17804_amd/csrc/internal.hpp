@@ -146,14 +146,18 @@ epic_status get_xfft_plan(const epic_common *common, const epic_station *st, int
 epic_status get_plan(const epic_common *common, const epic_station *st, int device,
                      PlanHandle *out);
 
-// Device table of exp(+2 pi i k / n), k < n (FP64-generated, FP32 stored).
+// Device table of exp(+2 pi i k / n), k < n (FP64-generated, FP32 stored),
+// and its host form.
 epic_status get_twiddles(int n, int device, const float2 **out);
+void fill_twiddles(int n, float2 *dst);
 
 // Split-precision DFT tables in MFMA fragment order (k_dft.hip).
 epic_status get_dft_tables(int n, int precision, int device, const void **out);
 
-// DFT matrix rows [n][n] as packed (re, im) hi parts, then lo parts (k_dft.hip).
+// DFT matrix rows [n][n] as packed (re, im) hi parts, then lo parts (k_dft.hip),
+// and its host form (n * n * 8 bytes).
 epic_status get_dft_rows(int n, int precision, int device, const uint32_t **out);
+void fill_rows_any(int n, int precision, void *dst);
 
 // Fused split-precision cadence for square grids n in {16, 32, 64}: one
 // work-group per (station, channel) item over the whole cadence, block sums of
@@ -178,6 +182,12 @@ epic_status run_cadence(const epic_common *c, const epic_station *st, int n, con
 epic_status tune_cadence(const epic_common *c, const epic_station *st, int n,
                          const PlanHandle *plans, int device, hipStream_t stream);
 void clear_cadence_cache();
+
+// The cadence of stations that the persistent fused kernels cover, with every
+// table in a fixed file-scope device array (no allocation; cadence.cpp).
+epic_status run_cadence_noalloc(const epic_common *c, const epic_station *st, int n, int device,
+                                hipStream_t stream);
+size_t noalloc_scratch_bytes();
 bool timing_on();
 
 // ---------------------------------------------------------------------------

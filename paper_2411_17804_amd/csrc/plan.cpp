@@ -153,6 +153,15 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     return EPIC_OK;
 }
 
+void fill_twiddles(int n, float2 *dst)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < n; ++k) {
+        const double a = two_pi * static_cast<double>(k) / static_cast<double>(n);
+        dst[k] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
+    }
+}
+
 epic_status get_twiddles(int n, int device, const float2 **out)
 {
     std::lock_guard<std::mutex> lock(g_mu);
@@ -163,11 +172,7 @@ epic_status get_twiddles(int n, int device, const float2 **out)
         return EPIC_OK;
     }
     std::vector<float2> tw(n);
-    const double two_pi = 6.283185307179586476925286766559;
-    for (int k = 0; k < n; ++k) {
-        const double a = two_pi * static_cast<double>(k) / static_cast<double>(n);
-        tw[k] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
-    }
+    fill_twiddles(n, tw.data());
     void *dev = nullptr;
     epic_status s = dev_alloc(&dev, sizeof(float2) * n);
     if (s != EPIC_OK) return s;

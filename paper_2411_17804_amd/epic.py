@@ -34,6 +34,7 @@ KERNEL_GAUSSIAN = 1
 
 # every function the header declares
 ABI_FUNCTIONS = ("grid_voltages", "fft2_batched", "accumulate_power", "image_cadence",
+                 "image_cadence_noalloc",
                  "image_to_visibilities", "combine_incoherent", "xfft_correlate", "xfft_image", "array_cadence", "array_xfft", "grid_voltages_pol", "image_cadence_pol",
                  "epic_autotune", "epic_validate", "epic_timing_enable", "epic_timing_report",
                  "epic_timing_reset", "epic_status_string", "epic_last_error",
@@ -86,6 +87,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.accumulate_power.restype = i32
     lib.image_cadence.argtypes = [P, P, i32, P]
     lib.image_cadence.restype = i32
+    lib.image_cadence_noalloc.argtypes = [P, P, i32, P]
+    lib.image_cadence_noalloc.restype = i32
     lib.image_to_visibilities.argtypes = [i32, i32, i32, i32, P, P, P]
     lib.image_to_visibilities.restype = i32
     lib.combine_incoherent.argtypes = [i32, i32, i32, i32, i32, P, P, P, P]
@@ -429,6 +432,15 @@ def image_cadence(common: Common, stations, stream=None):
     c, keep1 = common.to_c()
     arr, keep = _stations_c(stations, common)
     _check(lib.image_cadence(ctypes.byref(c), arr, len(stations), _stream(stream)))
+
+
+def image_cadence_noalloc(common: Common, stations, stream=None):
+    """image_cadence without any device allocation (tables in the library's
+    fixed scratch array; square grids up to 64 only)."""
+    lib = load()
+    c, keep1 = common.to_c()
+    arr, keep = _stations_c(stations, common)
+    _check(lib.image_cadence_noalloc(ctypes.byref(c), arr, len(stations), _stream(stream)))
 
 
 def autotune(common: Common, stations, stream=None):
