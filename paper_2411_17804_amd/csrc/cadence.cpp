@@ -4,17 +4,16 @@
 // (square grids up to 64, one class per grid size, split where the LDS of
 // the class's largest station would not fit the fast kernel), the fused
 // split-precision kernel (square grids up to 64, per grid size and footprint
-// tile count, split where the LDS would overflow) and the FP32 path for
-// 128 x 128 grids.  The first two are persistent kernels: one launch per
-// class takes its (station, channel) items from a work queue (queue.hpp)
-// whose lists are balanced over the XCDs and ordered longest first, and each
-// item images its pair over the whole cadence, keeping FP64 running sums in
-// the caller's image buffer until it writes the mean products (accum.hpp).
-// The 128 x 128 class runs per time block: a gridding launch into footprint
-// boxes, then the fused transform-and-square launch, for each batch of
-// (station, channel) pairs whose boxes fit the box buffer.  Stations outside
-// every class take the composed path (grid -> transform -> square and
-// accumulate, in time chunks).
+// tile count, split where the LDS would overflow) and the FP32 kernel for
+// 128 x 128 grids.  All are persistent kernels: one launch per class takes
+// its (station, channel) items from a work queue (queue.hpp) whose lists are
+// balanced over the XCDs and ordered longest first, and each item images its
+// pair over the whole cadence, keeping FP64 running sums in the caller's
+// image buffer until it writes the mean products (accum.hpp).  The
+// 128 x 128 kernel grids each block of samples into footprint boxes in its
+// work-group's slice of a box buffer before transforming them.  Stations
+// outside every class take the composed path (grid -> transform -> square
+// and accumulate, in time chunks).
 //
 // The class tables, item lists and queue counters are built once per distinct
 // call (same geometry, buffers and stream) and kept.  The first call runs
@@ -68,20 +67,11 @@ int persistent_grid(const void *kernel, int block, size_t lds, int n_items)
 namespace {
 
 constexpr int kPathFft = 0, kPathDft = 1, kPathFft128 = 2;
-// Bytes of footprint boxes per batch of the 128 x 128 class: 2 GiB, or
-// EPIC_BOX_BUDGET_MB megabytes (a smaller buffer means more, smaller batches).
-size_t box_budget()
-{
-    const char *e = std::getenv("EPIC_BOX_BUDGET_MB");
-    const long mb = e ? std::atol(e) : 0;
-    return mb > 0 ? static_cast<size_t>(mb) << 20 : size_t(2) << 30;
-}
 // Samples summed in FP32 before the FP64 running sums (the bound of the
 // plain block sum, (B - 1) units in the last place, is what limits the error
-// of the mean), and the time block of the 128 x 128 class (box buffer).
+// of the mean; in the 128 x 128 class it is also the gridding block).
 constexpr int kDefaultFlush = 16;
 const int kFlushCandidates[] = {8, 16};
-constexpr int kBlock128 = 64;
 
 struct Tile {
     int variant = 0;
@@ -95,7 +85,7 @@ struct Group {
     Tile tile;
     std::vector<int> members;     // station indices of the call
     FusedBatch batch;             // device pointers set after upload
-    std::vector<std::pair<int, int>> pair_batches;   // 128 x 128 class: (first item, count)
+    size_t wg_box_floats = 0;     // 128 x 128 class: footprint boxes per work-group
     std::vector<StationDev> host_sds;
     std::vector<int4> host_items;
     int queue_slot = 0;           // first of this group's kXcds counters
@@ -105,7 +95,7 @@ struct CadencePlan {
     std::vector<Group> groups;
     std::vector<int> composed;
     void *dev_tables = nullptr;
-    float2 *boxes = nullptr;         // footprint boxes of one batch (128 x 128 class)
+    float2 *boxes = nullptr;         // footprint boxes of the 128 x 128 classes' work-groups
     int *counters = nullptr;         // queue counters, kXcds per persistent group
     int n_counters = 0;
     const float2 *twiddles[257] = {};
@@ -379,32 +369,22 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
         if (gi < tiles_override.size() && tiles_override[gi].flush > 0) g.tile = tiles_override[gi];
         g.batch.variant = g.tile.variant;
         for (int i : g.members) g.host_sds.push_back(make_station_dev(&st[i], plans[i]));
-        if (g.path == kPathFft128) {
-            for (size_t k = 0; k < g.host_sds.size(); ++k)
-                for (int ch = 0; ch < c->n_chan; ++ch) g.host_items.push_back(make_int4(static_cast<int>(k), ch, 0, 0));
-            // batches of pairs whose boxes for one time block fit the budget;
-            // box offsets restart at 0 in every batch (one buffer serves all)
-            const int block = std::min(kBlock128, c->n_time);
-            size_t pair_floats = 0;
-            for (const StationDev &sd : g.host_sds)
-                pair_floats = std::max(pair_floats, static_cast<size_t>(block) * c->n_pol * sd.max_bw * sd.max_bh);
-            const int n_pairs = static_cast<int>(g.host_items.size());
-            int per = static_cast<int>(std::max<size_t>(1, box_budget() / (sizeof(float2) * pair_floats)));
-            if (per > 256 && per < n_pairs) per = per / 256 * 256;   // whole waves of work-groups
-            per = std::min(per, n_pairs);
-            for (int first = 0; first < n_pairs; first += per) {
-                const int cnt = std::min(per, n_pairs - first);
-                for (int q = 0; q < cnt; ++q)
-                    g.host_items[first + q].w = static_cast<int>(static_cast<size_t>(q) * pair_floats);
-                g.pair_batches.emplace_back(first, cnt);
-            }
-            box_floats = std::max(box_floats, static_cast<size_t>(per) * pair_floats);
-        } else {
-            build_queue_lists(g, c->n_chan, c->n_time, c->n_pol);
-            g.queue_slot = n_counters;
-            n_counters += kXcds;
-        }
+        build_queue_lists(g, c->n_chan, c->n_time, c->n_pol);
+        g.queue_slot = n_counters;
+        n_counters += kXcds;
         g.batch.n_items = static_cast<int>(g.host_items.size());
+        if (g.path == kPathFft128) {
+            // each work-group grids one block of `flush` samples at a time
+            // into its own boxes; the classes run one after another, so one
+            // buffer serves them all
+            const int block = std::min(g.tile.flush, c->n_time);
+            size_t wg = 0;
+            for (const StationDev &sd : g.host_sds)
+                wg = std::max(wg, static_cast<size_t>(block) * c->n_pol * sd.max_bw * sd.max_bh);
+            g.wg_box_floats = (wg + 31) & ~static_cast<size_t>(31);   // 256-byte slices
+            g.batch.grid = cadence128_grid(c->n_pol, c->volt_type, g.batch.n_items);
+            box_floats = std::max(box_floats, g.wg_box_floats * g.batch.grid);
+        }
         n_sds += g.host_sds.size();
         n_items += g.host_items.size();
         if (g.path != kPathDft && !p->twiddles[g.n]) {
@@ -454,23 +434,9 @@ epic_status launch_group(const epic_common *c, const CadencePlan *p, const Group
     const int flush = g.tile.flush;
     if (g.path == kPathFft)
         return launch_fused_fft(g.batch, c->n_pol, c->n_time, c->volt_type, flush, p->twiddles[g.n], stream);
-    if (g.path == kPathFft128) {
-        const int block = std::min(kBlock128, c->n_time);
-        const int n_blocks = (c->n_time + block - 1) / block;
-        for (int blk = 0; blk < n_blocks; ++blk)
-            for (const auto &pb : g.pair_batches) {
-                FusedBatch sub = g.batch;
-                sub.items = g.batch.items + pb.first;
-                sub.n_items = pb.second;
-                epic_status s = launch_grid_box(sub, c->n_pol, c->n_time, c->volt_type, block, blk,
-                                                p->boxes, stream);
-                if (s != EPIC_OK) return s;
-                s = launch_fused_fft128(sub, c->n_pol, c->n_time, block, blk, flush, p->boxes,
-                                        p->twiddles[g.n], stream);
-                if (s != EPIC_OK) return s;
-            }
-        return EPIC_OK;
-    }
+    if (g.path == kPathFft128)
+        return launch_cadence128(g.batch, c->n_pol, c->n_time, c->volt_type, flush, p->boxes, g.wg_box_floats,
+                                 p->twiddles[g.n], stream);
     return launch_fused_dft(g.batch, c->n_pol, c->n_time, c->volt_type, c->precision, flush,
                             p->rows[g.n], stream);
 }

@@ -55,8 +55,7 @@ struct StationDev {
 // A batch of fused work: items (station index, channel, time chunk, band or
 // 0) over a device table of stations, plus the class-wide maxima the LDS
 // layout uses.  Persistent kernels take their items from the queue q with
-// `grid` work-groups; the 128 x 128 FP32 pair of kernels reads items[] by
-// work-group index.
+// `grid` work-groups.
 struct FusedBatch {
     const StationDev *sds = nullptr;   // device [n_stations]
     const int4 *items = nullptr;       // device [n_items]
@@ -276,20 +275,18 @@ epic_status launch_fused_fft(const FusedBatch &b, int n_pol, int n_time, int vol
 // Whether the fused FP32 kernels cover a batch with these maxima.
 bool fused_fft_supported(const FusedBatch &b, int n_pol, int volt_type);
 
-// The FP32 cadence for 128 x 128 grids (k_fused128.hip), per time block of
-// `chunk` samples: launch_grid_box grids the block's samples of every
-// (station, channel) pair of the batch (items: station index, channel, 0, box
-// offset in float2) into footprint boxes [t][pol][max_bh][max_bw];
-// launch_fused_fft128 transforms them and adds block sums of `flush` samples
-// to the pair's FP64 running sums in the image buffer (one item per pair; the
-// last time block writes the mean products).
+// The FP32 cadence for 128 x 128 grids (k_fused128.hip): a persistent
+// kernel over the batch's (station, channel) items, each over the whole
+// cadence in blocks of `flush` samples, gridded into the work-group's
+// footprint boxes (boxes + blockIdx * wg_floats; [flush][pol][max_bh][max_bw]
+// float2) and then transformed and squared into FP64 running sums in the
+// image buffer.  b.grid work-groups at most (cadence128_grid, which sizes
+// the box buffer).
 bool fused128_supported(int n, int max_bw, int max_bh, int n_elem, int n_pol, int volt_type,
                         int ktaps, int max_cell_taps);
-epic_status launch_grid_box(const FusedBatch &b, int n_pol, int n_time, int volt_type, int chunk,
-                            int block, float2 *boxes, hipStream_t stream);
-epic_status launch_fused_fft128(const FusedBatch &b, int n_pol, int n_time, int chunk, int block,
-                                int flush, const float2 *boxes, const float2 *twiddles,
-                                hipStream_t stream);
+int cadence128_grid(int n_pol, int volt_type, int n_items);
+epic_status launch_cadence128(const FusedBatch &b, int n_pol, int n_time, int volt_type, int flush,
+                              float2 *boxes, size_t wg_floats, const float2 *twiddles, hipStream_t stream);
 
 // Incoherent combination of station images (k_combine.hip): device pointers
 // of up to kMaxCombine station images, passed by value as a kernel argument.

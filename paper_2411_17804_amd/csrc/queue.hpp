@@ -48,9 +48,11 @@ __device__ __forceinline__ int queue_claim(const ItemQueue &q, int home)
 // keeps thread 0 from overwriting it before every thread has read it, and the
 // one before the claim keeps the previous item's LDS reads ahead of the next
 // item's writes.
-// `slot` is one int of LDS that nothing else uses while the loop runs.
+// `slot` is one int of LDS; with `shared_slot` the item body may write that
+// word too, so a third barrier keeps its first write behind every read of
+// the claim.
 template <typename F>
-__device__ __forceinline__ void for_each_item(const ItemQueue &q, int *slot, F &&body)
+__device__ __forceinline__ void for_each_item(const ItemQueue &q, int *slot, F &&body, bool shared_slot = false)
 {
     const int home = static_cast<int>(blockIdx.x) & (kXcds - 1);
 #pragma unroll 1
@@ -58,7 +60,10 @@ __device__ __forceinline__ void for_each_item(const ItemQueue &q, int *slot, F &
         __syncthreads();
         if (threadIdx.x == 0) *slot = queue_claim(q, home);
         __syncthreads();
-        const int it = *slot;
+        // the same value in every lane: a scalar, so the item's tables are
+        // read with scalar loads into scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(*slot);
+        if (shared_slot) __syncthreads();
         if (it < 0) break;
         body(q.items[it]);
     }

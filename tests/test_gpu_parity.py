@@ -529,15 +529,26 @@ def test_graph_replays_match_eager(torch, prec):
             assert torch.equal(a, b.image), f"replay {rep} differs from the eager result"
 
 
-def test_fused128_box_batches(torch, monkeypatch):
-    # a box buffer of 3 MB holds one (station, channel) pair of 128 x 128
-    # footprint boxes per time block, so the three channels run as three
-    # batches per block; images must equal the one-batch run bit for bit
+def test_cadence128_mixed_supports(torch):
+    # 128 x 128 FP32 stations of three kernel supports in one call: the C3
+    # lattice (2048 elements, support 3), a 512-element subset with support 5
+    # and a 1024-element subset with the nearest-cell kernel.  Together their
+    # taps overflow the LDS, so the class splits into persistent launches;
+    # n_time = 40 leaves a ragged last block of samples.
+    import dataclasses
     from paper_2411_17804_amd import epic
-    say("image_cadence fp32 C3, one pair per box batch")
+    say("image_cadence fp32, 128 x 128 stations of supports 3, 5 and 1")
     cfg = W.make_config(3, chan_subset=[7, 100, 201], n_time=40, precision=W.FP32_FFT)
-    volts = [W.station_volts(cfg, 0)]
-    common, stations = station_objects(cfg, [to_device_volts(volts[0])])
+    base = cfg.stations[0]
+    rng = np.random.default_rng(5)
+    sub5 = np.sort(rng.choice(base.n_elem, 512, replace=False))
+    sub1 = np.sort(rng.choice(base.n_elem, 1024, replace=False))
+    cfg.stations = [base,
+                    dataclasses.replace(base, pos_m=base.pos_m[sub5], support=5, sigma_cells=5.0 / 6.0),
+                    dataclasses.replace(base, pos_m=base.pos_m[sub1], kernel_type=W.KERNEL_NEAREST,
+                                        support=1, sigma_cells=0.0)]
+    volts = [W.station_volts(cfg, s) for s in range(3)]
+    common, stations = station_objects(cfg, [to_device_volts(v) for v in volts])
     epic.cache_clear()
     epic.timing_reset()
     epic.timing_enable(True)
@@ -545,19 +556,23 @@ def test_fused128_box_batches(torch, monkeypatch):
     torch.cuda.synchronize()
     epic.timing_enable(False)
     used = epic.timing_report()
-    assert "fused_fft128_cadence" in used and "grid_box" in used, used   # the fused path ran
-    one = stations[0].image.clone()
-    err = oracle.image_error(to_complex(one), oracle_image(cfg, 0, volts[0]), 2)
-    say(f"  worst error {err.max():.2e}")
-    assert err.max() <= FP32_TOL
-    monkeypatch.setenv("EPIC_BOX_BUDGET_MB", "3")
-    epic.cache_clear()
-    stations[0].image.fill_(float("nan"))
-    for rep in range(3):                         # eager, then graph replays
+    launches = used.get("fused_fft128_cadence", (0, 0.0))[0]
+    say(f"  launches {used}")
+    assert 2 <= launches <= 3, used                # every station in the 128 x 128 class
+    assert set(used) == {"fused_fft128_cadence"}, used
+    first = [s.image.clone() for s in stations]
+    for s in range(3):
+        err = oracle.image_error(to_complex(first[s]), oracle_image(cfg, s, volts[s]), 2)
+        say(f"  station {s} (support {cfg.stations[s].support}) worst error {err.max():.2e}")
+        assert err.max() <= FP32_TOL
+    for rep in range(3):                         # graph replays
+        for s in stations:
+            s.image.fill_(float("nan"))
+        torch.cuda.synchronize()
         epic.image_cadence(common, stations)
         torch.cuda.synchronize()
-        assert torch.equal(one, stations[0].image), f"call {rep} differs"
-    monkeypatch.delenv("EPIC_BOX_BUDGET_MB")
+        for a, b in zip(first, stations):
+            assert torch.equal(a, b.image), f"replay {rep} differs"
     epic.cache_clear()
 
 
