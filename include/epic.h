@@ -171,10 +171,10 @@ epic_status image_cadence(const epic_common *common, const epic_station *station
  * and queue counters) is written into one fixed device array of 64 MiB that
  * the library holds on each GPU until the process ends, and the images
  * themselves carry the running sums.  Covered: stations with square grids up
- * to 64 x 64 (FP32 or split precision); anything else, or a call whose tables
- * exceed the 64 MiB (a 256-element station with a 3 x 3 kernel on a 64 x 64
- * grid needs about 37 KB per channel), returns EPIC_ERR_UNSUPPORTED before any
- * launch.  The tables are
+ * to 64 x 64 at FP32 and up to 128 x 128 in split precision (the persistent
+ * kernels); anything else, or a call whose tables exceed the 64 MiB (a
+ * 256-element station with a 3 x 3 kernel on a 64 x 64 grid needs about 37 KB
+ * per channel), returns EPIC_ERR_UNSUPPORTED before any launch.  The tables are
  * rebuilt on the host and copied on every call (nothing is cached).  The call
  * first waits for the earlier work on `stream`, which may still read the
  * array; calls on one GPU share the array, so calls that overlap on one GPU

@@ -122,9 +122,16 @@ std::string class_key(const Group &g, const epic_common *c)
     return o.str();
 }
 
+// The 128 x 128 split-precision class runs either its persistent kernel
+// (variant 0) or, per station, the composed path (variant 1): on gfx950 the
+// composed path's separate gridding, transform and squaring kernels can be
+// the faster of the two, so the autotuner measures both.
+bool runs_composed(const Group &g) { return g.path == kPathDft && g.n == 128 && g.tile.variant == 1; }
+
 // Kernel shapes a class can run (variant numbers the launcher understands).
 std::vector<int> variants_of(const Group &g, const epic_common *c)
 {
+    if (g.path == kPathDft && g.n == 128) return {0, 1};
     if (g.path == kPathFft && g.n == 64 && c->n_pol == 2) {
         std::vector<int> v;
         for (int k = 0; k < 2; ++k)
@@ -205,6 +212,8 @@ FusedBatch station_batch(const StationDev &sd, int n)
     b.max_cell_taps = sd.max_cell_taps;
     b.max_ktaps = sd.ktaps;
     b.max_side = std::max(sd.max_bw, sd.max_bh);
+    b.max_bw = sd.max_bw;
+    b.max_bh = sd.max_bh;
     return b;
 }
 
@@ -216,6 +225,8 @@ FusedBatch merged(const FusedBatch &a, const FusedBatch &b)
     m.max_cell_taps = std::max(a.max_cell_taps, b.max_cell_taps);
     m.max_ktaps = std::max(a.max_ktaps, b.max_ktaps);
     m.max_side = std::max(a.max_side, b.max_side);
+    m.max_bw = std::max(a.max_bw, b.max_bw);
+    m.max_bh = std::max(a.max_bh, b.max_bh);
     return m;
 }
 
@@ -238,6 +249,8 @@ void classify(const epic_common *c, const epic_station *st, int n, const PlanHan
     for (int i = 0; i < n; ++i) {
         const StationDev sd = make_station_dev(&st[i], plans[i]);
         const bool square = st[i].nx == st[i].ny && st[i].nx <= 64;
+        // the split-precision kernels also take 128 x 128 grids
+        const bool split_square = square || (st[i].nx == 128 && st[i].ny == 128);
         int path = -1, tiles = 0;
         if (st[i].nx == st[i].ny && c->precision == EPIC_FP32_FFT &&
             fused128_supported(st[i].nx, sd.max_bw, sd.max_bh, sd.n_elem, c->n_pol, c->volt_type,
@@ -245,12 +258,14 @@ void classify(const epic_common *c, const epic_station *st, int n, const PlanHan
             path = kPathFft128;
         } else if (square && c->precision == EPIC_FP32_FFT) {
             path = kPathFft;
-        } else if (square) {
+        } else if (split_square && c->precision != EPIC_FP32_FFT) {
             const FusedBatch one = station_batch(sd, st[i].nx);
             const int64_t vbytes = static_cast<int64_t>(sd.n_elem) * c->n_pol * (c->volt_type == EPIC_CI8 ? 2 : 8);
             if (vbytes % 4 == 0 && fused_dft_supported(one, c->n_pol, c->volt_type)) {
                 path = kPathDft;
-                tiles = tiles_for_side(one.max_side, one.n);
+                // one class for 128 x 128 (its kernel takes any footprint up
+                // to its limit); by footprint tiles below that
+                tiles = one.n == 128 ? 0 : tiles_for_side(one.max_side, one.n);
             }
         }
         if (path < 0) {
@@ -330,6 +345,10 @@ double item_cost(const StationDev &sd, int n_pol, int nt)
     return nt * (npix * sd.log2n * 2.0 * n_pol + 4.0 * sd.n_elem * sd.ktaps * n_pol);
 }
 
+// Work items per (station, channel): the 128 x 128 split-precision kernel
+// takes each half of the output rows as an item of its own.
+int parts_of(const Group &g) { return g.path == kPathDft && g.n == 128 ? 2 : 1; }
+
 // The persistent group's (station, channel) items in kXcds lists: longest
 // first onto the least loaded list, and each list ordered longest first.
 void build_queue_lists(Group &g, int n_chan, int n_time, int n_pol)
@@ -339,9 +358,12 @@ void build_queue_lists(Group &g, int n_chan, int n_time, int n_pol)
         int4 it;
     };
     std::vector<Item> all;
+    const int parts = parts_of(g);
     for (size_t k = 0; k < g.host_sds.size(); ++k)
         for (int ch = 0; ch < n_chan; ++ch)
-            all.push_back({item_cost(g.host_sds[k], n_pol, n_time), make_int4(static_cast<int>(k), ch, 0, 0)});
+            for (int part = 0; part < parts; ++part)
+                all.push_back({item_cost(g.host_sds[k], n_pol, n_time) / parts,
+                               make_int4(static_cast<int>(k), ch, part, 0)});
     std::stable_sort(all.begin(), all.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
     double load[kXcds] = {};
     std::vector<int4> lists[kXcds];
@@ -429,9 +451,17 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
     return EPIC_OK;
 }
 
-epic_status launch_group(const epic_common *c, const CadencePlan *p, const Group &g, hipStream_t stream)
+epic_status launch_group(const epic_common *c, const epic_station *st, const PlanHandle *plans, int device,
+                         const CadencePlan *p, const Group &g, hipStream_t stream)
 {
     const int flush = g.tile.flush;
+    if (runs_composed(g)) {
+        for (int i : g.members) {
+            epic_status s = cadence_composed(c, &st[i], plans[i], device, stream);
+            if (s != EPIC_OK) return s;
+        }
+        return EPIC_OK;
+    }
     if (g.path == kPathFft)
         return launch_fused_fft(g.batch, c->n_pol, c->n_time, c->volt_type, flush, p->twiddles[g.n], stream);
     if (g.path == kPathFft128)
@@ -449,7 +479,7 @@ epic_status enqueue_all(const epic_common *c, const epic_station *st, const Plan
     epic_status s = launch_queue_reset(p->counters, p->n_counters, stream);
     if (s != EPIC_OK) return s;
     for (const Group &g : p->groups) {
-        s = launch_group(c, p, g, stream);
+        s = launch_group(c, st, plans, device, p, g, stream);
         if (s != EPIC_OK) return s;
     }
     for (int i : p->composed) {
@@ -565,14 +595,14 @@ epic_status tune_cadence(const epic_common *c, const epic_station *st, int n,
                 if (s != EPIC_OK) return s;
                 // one untimed launch, then the better of two timed ones
                 s = launch_queue_reset(p->counters, p->n_counters, stream);
-                if (s == EPIC_OK) s = launch_group(c, p, p->groups[gi], stream);
+                if (s == EPIC_OK) s = launch_group(c, st, plans, device, p, p->groups[gi], stream);
                 if (s != EPIC_OK) return s;
                 float ms = 1e30f;
                 for (int rep = 0; rep < 2; ++rep) {
                     s = launch_queue_reset(p->counters, p->n_counters, stream);
                     if (s != EPIC_OK) return s;
                     EPIC_HIP_TRY(hipEventRecord(e0, stream));
-                    s = launch_group(c, p, p->groups[gi], stream);
+                    s = launch_group(c, st, plans, device, p, p->groups[gi], stream);
                     if (s != EPIC_OK) return s;
                     EPIC_HIP_TRY(hipEventRecord(e1, stream));
                     EPIC_HIP_TRY(hipEventSynchronize(e1));
@@ -686,14 +716,15 @@ epic_status run_cadence_noalloc(const epic_common *c, const epic_station *st, in
     classify(c, st, n, plans.data(), p.groups, p.composed);
     if (!p.composed.empty())
         return fail(EPIC_ERR_UNSUPPORTED, "image_cadence_noalloc: station " + std::to_string(p.composed.front()) +
-                                              " needs the composed path's workspaces; only square grids up to 64 "
-                                              "(FP32 or split precision) run without allocating");
+                                              " needs the composed path's workspaces; square grids up to 64 (FP32) "
+                                              "or 128 (split precision) run without allocating");
     std::vector<std::vector<float2>> tw_host;
     std::vector<std::vector<unsigned char>> rows_host;
     for (Group &g : p.groups) {
         if (g.path == kPathFft128)
             return fail(EPIC_ERR_UNSUPPORTED, "image_cadence_noalloc: 128 x 128 FP32 stations need the footprint-box "
-                                              "buffer; only square grids up to 64 run without allocating");
+                                              "buffer; FP32 runs without allocating on square grids up to 64");
+        if (runs_composed(g)) g.tile.variant = 0;   // the persistent kernel allocates nothing
         g.batch.variant = g.tile.variant;
         for (int i : g.members) g.host_sds.push_back(make_station_dev(&st[i], plans[i]));
         build_queue_lists(g, c->n_chan, c->n_time, c->n_pol);
@@ -731,7 +762,7 @@ epic_status run_cadence_noalloc(const epic_common *c, const epic_station *st, in
     s = launch_queue_reset(p.counters, p.n_counters, stream);
     if (s != EPIC_OK) return s;
     for (const Group &g : p.groups) {
-        s = launch_group(c, &p, g, stream);
+        s = launch_group(c, st, plans.data(), device, &p, g, stream);
         if (s != EPIC_OK) return s;
     }
     return EPIC_OK;

@@ -68,6 +68,7 @@ struct FusedBatch {
     int max_cell_taps = 0;
     int max_ktaps = 0;                 // max kernel taps per element (support^2)
     int max_side = 0;                  // max footprint-box side
+    int max_bw = 0, max_bh = 0;        // max footprint-box width, height
     int n = 0;                         // grid size (square) shared by the batch
 };
 
@@ -158,7 +159,7 @@ epic_status get_dft_tables(int n, int precision, int device, const void **out);
 epic_status get_dft_rows(int n, int precision, int device, const uint32_t **out);
 void fill_rows_any(int n, int precision, void *dst);
 
-// Fused split-precision cadence for square grids n in {16, 32, 64}: one
+// Fused split-precision cadence for square grids n in {16, 32, 64, 128}: one
 // work-group per (station, channel) item over the whole cadence, block sums of
 // `flush` samples added to FP64 running sums in the image buffer (accum.hpp),
 // which finally receives the mean products.
@@ -167,6 +168,11 @@ epic_status launch_fused_dft(const FusedBatch &b, int n_pol, int n_time, int vol
 
 // Whether launch_fused_dft covers a batch with these maxima.
 bool fused_dft_supported(const FusedBatch &b, int n_pol, int volt_type);
+// The same for 128 x 128 grids (k_fused_dft128.hip; items carry the half of
+// the output rows in z), reached through the two calls above.
+epic_status launch_fused_dft128(const FusedBatch &b, int n_pol, int n_time, int volt_type, int precision,
+                                int flush, const uint32_t *rows, hipStream_t stream);
+bool fused_dft128_supported(const FusedBatch &b, int n_pol, int volt_type);
 
 // Library-owned device workspace, per (device, stream, slot); grows on demand.
 epic_status get_workspace(int device, hipStream_t stream, int slot, size_t bytes, void **out);

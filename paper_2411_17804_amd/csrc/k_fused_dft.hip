@@ -36,24 +36,6 @@
 
 namespace epic {
 
-namespace {
-
-typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-
-template <int PREC>
-__device__ __forceinline__ uint32_t pack2(typename Split<PREC>::scalar a, typename Split<PREC>::scalar b)
-{
-    return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, a)) |
-           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, b)) << 16);
-}
-
-// (re, im) packed -> (re, -im): 2x2 block column for the real output part
-__device__ __forceinline__ uint32_t neg_hi(uint32_t w) { return w ^ 0x80000000u; }
-// (re, im) packed -> (im, re): 2x2 block column for the imaginary output part
-__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
-
-}  // namespace
-
 template <int N, int T>
 struct FusedDftShape {
     static constexpr int WAVES = N / 16;
@@ -61,10 +43,6 @@ struct FusedDftShape {
     static constexpr int PITCH = 16 * T + 4;      // LDS pitch of G^T rows and F_x rows (words)
     static constexpr int ROUNDS = (16 * T * 16 * T + BLOCK - 1) / BLOCK;   // gather rounds
 };
-
-// Voltage words per (element, pol) in LDS: int8 voltages are held as an exact
-// FP16 pair (one word), float voltages as a float pair (two words).
-constexpr int volt_words(int vt) { return vt == EPIC_CI8 ? 1 : 2; }
 
 inline size_t fused_dft_lds_bytes(int N, int T, int np, int vt, int n_elem, int max_cells)
 {
@@ -500,6 +478,7 @@ epic_status by_size(const FusedBatch &b, int n_pol, int volt_type, int n_time, i
 epic_status launch_fused_dft(const FusedBatch &b, int n_pol, int n_time, int volt_type,
                             int precision, int flush, const uint32_t *rows, hipStream_t stream)
 {
+    if (b.n == 128) return launch_fused_dft128(b, n_pol, n_time, volt_type, precision, flush, rows, stream);
     if (precision == EPIC_FP16_SPLIT)
         return by_size<EPIC_FP16_SPLIT>(b, n_pol, volt_type, n_time, flush, rows, stream);
     return by_size<EPIC_BF16_SPLIT>(b, n_pol, volt_type, n_time, flush, rows, stream);
@@ -507,6 +486,7 @@ epic_status launch_fused_dft(const FusedBatch &b, int n_pol, int n_time, int vol
 
 bool fused_dft_supported(const FusedBatch &b, int n_pol, int volt_type)
 {
+    if (b.n == 128) return fused_dft128_supported(b, n_pol, volt_type);
     if (b.n != 16 && b.n != 32 && b.n != 64) return false;
     const int64_t vbytes = static_cast<int64_t>(b.max_elem) * n_pol * (volt_type == EPIC_CI8 ? 2 : 8);
     if (vbytes % 4 != 0) return false;

@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "epic.h"
 
 namespace epic {
@@ -69,6 +71,29 @@ __device__ __forceinline__ floatx4_t mma3(typename Split<PREC>::vec8 ah, typenam
     acc = Split<PREC>::mfma(ah, bh, acc);
     return acc;
 }
+
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// Two split parts packed into 32 bits (a low, b high): one complex value
+// (re, im) of an A or B fragment.
+template <int PREC>
+__device__ __forceinline__ uint32_t pack2(typename Split<PREC>::scalar a, typename Split<PREC>::scalar b)
+{
+    return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, a)) |
+           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, b)) << 16);
+}
+
+// (re, im) packed -> (re, -im): 2x2 block column for the real output part
+__device__ __forceinline__ uint32_t neg_hi(uint32_t w) { return w ^ 0x80000000u; }
+// (re, im) packed -> (im, re): 2x2 block column for the imaginary output part
+__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
+// (re, im) packed -> (-re, -im)
+__device__ __forceinline__ uint32_t neg_both(uint32_t w) { return w ^ 0x80008000u; }
+
+// Voltage words per (element, pol) in the fused split kernels' LDS: int8
+// voltages are held as an exact FP16 pair (one word), float voltages as a
+// float pair (two words).
+constexpr int volt_words(int vt) { return vt == EPIC_CI8 ? 1 : 2; }
 
 // Power of two s with max_abs * s in [2^14, 2^15) (1 if max_abs is 0 or not
 // finite), so scaled FP16 parts cannot overflow and keep full relative

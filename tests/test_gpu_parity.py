@@ -385,8 +385,8 @@ def test_image_cadence_split(torch, case):
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_image_cadence_split_wide_box(torch, prec):
     # C3's lattice stretched to twice its extent along y: the footprint box
-    # (about 68 x 70 cells) is more than 4 tiles on both sides, so the 128 x 128
-    # split transform runs its 16-wave form on the footprint's tiles
+    # (about 68 x 70 cells) spans 5 tiles on both sides, the largest box the
+    # fused 128 x 128 split kernel takes
     p = W.FP16_SPLIT if prec == "fp16" else W.BF16_SPLIT
     cfg = W.make_config(3, chan_subset=[0, 255], n_time=6, precision=p)
     st = cfg.stations[0]
@@ -440,6 +440,10 @@ def test_composed_cadence_in_chunks(torch, monkeypatch, idx, prec):
     p = {"fp16": W.FP16_SPLIT, "bf16": W.BF16_SPLIT, "fp32": W.FP32_FFT}[prec]
     cfg = W.make_config(idx, chan_subset=[3, 200] if idx == 3 else [9], n_time=11, precision=p)
     st = cfg.stations[0]
+    if idx == 3:
+        # stretched along y to a footprint of about 100 rows: beyond the fused
+        # 128 x 128 split kernel, so the composed path runs
+        st.pos_m = st.pos_m * np.array([1.0, 3.0])
     per_sample = cfg.n_chan * cfg.n_pol * st.nx * st.ny * 8
     say(f"image_cadence C{idx} {prec} in chunks of {max(1, (2 << 20) // per_sample)} samples")
     v = W.station_volts(cfg, 0)
@@ -458,13 +462,13 @@ def test_composed_cadence_in_chunks(torch, monkeypatch, idx, prec):
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_footprint_pruned_transform_matches_dense(torch, prec):
-    # the cadence's split transform sums only the footprint's tiles; the dense
-    # transform of the same gridded planes (zero outside the footprint) must
-    # give the same images bit for bit
+    # the composed cadence's split transform (256 x 256 grids take that path)
+    # sums only the footprint's tiles; the dense transform of the same gridded
+    # planes (zero outside the footprint) must give the same images bit for bit
     from paper_2411_17804_amd import epic
-    say(f"pruned split transform vs dense, C3 {prec}")
+    say(f"pruned split transform vs dense, C5 {prec}")
     p = W.FP16_SPLIT if prec == "fp16" else W.BF16_SPLIT
-    cfg = W.make_config(3, chan_subset=[0, 77, 255], n_time=10, precision=p)
+    cfg = W.make_config(5, chan_subset=[0, 127], n_time=3, precision=p)
     st = cfg.stations[0]
     v = W.station_volts(cfg, 0)
     common, (station,) = station_objects(cfg, [to_device_volts(v)], p)
@@ -565,6 +569,51 @@ def test_cadence128_mixed_supports(torch):
         err = oracle.image_error(to_complex(first[s]), oracle_image(cfg, s, volts[s]), 2)
         say(f"  station {s} (support {cfg.stations[s].support}) worst error {err.max():.2e}")
         assert err.max() <= FP32_TOL
+    for rep in range(3):                         # graph replays
+        for s in stations:
+            s.image.fill_(float("nan"))
+        torch.cuda.synchronize()
+        epic.image_cadence(common, stations)
+        torch.cuda.synchronize()
+        for a, b in zip(first, stations):
+            assert torch.equal(a, b.image), f"replay {rep} differs"
+    epic.cache_clear()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_split128_one_launch_mixed_supports(torch, prec):
+    # 128 x 128 split-precision stations of supports 3, 5 and 1 (the C3
+    # lattice and two subsets of it) in one persistent launch; n_time = 20
+    # ends on a partial block of samples
+    import dataclasses
+    from paper_2411_17804_amd import epic
+    p = W.FP16_SPLIT if prec == "fp16" else W.BF16_SPLIT
+    say(f"image_cadence {prec}, 128 x 128 stations of supports 3, 5 and 1")
+    cfg = W.make_config(3, chan_subset=[0, 131, 255], n_time=20, precision=p)
+    base = cfg.stations[0]
+    rng = np.random.default_rng(7)
+    sub5 = np.sort(rng.choice(base.n_elem, 512, replace=False))
+    sub1 = np.sort(rng.choice(base.n_elem, 1024, replace=False))
+    cfg.stations = [base,
+                    dataclasses.replace(base, pos_m=base.pos_m[sub5], support=5, sigma_cells=5.0 / 6.0),
+                    dataclasses.replace(base, pos_m=base.pos_m[sub1], kernel_type=W.KERNEL_NEAREST,
+                                        support=1, sigma_cells=0.0)]
+    volts = [W.station_volts(cfg, s) for s in range(3)]
+    common, stations = station_objects(cfg, [to_device_volts(v) for v in volts], p)
+    epic.cache_clear()
+    epic.timing_reset()
+    epic.timing_enable(True)
+    epic.image_cadence(common, stations)
+    torch.cuda.synchronize()
+    epic.timing_enable(False)
+    used = epic.timing_report()
+    say(f"  launches {used}")
+    assert set(used) == {"fused_dft128_cadence"} and used["fused_dft128_cadence"][0] == 1, used
+    first = [s.image.clone() for s in stations]
+    for s in range(3):
+        err = oracle.image_error(to_complex(first[s]), oracle_image(cfg, s, volts[s]), 2)
+        say(f"  station {s} (support {cfg.stations[s].support}) worst error {err.max():.2e}")
+        assert err.max() <= SPLIT_TOL[prec]
     for rep in range(3):                         # graph replays
         for s in stations:
             s.image.fill_(float("nan"))

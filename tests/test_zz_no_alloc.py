@@ -25,11 +25,14 @@ def test_noalloc_matches_image_cadence(prec):
     from paper_2411_17804_amd import epic
     epic.load()
     name = "fp32" if prec == W.FP32_FFT else "fp16-split"
-    # first call: a hierarchical batch of the stations with grids up to 64 (3
-    # stations, 6 channels, ragged cadence); second call: smaller (one
-    # station, 2 channels, fewer samples)
+    # first call: a hierarchical batch (3 stations, 6 channels, ragged
+    # cadence) of grids up to 64, and in split precision one 128 x 128 station
+    # too (its persistent kernel); second call: smaller (one station, 2
+    # channels, fewer samples)
     big = W.make_config(4, chan_subset=[0, 9, 20, 33, 47, 63], n_time=41, n_stations=24, precision=prec)
-    big.stations = [s for s in big.stations if s.nx <= 64][:3]
+    small_grids = [s for s in big.stations if s.nx <= 64]
+    big.stations = small_grids[:3] if prec == W.FP32_FFT else \
+        small_grids[:2] + [s for s in big.stations if s.nx == 128][:1]
     small = W.make_config(2, chan_subset=[5, 600], n_time=23, precision=prec)
     free_after_first = None
     for k, cfg in enumerate((big, small)):
