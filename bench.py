@@ -53,18 +53,33 @@ def log(msg):
 
 # Sources of each timed kernel: a counter summary under profiles/ is only used
 # while the hash of these files matches the one recorded with the counters.
+_PERSISTENT = ["accum.hpp", "queue.hpp", "lds_sync.hpp", "volts.hpp"]
 KERNEL_SOURCES = {
-    "fused_fft_cadence": ["k_fused.hip", "fft_lds.hpp", "volts.hpp"],
-    "fused_dft_cadence": ["k_fused_dft.hip", "mfma_split.hpp", "volts.hpp"],
+    "fused_fft_cadence": ["k_fused.hip", "fft_lds.hpp"] + _PERSISTENT,
+    "fused_fft128_cadence": ["k_fused128.hip", "fft_lds.hpp"] + _PERSISTENT,
+    "fused_dft_cadence": ["k_fused_dft.hip", "mfma_split.hpp"] + _PERSISTENT,
+    "fused_dft128_cadence": ["k_fused_dft128.hip", "mfma_split.hpp"] + _PERSISTENT,
+    "dft2_tiles128": ["k_dft.hip", "mfma_split.hpp"],
 }
 
 
-def measured_traffic(kernel: str, workload: str, chunk):
+def source_hash(kernel: str):
+    """First 16 hex digits of the SHA-256 of a timed kernel's source files."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        p = os.path.join(ROOT, "paper_2411_17804_amd", "csrc", f)
+        if not os.path.exists(p):
+            return None
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, flush):
     """HBM bytes per launch from profiles/<kernel>_<workload>_hbm_bytes.md, or
     None if there is no summary, the kernel changed since it was taken, or it
-    was taken at another time-chunk length (the partial-sum writes scale with
-    1/chunk)."""
-    import hashlib
+    was taken with another flush interval (the FP64 running-sum updates scale
+    with 1/flush)."""
     import re
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_bytes.md")
     if kernel not in KERNEL_SOURCES or not os.path.exists(path):
@@ -72,16 +87,12 @@ def measured_traffic(kernel: str, workload: str, chunk):
     text = open(path).read()
     m_b = re.search(r"traffic_bytes_per_launch: (\d+)", text)
     m_h = re.search(r"source_sha256_16: ([0-9a-f]+)", text)
-    m_c = re.search(r"chunk: (\d+)", text)
-    if not (m_b and m_h and m_c) or chunk is None or int(m_c.group(1)) != chunk:
+    m_f = re.search(r"flush: (\d+|none)", text)
+    if not (m_b and m_h and m_f):
         return None
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES[kernel]:
-        p = os.path.join(ROOT, "paper_2411_17804_amd", "csrc", f)
-        if not os.path.exists(p):
-            return None
-        h.update(open(p, "rb").read())
-    return int(m_b.group(1)) if h.hexdigest()[:16] == m_h.group(1) else None
+    if m_f.group(1) != "none" and (flush is None or int(m_f.group(1)) != flush):
+        return None
+    return int(m_b.group(1)) if source_hash(kernel) == m_h.group(1) else None
 
 
 def box_sides(cfg, st):
@@ -153,9 +164,8 @@ ROOFLINE_KERNELS = {
     # FP32 path, fused: gridding, transform, products and accumulation in one kernel
     "fused_fft_cadence": ("alu", lambda s: s.nx <= 64, lambda c, st, n: _fft_work(c, st)),
     "fused_cadence": ("alu", lambda s: s.nx <= 128, lambda c, st, n: _fft_work(c, st)),
-    # FP32 128 x 128 transform-and-square over gridded boxes (gridding in grid_box)
-    "fused_fft128_cadence": ("alu", lambda s: s.nx == 128,
-                             lambda c, st, n: _fft_work(c, st, with_grid=False)),
+    # FP32 128 x 128: gridding into footprint boxes, transform, products
+    "fused_fft128_cadence": ("alu", lambda s: s.nx == 128, lambda c, st, n: _fft_work(c, st)),
     # split precision, fused (N <= 64) and the 128 x 128 plane transform
     "fused_dft_cadence": ("mfma", lambda s: s.nx <= 64, lambda c, st, n: _split_work(c, st)),
     "fused_dft128_cadence": ("mfma", lambda s: s.nx == 128, lambda c, st, n: _split_work(c, st)),
@@ -171,7 +181,7 @@ PEAKS = {"alu": (PEAK_FP32_VALU_TFLOPS, "TFLOP/s"), "mfma": (PEAK_FP16_MFMA_TFLO
          "hbm": (PEAK_HBM_GBS, "GB/s")}
 
 
-def roofline(cfg, kern, steps, prec, chunks, traffic_ok):
+def roofline(cfg, kern, steps, prec, tuned, traffic_ok):
     """Roofline of the kernel that takes the most time per step: its
     algorithmic work per launch (the work of the stations it serves per
     cadence, divided by its launches per cadence) over its average launch
@@ -191,13 +201,16 @@ def roofline(cfg, kern, steps, prec, chunks, traffic_ok):
     peak, unit = PEAKS[bound]
     scale = 1e9 if unit == "GB/s" else 1e12
     achieved = work / (avg_ms / 1e3) / scale
-    prefix = {"fused_fft_cadence": "fft_", "fused_dft_cadence": "dft_"}.get(dom_name)
-    cls = sorted(v for k, v in chunks.items() if prefix and k.startswith(prefix) and ":" not in k)
-    chunk = cls[0] if cls and len(set(cls)) == 1 else None
+    # the flush interval of the kernel's classes (the tuned value, else the default 16)
+    prefix = {"fused_fft_cadence": "fft_n", "fused_fft128_cadence": "fft128_",
+              "fused_dft_cadence": "dft_n", "fused_dft128_cadence": "dft_n128"}.get(dom_name)
+    fl = sorted({v for k, v in tuned.items() if prefix and k.startswith(prefix) and ":" not in k
+                 and (dom_name != "fused_dft_cadence" or not k.startswith("dft_n128"))})
+    flush = fl[0] if len(fl) == 1 else (16 if not fl else None)
     out.update({"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": unit,
                 "frac": round(achieved / peak, 4),
-                "traffic": measured_traffic(dom_name, f"C{cfg.index}", chunk) if traffic_ok else None,
-                "work_per_launch": work, "chunk": chunk})
+                "traffic": measured_traffic(dom_name, f"C{cfg.index}", flush) if traffic_ok else None,
+                "work_per_launch": work, "flush": flush if prefix else None})
     if bound == "alu":
         out["flop_per_pixel_sample"] = round(
             work * per_step / sum(s.nx * s.ny * cfg.n_chan * cfg.n_time for s in served), 2)
@@ -215,18 +228,18 @@ def time_precision(cfg, prec_name, common, stations, steps, warmup, autotune):
     import torch
     from paper_2411_17804_amd import epic
     tune_file = os.environ["EPIC_TUNE_CACHE"]
-    chunks = {}
+    tuned = {}
     if autotune:
         t_tune = time.time()
         epic.autotune(common, stations)
         log(f"{prec_name}: autotune done in {time.time() - t_tune:.1f} s")
         if os.path.exists(tune_file):
-            # "class variant chunk" lines
+            # "class variant flush" lines
             for line in open(tune_file):
                 parts = line.split()
                 if len(parts) == 3:
-                    chunks[parts[0]] = int(parts[2])
-                    chunks[parts[0] + ":variant"] = int(parts[1])
+                    tuned[parts[0]] = int(parts[2])
+                    tuned[parts[0] + ":variant"] = int(parts[1])
     for _ in range(warmup):
         epic.image_cadence(common, stations)
     torch.cuda.synchronize()
@@ -242,8 +255,8 @@ def time_precision(cfg, prec_name, common, stations, steps, warmup, autotune):
     torch.cuda.synchronize()
     epic.timing_enable(False)
     kern = epic.timing_report()
-    log(f"{prec_name}: {ms:.2f} ms/step; tuned {chunks}; kernels {kern}")
-    return ms, kern, chunks
+    log(f"{prec_name}: {ms:.2f} ms/step; tuned {tuned}; kernels {kern}")
+    return ms, kern, tuned
 
 
 def cpu_sample(cfg):
@@ -389,16 +402,16 @@ def main():
                               dtype=torch.float32, device=dev)
             stations.append(epic.Station(st.pos_m, st.nx, st.ny, st.kernel_type, st.support,
                                          st.sigma_cells, volts=vdev[s], image=img))
-        ms, kern, chunks = time_precision(cfg, p, common, stations, args.steps, args.warmup,
-                                          not args.no_autotune)
+        ms, kern, tuned = time_precision(cfg, p, common, stations, args.steps, args.warmup,
+                                         not args.no_autotune)
         value = pix / (ms / 1e3)
         results[p] = {
             "value": value, "ms_per_step": ms,
             "realtime_factor": (cfg.n_time * 25e-6) / (ms / 1e3),
-            "roofline": roofline(cfg, kern, args.steps, p, chunks, full),
+            "roofline": roofline(cfg, kern, args.steps, p, tuned, full),
             "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()},
             "launches_per_step": round(sum(v[0] for v in kern.values()) / args.steps, 1),
-            "tuned": chunks,
+            "tuned": tuned,
         }
         # keep the sampled stations' images for the error check; free the rest
         images[p] = {s: stations[s].image[torch.as_tensor(ch, device=dev)].cpu().numpy()

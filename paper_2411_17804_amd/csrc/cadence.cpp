@@ -72,6 +72,11 @@ constexpr int kPathFft = 0, kPathDft = 1, kPathFft128 = 2;
 // of the mean; in the 128 x 128 class it is also the gridding block).
 constexpr int kDefaultFlush = 16;
 const int kFlushCandidates[] = {8, 16};
+// Samples the 128 x 128 FP32 kernel grids at a time (its variants): each
+// work-group's boxes for one sample take about 100 KB on the largest
+// stations, so blocks of a few samples stay in the L2 between gridding and
+// transform.
+const int kGridBlocks128[] = {2, 4, 1, 16};
 
 struct Tile {
     int variant = 0;
@@ -122,6 +127,8 @@ std::string class_key(const Group &g, const epic_common *c)
     return o.str();
 }
 
+int grid_block128(const Group &g) { return kGridBlocks128[g.tile.variant & 3]; }
+
 // The 128 x 128 split-precision class runs either its persistent kernel
 // (variant 0) or, per station, the composed path (variant 1): on gfx950 the
 // composed path's separate gridding, transform and squaring kernels can be
@@ -132,6 +139,7 @@ bool runs_composed(const Group &g) { return g.path == kPathDft && g.n == 128 && 
 std::vector<int> variants_of(const Group &g, const epic_common *c)
 {
     if (g.path == kPathDft && g.n == 128) return {0, 1};
+    if (g.path == kPathFft128) return {0, 1, 2, 3};
     if (g.path == kPathFft && g.n == 64 && c->n_pol == 2) {
         std::vector<int> v;
         for (int k = 0; k < 2; ++k)
@@ -396,10 +404,10 @@ epic_status build_plan(const epic_common *c, const epic_station *st, int n, cons
         n_counters += kXcds;
         g.batch.n_items = static_cast<int>(g.host_items.size());
         if (g.path == kPathFft128) {
-            // each work-group grids one block of `flush` samples at a time
-            // into its own boxes; the classes run one after another, so one
-            // buffer serves them all
-            const int block = std::min(g.tile.flush, c->n_time);
+            // each work-group grids a block of samples at a time into its own
+            // boxes; the classes run one after another, so one buffer serves
+            // them all
+            const int block = std::min(grid_block128(g), c->n_time);
             size_t wg = 0;
             for (const StationDev &sd : g.host_sds)
                 wg = std::max(wg, static_cast<size_t>(block) * c->n_pol * sd.max_bw * sd.max_bh);
@@ -465,8 +473,8 @@ epic_status launch_group(const epic_common *c, const epic_station *st, const Pla
     if (g.path == kPathFft)
         return launch_fused_fft(g.batch, c->n_pol, c->n_time, c->volt_type, flush, p->twiddles[g.n], stream);
     if (g.path == kPathFft128)
-        return launch_cadence128(g.batch, c->n_pol, c->n_time, c->volt_type, flush, p->boxes, g.wg_box_floats,
-                                 p->twiddles[g.n], stream);
+        return launch_cadence128(g.batch, c->n_pol, c->n_time, c->volt_type, flush, grid_block128(g), p->boxes,
+                                 g.wg_box_floats, p->twiddles[g.n], stream);
     return launch_fused_dft(g.batch, c->n_pol, c->n_time, c->volt_type, c->precision, flush,
                             p->rows[g.n], stream);
 }

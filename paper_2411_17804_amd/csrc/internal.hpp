@@ -283,15 +283,15 @@ bool fused_fft_supported(const FusedBatch &b, int n_pol, int volt_type);
 
 // The FP32 cadence for 128 x 128 grids (k_fused128.hip): a persistent
 // kernel over the batch's (station, channel) items, each over the whole
-// cadence in blocks of `flush` samples, gridded into the work-group's
-// footprint boxes (boxes + blockIdx * wg_floats; [flush][pol][max_bh][max_bw]
-// float2) and then transformed and squared into FP64 running sums in the
-// image buffer.  b.grid work-groups at most (cadence128_grid, which sizes
-// the box buffer).
+// cadence; `gblock` samples at a time are gridded into the work-group's
+// footprint boxes (boxes + blockIdx * wg_floats; [gblock][pol][max_bh][max_bw]
+// float2) and then transformed and squared, and block sums of `flush`
+// samples go to FP64 running sums in the image buffer.  b.grid work-groups at
+// most (cadence128_grid, which sizes the box buffer).
 bool fused128_supported(int n, int max_bw, int max_bh, int n_elem, int n_pol, int volt_type,
                         int ktaps, int max_cell_taps);
 int cadence128_grid(int n_pol, int volt_type, int n_items);
-epic_status launch_cadence128(const FusedBatch &b, int n_pol, int n_time, int volt_type, int flush,
+epic_status launch_cadence128(const FusedBatch &b, int n_pol, int n_time, int volt_type, int flush, int gblock,
                               float2 *boxes, size_t wg_floats, const float2 *twiddles, hipStream_t stream);
 
 // Incoherent combination of station images (k_combine.hip): device pointers

@@ -348,13 +348,15 @@ __device__ __forceinline__ void transform_sample(const StationDev &sd, const Cha
 }
 
 // The persistent kernel: (station, channel) items from the work queue, each
-// over the whole cadence in blocks of `flush` samples (grid phase, then
-// transform phase); the work-group's boxes are its slice of `boxes`
-// (wg_floats float2 each, blocks of flush samples x pols x the class's
-// largest box).
+// over the whole cadence in blocks of `flush` samples whose sums go to the
+// FP64 running sums, each block gridded and transformed `gblock` samples at a
+// time (grid phase, then transform phase); the work-group's boxes are its
+// slice of `boxes` (wg_floats float2 each: gblock samples x pols x the
+// class's largest box).  A small gblock keeps each work-group's boxes in the
+// L2 between the two phases.
 template <int NP, int VT>
 __global__ __launch_bounds__(kF128Block) void k_cadence128(const StationDev *__restrict__ sds, ItemQueue q,
-                                                          int n_time, int flush, int max_ntap,
+                                                          int n_time, int flush, int gblock, int max_ntap,
                                                           float2 *__restrict__ boxes, size_t wg_floats,
                                                           const float2 *__restrict__ twg)
 {
@@ -377,11 +379,6 @@ __global__ __launch_bounds__(kF128Block) void k_cadence128(const StationDev *__r
 #pragma unroll 1
         for (int t0 = 0; t0 < n_time; t0 += flush) {
             const int t1 = min(n_time, t0 + flush);
-            grid_phase<NP, VT>(sd, cp, c, n_time, t0, t1, max_ntap, lds, box);
-            // the boxes (global memory) are visible to the whole work-group
-            // and the LDS is free for the plane
-            __syncthreads();
-            // the block's sums (registers that are free during the grid phase)
             float acc[4][8][NQ];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -390,9 +387,17 @@ __global__ __launch_bounds__(kF128Block) void k_cadence128(const StationDev *__r
 #pragma unroll
                     for (int qq = 0; qq < NQ; ++qq) acc[r][k][qq] = 0.f;
 #pragma unroll 1
-            for (int t = t0; t < t1; ++t)
-                transform_sample<NP>(sd, cp, box + static_cast<size_t>(t - t0) * NP * bplane, bplane, lds,
-                                     twg, cgrp, acc);
+            for (int g0 = t0; g0 < t1; g0 += gblock) {
+                const int g1 = min(t1, g0 + gblock);
+                grid_phase<NP, VT>(sd, cp, c, n_time, g0, g1, max_ntap, lds, box);
+                // the boxes (global memory) are visible to the whole work-group
+                // and the LDS is free for the plane
+                __syncthreads();
+#pragma unroll 1
+                for (int t = g0; t < g1; ++t)
+                    transform_sample<NP>(sd, cp, box + static_cast<size_t>(t - g0) * NP * bplane, bplane, lds,
+                                         twg, cgrp, acc);
+            }
             // the block's sums go to the FP64 running sums, a few entries at a time
             int lt;
             asm volatile("v_mov_b32 %0, %1" : "=v"(lt) : "v"(static_cast<int>(threadIdx.x)));
@@ -456,7 +461,7 @@ int cadence128_grid(int n_pol, int volt_type, int n_items)
     return persistent_grid(kernel_for(n_pol, volt_type), kF128Block, kF128Lds, n_items);
 }
 
-epic_status launch_cadence128(const FusedBatch &b, int n_pol, int n_time, int volt_type, int flush,
+epic_status launch_cadence128(const FusedBatch &b, int n_pol, int n_time, int volt_type, int flush, int gblock,
                               float2 *boxes, size_t wg_floats, const float2 *twiddles, hipStream_t stream)
 {
     const void *k = kernel_for(n_pol, volt_type);
@@ -467,7 +472,7 @@ epic_status launch_cadence128(const FusedBatch &b, int n_pol, int n_time, int vo
     KernelTimer timer("fused_fft128_cadence", stream);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(grid), dim3(kF128Block), kF128Lds, stream, b.sds, b.q, n_time, flush,
-                           max_ntap, boxes, wg_floats, twiddles);
+                           gblock, max_ntap, boxes, wg_floats, twiddles);
     };
     if (n_pol == 2 && volt_type == EPIC_CI8) go(k_cadence128<2, EPIC_CI8>);
     else if (n_pol == 2) go(k_cadence128<2, EPIC_CF32>);

@@ -538,11 +538,11 @@ def test_cadence128_mixed_supports(torch):
     # lattice (2048 elements, support 3), a 512-element subset with support 5
     # and a 1024-element subset with the nearest-cell kernel.  Together their
     # taps overflow the LDS, so the class splits into persistent launches;
-    # n_time = 40 leaves a ragged last block of samples.
+    # n_time = 37 leaves a ragged last block of samples and of gridding.
     import dataclasses
     from paper_2411_17804_amd import epic
     say("image_cadence fp32, 128 x 128 stations of supports 3, 5 and 1")
-    cfg = W.make_config(3, chan_subset=[7, 100, 201], n_time=40, precision=W.FP32_FFT)
+    cfg = W.make_config(3, chan_subset=[7, 100, 201], n_time=37, precision=W.FP32_FFT)
     base = cfg.stations[0]
     rng = np.random.default_rng(5)
     sub5 = np.sort(rng.choice(base.n_elem, 512, replace=False))
