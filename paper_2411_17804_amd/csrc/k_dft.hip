@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_dft_pass(const float2 *__restrict__ in,
     constexpr int KS = N / 16;            // K-steps
     constexpr int MTW = (MT + 3) / 4;     // M-tiles per wave
     constexpr int JP = N + 4;             // LDS pitch (packed complex) per column
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *lhi = lds;                  // [CB][JP] (re, im) hi parts
     uint32_t *llo = lds + CB * JP;        // [CB][JP] lo parts
     __shared__ float red[4];
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_dft2_plane(const float2 *__restrict__ i
     constexpr int MTW = (MT + 3) / 4;     // M-tiles per wave
     constexpr int JP = N + 4;             // LDS pitch (packed complex) per column
     constexpr int PER = N * N / 256;      // plane values per thread
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *lhi = lds;                  // [N][JP]: column c, transform index j
     uint32_t *llo = lds + N * JP;
     __shared__ float red[4];
@@ -464,7 +464,7 @@ void k_dft2_tiles128(const float2 *__restrict__ in, float2 *__restrict__ out,
     constexpr int SLOTS = NT / 256;       // tiles read at once (256 threads per tile)
     constexpr int MAX_TILES = NW == 16 ? 64 : 32;
     constexpr int PER = MAX_TILES / SLOTS;
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     __shared__ float red[NW];
     __shared__ int redi[4][NW];
     __shared__ float2 ph[N];              // the shift-theorem factors

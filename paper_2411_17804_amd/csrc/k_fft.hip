@@ -24,7 +24,7 @@ __global__ __launch_bounds__(BLOCK) void k_fft2_lds(const float2 *__restrict__ i
                                                     const float2 *__restrict__ twy)
 {
     constexpr int P = NX + 1;
-    extern __shared__ float2 lds[];
+    extern __shared__ __align__(16) float2 lds[];
     float2 *buf = lds;
     float2 *tx = lds + NY * P;
     float2 *ty = tx + NX;
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(BLOCK) void k_fft_rows(const float2 *__restrict__ i
                                                     int items_per_chan, int ny)
 {
     constexpr int P = NX + 1;
-    extern __shared__ float2 lds[];
+    extern __shared__ __align__(16) float2 lds[];
     float2 *buf = lds;
     float2 *t = lds + ROWS * P;
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * ROWS;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(BLOCK) void k_fft_cols(float2 *__restrict__ data,
                                                     int items_per_chan)
 {
     constexpr int P = COLS + 1;   // LDS holds the tile transposed-free: [y][col]
-    extern __shared__ float2 lds[];
+    extern __shared__ __align__(16) float2 lds[];
     float2 *buf = lds;
     float2 *t = lds + NY * P;
     constexpr int TILES = NX / COLS;

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(FusedShape<N>::BLOCK) void k_fused_fft(const Statio
     constexpr int NPIX = N * N;
     constexpr int NQ = NP == 2 ? 4 : 1;
     constexpr int PXT = (NPIX + BLOCK - 1) / BLOCK;   // pixels per thread
-    extern __shared__ float2 lds[];
+    extern __shared__ __align__(16) float2 lds[];
     float2 *buf = lds;                       // [NP][N][P]
     float2 *tw = lds + NP * PLANE;           // [N]
 
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kFused64Block) void k_fused_fft64(const StationDev 
     constexpr int PLANE = 64 * 64;
     constexpr int NQ = NP == 2 ? 4 : 1;
     constexpr int BLOCK = kFused64Block;
-    extern __shared__ float2 lds[];
+    extern __shared__ __align__(16) float2 lds[];
     float2 *buf = lds;                                   // [NP][PLANE], swizzled
     float2 *gb = buf + NP * PLANE;                       // [NP][max_cells] gathered box
     float2 *vf = gb + NP * max_cells;                    // [2][max_elem][NP] voltages
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(kFused64x2Block) void k_fused_fft64x2(const Station
     constexpr int BLOCK = kFused64x2Block;
     constexpr int ROUNDS = kFused64Rounds * kFused64Block / BLOCK;
     constexpr int PREFETCH = kFused64Prefetch * kFused64Block / BLOCK;
-    extern __shared__ float2 lds[];
+    extern __shared__ __align__(16) float2 lds[];
     float2 *buf = lds;                                   // [2][PLANE], swizzled
     float2 *vf = buf + NP * PLANE;                       // [2][max_elem][2] voltages
     Tap *taps_l = reinterpret_cast<Tap *>(vf + 2 * NP * max_elem);

@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kF128Block) void k_cadence128(const StationDev *__r
     constexpr int N = 128;
     constexpr int PLANE = N * N;
     constexpr int NQ = NP == 2 ? 4 : 1;
-    extern __shared__ float2 lds[];
+    extern __shared__ __align__(16) float2 lds[];
     // the queue slot: the first word of the hold area, which no item uses
     // while the claim is read
     int *slot = reinterpret_cast<int *>(lds + PLANE);

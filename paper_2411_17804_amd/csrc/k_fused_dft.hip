@@ -71,7 +71,7 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(F
     constexpr int NQ = NP == 2 ? 4 : 1;
     constexpr int NT = N / 16;                      // k_x tiles
     constexpr int GPLANE = 16 * T * PITCH;          // words per pol of G^T
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *gbh = lds;                            // [NP][16T][PITCH] G^T hi (re, im)
     uint32_t *gbl = gbh + NP * GPLANE;              // lo
     uint32_t *txh = gbl + NP * GPLANE;              // [N][PITCH] F[k_x][x0 + x] hi (re, im)
@@ -183,6 +183,14 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(F
             reduce_max(m, 0);
         }
 
+        lds_barrier();
+
+        int cur = 0;
+        // blocks of `flush` samples: their sums go to the FP64 running sums
+        // after the block's loop, so that code stays out of the sample loop
+#pragma unroll 1
+        for (int t0 = t_begin; t0 < t_end; t0 += flush) {
+        const int t1 = min(t_end, t0 + flush);
         float acc[NT][4][NQ];
 #pragma unroll
         for (int a = 0; a < NT; ++a)
@@ -190,10 +198,7 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(F
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) acc[a][i][q] = 0.f;
-        lds_barrier();
-
-        int cur = 0;
-        for (int t = t_begin; t < t_end; ++t) {
+        for (int t = t0; t < t1; ++t) {
             const bool has_next = t + 1 < t_end;
             // ---- 1. grid the footprint box, scale, split -> G^T in LDS -------
             float vmax = 0.f;
@@ -395,24 +400,21 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(F
                     }
                 }
             }
-            // a block of samples ends: its sums go to the FP64 running sums
-            if (block_ends(t, n_time, flush)) {
-                int px0;   // opaque: keeps the addresses from being hoisted
-                asm volatile("v_mov_b32 %0, %1" : "=v"(px0) : "v"((16 * wave + 4 * g) * N + r16));
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int pix = px0 + i * N + 16 * nt;
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q) {
-                            sums_add(sums, q, pix, acc[nt][i][q], t < flush);
-                            acc[nt][i][q] = 0.f;
-                        }
-                        asm volatile("" ::: "memory");
-                    }
-            }
             cur ^= 1;
+        }
+        {
+            int px0;   // opaque: keeps the addresses from being hoisted
+            asm volatile("v_mov_b32 %0, %1" : "=v"(px0) : "v"((16 * wave + 4 * g) * N + r16));
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int pix = px0 + i * N + 16 * nt;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) sums_add(sums, q, pix, acc[nt][i][q], t0 == t_begin);
+                    asm volatile("" ::: "memory");
+                }
+        }
         }
         sums_settle();
         const double inv_n = 1.0 / static_cast<double>(n_time);

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
     constexpr int NQ = NP == 2 ? 4 : 1;
     constexpr int VW = volt_words(VT);
     constexpr int VPRE = VoltPre<VT>::value;
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     const int gplane = d.gx * d.pg;
     uint32_t *gbh = lds;                               // [NP][gx][pg] G^T hi (re, im)
     uint32_t *gbl = gbh + NP * gplane;                 // lo

@@ -69,11 +69,13 @@ __device__ __forceinline__ void for_each_item(const ItemQueue &q, int *slot, F &
     }
 }
 
+// The claim slot takes 16 bytes of static LDS, so that the kernels'
+// dynamic LDS after it stays 16-byte aligned for their 128-bit accesses.
 template <typename F>
 __device__ __forceinline__ void for_each_item(const ItemQueue &q, F &&body)
 {
-    __shared__ int s_item;
-    for_each_item(q, &s_item, body);
+    __shared__ __align__(16) int s_item[4];
+    for_each_item(q, s_item, body);
 }
 
 }  // namespace epic
