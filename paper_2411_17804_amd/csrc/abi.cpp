@@ -58,6 +58,11 @@ StationDev epic::make_station_dev(const epic_station *s, const PlanHandle &p)
     d.max_cell_taps = p.max_cell_taps;
     d.max_bw = p.max_bw;
     d.max_bh = p.max_bh;
+    d.band_taps = p.band_taps;
+    d.band_row = p.band_row;
+    d.band_slot = p.band_slot;
+    d.max_band = p.max_band;
+    d.half_support = (s->kernel.support - 1) / 2;
     return d;
 }
 

@@ -217,6 +217,20 @@ epic_status build_host_plan(const epic_common *common, const epic_station *st, H
         });
         cell_order.insert(cell_order.end(), order.begin(), order.end());
         cell_order.push_back(-1);
+        if (n_elem >= kBandMinElem) {
+            // row-band tables: counting sort of the elements by nearest row
+            std::vector<int32_t> row(static_cast<size_t>(ny) + 1, 0);
+            for (int a = 0; a < n_elem; ++a) ++row[static_cast<size_t>(cj[a]) + 1];
+            for (int y = 0; y < ny; ++y) row[y + 1] += row[y];
+            std::vector<int32_t> slot(n_elem), next(row.begin(), row.end() - 1);
+            for (int a = 0; a < n_elem; ++a) slot[a] = next[cj[a]]++;
+            hd.band_slot.insert(hd.band_slot.end(), slot.begin(), slot.end());
+            for (int y = 0; y < ny; ++y)
+                hd.max_band = std::max(hd.max_band, row[std::min(ny, y + h + 1)] - row[std::max(0, y - h)]);
+            hd.band_row.insert(hd.band_row.end(), row.begin(), row.end());
+            hd.band_taps.resize(taps.size());
+            for (size_t k = base; k < taps.size(); ++k) hd.band_taps[k] = Tap{slot[taps[k].elem], taps[k].w};
+        }
     }
     return EPIC_OK;
 }

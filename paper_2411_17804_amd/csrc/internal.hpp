@@ -49,7 +49,11 @@ struct StationDev {
     int32_t max_cells;        // max footprint-box cells over channels
     int32_t max_cell_taps;    // max taps landing on one cell over channels
     int32_t max_bw, max_bh;   // largest footprint box sides over channels
-    int64_t part_off;         // first float of this station's chunk partial sums
+    const Tap *band_taps;     // row-band gather (stations of >= kBandMinElem elements), else null:
+    const int32_t *band_row;  //   taps by element slot, first slot of each row [n_chan][ny + 1],
+    const int32_t *band_slot; //   element -> slot [n_chan][n_elem]
+    int32_t max_band;         //   most slots reaching one row
+    int32_t half_support;     // (kernel support - 1) / 2
 };
 
 // A batch of fused work: items (station index, channel, time chunk, band or
@@ -117,6 +121,10 @@ struct PlanHandle {
     int32_t max_bw = 0, max_bh = 0;
     int32_t max_cell_taps = 0; // max taps landing on one cell over channels
     int64_t n_taps_total = 0;
+    const Tap *band_taps = nullptr;      // row-band gather tables (see HostPlan), or null
+    const int32_t *band_row = nullptr;
+    const int32_t *band_slot = nullptr;
+    int32_t max_band = 0;
 };
 
 // Plan of the XFFT route (Eq. 6 gridding of visibilities) of one station.

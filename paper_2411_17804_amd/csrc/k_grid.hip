@@ -9,6 +9,7 @@ namespace epic {
 
 constexpr int kGridCellBlock = 1024;   // grid cells per work-group (4 per thread)
 constexpr int kGridTB = 8;             // samples per gridding work-group
+constexpr size_t kBandLdsMax = 64 * 1024;  // LDS of one row band (one pass's words)
 
 // One work-group per (channel, block of TB samples, block of CB cells): every
 // cell's tap list is read once and applied to the TB samples, whose voltage
@@ -114,14 +115,19 @@ __global__ __launch_bounds__(256) void k_grid(StationDev sd, int n_time, int t0,
 // (channel, block, element), reading unit-stride rows and writing one
 // contiguous run of TB * NP values; k_grid_tb then gathers each tap's TB
 // samples from one or two cache lines instead of TB separate rows.
+// With slot set (the row-band gather), element e's run goes to position
+// slot[c][e] (the elements in order of their nearest row); the reads stay in
+// element order, so they remain unit-stride.
 template <int NP, int VT, int TB>
 __global__ __launch_bounds__(256) void k_volts_tb(const void *__restrict__ volts, int n_elem,
                                                   int n_time, int t0, int nt, int nblk,
+                                                  const int32_t *__restrict__ slot,
                                                   float2 *__restrict__ tv)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n_elem) return;
     const int blk = blockIdx.y, c = blockIdx.z;
+    const int dst_e = slot ? gload<int32_t>(slot, static_cast<size_t>(c) * n_elem + e) : e;
     float2 v[TB][NP];
 #pragma unroll
     for (int t = 0; t < TB; ++t) {
@@ -133,7 +139,7 @@ __global__ __launch_bounds__(256) void k_volts_tb(const void *__restrict__ volts
             for (int p = 0; p < NP; ++p) v[t][p] = make_float2(0.f, 0.f);
         }
     }
-    float2 *dst = tv + ((static_cast<size_t>(c) * nblk + blk) * n_elem + e) * TB * NP;
+    float2 *dst = tv + ((static_cast<size_t>(c) * nblk + blk) * n_elem + dst_e) * TB * NP;
 #pragma unroll
     for (int t = 0; t < TB; ++t)
 #pragma unroll
@@ -253,6 +259,126 @@ __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
                     out[(static_cast<size_t>(t) * NP + p) * npix + y * nx + x] = acc[t][p];
+    }
+}
+
+// The row-band gather (stations with row-band tables): one work-group per
+// (channel, grid row y) and every sample of the launch.  Every tap of a cell
+// in row y comes from an element whose nearest row is within h of y, i.e. one
+// of the slots [band_row[y - h], band_row[y + h + 1]); with the sample-blocked
+// voltages in slot order (k_volts_tb with the slots) those are one contiguous
+// range of runs per sample block.  The work-group takes the samples H at a
+// time (a pass): it copies H samples of each of the band's runs into LDS with
+// 16-byte loads (the 2h + 1 rows that share a run are neighbouring items on
+// one XCD, so it leaves HBM about once), then gathers.  The pass length sets
+// the LDS per work-group and so how many share a CU: measured on a 15.6k
+// element station, one pass per 8-sample run (one work-group per CU) took
+// 2.3x as long as passes of 2 samples (three per CU), and passes of 1 sample
+// (eight per CU) drove the fetched bytes up 24x, the L2 no longer holding the
+// band's lines between passes.  A thread owns one cell of the row (of each
+// group of 256) and keeps its first BT taps in registers for the whole
+// launch, so the tap lists are read once; it gathers from LDS, taps in list
+// order (the same sums, in the same order, as k_grid_tb).  Cells outside the
+// channel's box get zeros (region 0); region 2 launches only the box's rows.
+template <int NP, int TB, int H>
+__global__ __launch_bounds__(256) void k_grid_band(StationDev sd, int nt, int nblk, int n_chan, int n_rows,
+                                                   const float2 *__restrict__ tv, float2 *__restrict__ grid,
+                                                   int region)
+{
+    constexpr int BT = 32;                           // taps per cell held in registers
+    constexpr int RUN = TB * NP;                     // float2 per slot and sample block in tv
+    constexpr int PART = H * NP;                     // float2 per slot and pass
+    constexpr int PW = PART / 2;                     // 16-byte words per slot and pass
+    constexpr int NQ = TB / H;                       // passes per sample block
+    // a slot's part in LDS is padded by 16 bytes: neighbouring cells read
+    // neighbouring slots, and at a stride of a power of two 16-byte words
+    // lanes' reads would start on the same banks
+    constexpr int SLOT = PART + 2;
+    static_assert(PART % 2 == 0 && TB % H == 0, "whole 16-byte words per slot and pass");
+    extern __shared__ __align__(16) float2 band[];   // [slots][SLOT]
+    const int64_t total = static_cast<int64_t>(n_chan) * n_rows;
+    const int64_t id = blockIdx.x;
+    // neighbouring rows of one channel back to back on one XCD (work-group
+    // ids go to the 8 XCDs round-robin)
+    const int64_t item = total % 8 == 0 ? (id % 8) * (total / 8) + id / 8 : id;
+    const int r = static_cast<int>(item % n_rows);
+    const int c = static_cast<int>(item / n_rows);
+    const ChanPlan cp = sd.chan[c];
+    int y = r;
+    if (region == 2) {
+        if (r >= cp.bh) return;
+        y = cp.y0 + r;
+    }
+    const int nx = sd.nx, ny = sd.ny, h = sd.half_support;
+    const int npix = nx * ny;
+    const gptr<int32_t> rows = global_ptr<int32_t>(sd.band_row) + static_cast<size_t>(c) * (ny + 1);
+    const int s0 = rows[max(0, y - h)], s1 = rows[min(ny, y + h + 1)];
+    const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
+    const Tap *taps = sd.band_taps + cp.tap_off;
+    const int by = y - cp.y0;
+    const int n4 = (s1 - s0) * PW;                   // 16-byte words per pass
+    const int nq = nblk * NQ;
+    const float2 *base = tv + (static_cast<size_t>(c) * nblk * sd.n_elem + s0) * RUN;
+    for (int x0 = 0; x0 < nx; x0 += blockDim.x) {
+        const int x = x0 + static_cast<int>(threadIdx.x);
+        const int bx = x - cp.x0;
+        int k0 = 0, kn = 0;
+        if (x < nx && bx >= 0 && bx < cp.bw && by >= 0 && by < cp.bh) {
+            const int cell = by * cp.bw + bx;
+            k0 = cs[cell];
+            kn = cs[cell + 1] - k0;
+        }
+        // this cell's first BT taps: LDS offset of the slot's part, weight
+        int off[BT];
+        float wt[BT];
+#pragma unroll
+        for (int k = 0; k < BT; ++k) {
+            const Tap tp = k < kn ? gload<Tap>(taps, k0 + k) : Tap{s0, 0.f};
+            off[k] = (tp.elem - s0) * SLOT;
+            wt[k] = tp.w;
+        }
+        for (int q = 0; q < nq; ++q) {
+            __syncthreads();   // the previous pass's reads of the LDS are done
+            const float2 *src = base + static_cast<size_t>(q / NQ) * sd.n_elem * RUN + (q % NQ) * PART;
+            float4 *dst = reinterpret_cast<float4 *>(band);
+            for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+                const int sl = i / PW, w = i - sl * PW;
+                dst[sl * (SLOT / 2) + w] = gload<float4>(src + static_cast<size_t>(sl) * RUN, w);
+            }
+            __syncthreads();
+            float2 acc[H][NP];
+#pragma unroll
+            for (int t = 0; t < H; ++t)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) acc[t][p] = make_float2(0.f, 0.f);
+            auto add = [&](int o, float w) {
+                const float2 *v = band + o;
+#pragma unroll
+                for (int t = 0; t < H; ++t)
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const float2 e = v[t * NP + p];
+                        acc[t][p].x = fmaf(w, e.x, acc[t][p].x);
+                        acc[t][p].y = fmaf(w, e.y, acc[t][p].y);
+                    }
+            };
+#pragma unroll
+            for (int k = 0; k < BT; ++k)
+                if (k < kn) add(off[k], wt[k]);
+            for (int k = BT; k < kn; ++k) {
+                const Tap tp = gload<Tap>(taps, k0 + k);
+                add((tp.elem - s0) * SLOT, tp.w);
+            }
+            if (x < nx) {
+                const int tb = q * H;   // the pass's first sample
+                float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix + static_cast<size_t>(y) * nx + x;
+#pragma unroll
+                for (int t = 0; t < H; ++t)
+                    if (tb + t < nt)
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) out[(static_cast<size_t>(t) * NP + p) * npix] = acc[t][p];
+            }
+        }
     }
 }
 
@@ -381,18 +507,41 @@ epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_ti
 {
     constexpr int TB = kGridTB;
     const int nblk = (nt + TB - 1) / TB;
+    // the row-band gather where the station has its tables, the gather writes
+    // whole rows (the whole plane or the box's rows) and one band's words per
+    // pass fit the LDS
+    constexpr int H = 2;   // samples per pass
+    const size_t band_lds = sizeof(float2) * (H * n_pol + 2) * static_cast<size_t>(sd.max_band);
+    const bool banded = sd.band_taps && sd.max_band > 0 && region != 1 && band_lds <= kBandLdsMax;
+    const int32_t *slot = banded ? sd.band_slot : nullptr;
     const dim3 tblocks((sd.n_elem + 255) / 256, nblk, n_chan), threads(256);
     {
         KernelTimer timer("volts_tb", stream);
         if (n_pol == 1 && volt_type == EPIC_CI8)
-            hipLaunchKernelGGL((k_volts_tb<1, EPIC_CI8, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
+            hipLaunchKernelGGL((k_volts_tb<1, EPIC_CI8, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, slot, tv);
         else if (n_pol == 1)
-            hipLaunchKernelGGL((k_volts_tb<1, EPIC_CF32, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
+            hipLaunchKernelGGL((k_volts_tb<1, EPIC_CF32, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, slot, tv);
         else if (volt_type == EPIC_CI8)
-            hipLaunchKernelGGL((k_volts_tb<2, EPIC_CI8, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
+            hipLaunchKernelGGL((k_volts_tb<2, EPIC_CI8, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, slot, tv);
         else
-            hipLaunchKernelGGL((k_volts_tb<2, EPIC_CF32, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, tv);
+            hipLaunchKernelGGL((k_volts_tb<2, EPIC_CF32, TB>), tblocks, threads, 0, stream, sd.volts, sd.n_elem, n_time, t0, nt, nblk, slot, tv);
         EPIC_HIP_TRY(hipGetLastError());
+    }
+    if (banded) {
+        const int n_rows = region == 2 ? sd.max_bh : sd.ny;
+        const int64_t n_wg = static_cast<int64_t>(n_chan) * n_rows;
+        if (n_wg > 0x7fffffff) return fail(EPIC_ERR_UNSUPPORTED, "gridding launch too large");
+        KernelTimer timer("grid_gather", stream);
+        auto go = [&](auto kern) -> epic_status {
+            EPIC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(band_lds)));
+            hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(n_wg)), threads, band_lds, stream, sd, nt, nblk,
+                               n_chan, n_rows, tv, grid, region);
+            EPIC_HIP_TRY(hipGetLastError());
+            return EPIC_OK;
+        };
+        return n_pol == 1 ? go(k_grid_band<1, TB, H>) : go(k_grid_band<2, TB, H>);
     }
     // a sample block of voltages of 1 MB or more (a quarter of an XCD's L2):
     // one-row cell blocks, run block after block of one sample block per XCD

@@ -122,8 +122,11 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     const size_t b_taps = up(sizeof(Tap) * taps.size());
     const size_t b_order = up(sizeof(int32_t) * cell_order.size());
     const size_t b_ec = up(sizeof(int32_t) * elem_cell.size());
+    const size_t b_bt = up(sizeof(Tap) * hp.band_taps.size());
+    const size_t b_br = up(sizeof(int32_t) * hp.band_row.size());
+    const size_t b_bp = up(sizeof(int32_t) * hp.band_slot.size());
     void *dev = nullptr;
-    epic_status s = dev_alloc(&dev, b_chan + b_cell + b_taps + b_order + b_ec);
+    epic_status s = dev_alloc(&dev, b_chan + b_cell + b_taps + b_order + b_ec + b_bt + b_br + b_bp);
     if (s != EPIC_OK) return s;
     char *p = static_cast<char *>(dev);
     hipError_t e = hipMemcpy(p, chans.data(), sizeof(ChanPlan) * chans.size(), hipMemcpyHostToDevice);
@@ -139,6 +142,16 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     if (e == hipSuccess)
         e = hipMemcpy(p + b_chan + b_cell + b_taps + b_order, elem_cell.data(),
                       sizeof(int32_t) * elem_cell.size(), hipMemcpyHostToDevice);
+    char *pb = p + b_chan + b_cell + b_taps + b_order + b_ec;
+    if (e == hipSuccess && hp.max_band > 0) {
+        e = hipMemcpy(pb, hp.band_taps.data(), sizeof(Tap) * hp.band_taps.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(pb + b_bt, hp.band_row.data(), sizeof(int32_t) * hp.band_row.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(pb + b_bt + b_br, hp.band_slot.data(), sizeof(int32_t) * hp.band_slot.size(),
+                          hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         (void)hipFree(dev);
         return hip_fail(e, "plan upload");
@@ -148,6 +161,12 @@ epic_status get_plan(const epic_common *common, const epic_station *st, int devi
     hd.taps = reinterpret_cast<const Tap *>(p + b_chan + b_cell);
     hd.cell_order = reinterpret_cast<const int32_t *>(p + b_chan + b_cell + b_taps);
     hd.elem_cell = reinterpret_cast<const int32_t *>(p + b_chan + b_cell + b_taps + b_order);
+    if (hp.max_band > 0) {
+        hd.band_taps = reinterpret_cast<const Tap *>(pb);
+        hd.band_row = reinterpret_cast<const int32_t *>(pb + b_bt);
+        hd.band_slot = reinterpret_cast<const int32_t *>(pb + b_bt + b_br);
+        hd.max_band = hp.max_band;
+    }
     g_plans.emplace(std::move(key), PlanEntry{dev, hd});
     *out = hd;
     return EPIC_OK;

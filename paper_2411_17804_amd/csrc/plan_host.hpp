@@ -34,13 +34,29 @@ struct ChanPlan {
 // count and a -1 (cell_order, same offsets); from tap_off, the taps in cell
 // order, ascending element order within a cell.  elem_cell[c][a] is element
 // a's nearest cell ci | cj << 16.
+//
+// Stations of at least kBandMinElem elements also get the tables of the
+// row-band gather: per channel each element's slot in the order of the
+// elements' nearest-cell rows (stable in element order: band_slot[c][e]), the
+// first slot of each grid row (band_row[c][y], y = 0 .. ny), and a copy of
+// the taps with each element replaced by its slot (band_taps, same offsets as
+// taps).
+// The elements whose footprints reach row y are then the slots
+// [band_row[y - h], band_row[y + h + 1]) (h = half the kernel support), at most
+// max_band of them.
+constexpr int kBandMinElem = 8192;
+
 struct HostPlan {
     std::vector<ChanPlan> chans;
     std::vector<int32_t> cell_start;
     std::vector<int32_t> cell_order;
     std::vector<int32_t> elem_cell;
     std::vector<Tap> taps;
+    std::vector<int32_t> band_slot;
+    std::vector<int32_t> band_row;
+    std::vector<Tap> band_taps;
     int32_t max_box = 0, max_bw = 0, max_bh = 0, max_cell_taps = 0;
+    int32_t max_band = 0;       // 0: no row-band tables
 };
 
 // Error detail of the calling thread (epic_last_error).

@@ -8,6 +8,7 @@
 // gather lists cover every element's K x K taps exactly once, the weights of
 // an element sum to 1, offsets are monotone and in range, the cell order is
 // a permutation of the box cells).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -112,7 +113,42 @@ void check_plan(const epic_common &c, const epic_station &s, const char *name)
         }
         for (int i = 0; perm && i < ncell; ++i) perm = hit[i] == 1;
         expect(perm && ord[ncell] == -1, "cell order is a permutation of the box cells");
+        if (ne < kBandMinElem) continue;
+        // row-band tables: slot order by nearest row, rows' first slots, and
+        // every tap of a row-y cell inside the slots of rows y - h .. y + h
+        const int h = (K - 1) / 2;
+        const int32_t *bs = hp.band_slot.data() + static_cast<size_t>(ch) * ne;
+        const int32_t *br = hp.band_row.data() + static_cast<size_t>(ch) * (s.ny + 1);
+        std::vector<int> slot_of(bs, bs + ne), owner(ne, -1);
+        bool bperm = true;
+        for (int a = 0; a < ne; ++a) {
+            if (bs[a] < 0 || bs[a] >= ne || owner[bs[a]] >= 0) { bperm = false; break; }
+            owner[bs[a]] = a;
+        }
+        expect(bperm, "band slots are a permutation of the elements");
+        for (int a = 0; bperm && a < ne; ++a) {
+            const int row_a = hp.elem_cell[static_cast<size_t>(ch) * ne + a] >> 16;
+            expect(bs[a] >= br[row_a] && bs[a] < br[row_a + 1], "an element's slot lies in its row's range");
+            if (bs[a] < br[row_a] || bs[a] >= br[row_a + 1]) break;
+        }
+        bool rows_ok = br[0] == 0 && br[s.ny] == ne;
+        for (int y = 0; y < s.ny; ++y) rows_ok = rows_ok && br[y] <= br[y + 1];
+        expect(rows_ok, "band rows monotone, spanning the elements");
+        bool bt_ok = bperm, within = true;
+        for (int cell = 0; bperm && cell < ncell; ++cell) {
+            const int y = cp.y0 + cell / cp.bw;
+            const int lo = br[std::max(0, y - h)], hi = br[std::min(s.ny, y + h + 1)];
+            expect(hi - lo <= hp.max_band, "band within max_band");
+            for (int k = cs[cell]; k < cs[cell + 1]; ++k) {
+                const Tap t = hp.taps[cp.tap_off + k], b = hp.band_taps[cp.tap_off + k];
+                bt_ok = bt_ok && t.elem >= 0 && t.elem < ne && b.elem == slot_of[t.elem] && b.w == t.w;
+                within = within && b.elem >= lo && b.elem < hi;
+            }
+        }
+        expect(bt_ok, "band taps are the taps with elements replaced by their slots");
+        expect(within, "every tap of a row's cells lies in the row's band");
     }
+    expect((ne >= kBandMinElem) == (hp.max_band > 0), "band tables exactly for large stations");
 }
 
 }  // namespace
