@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
     uint32_t *fh = gbl + NP * gplane;                  // [32][pf] DFT rows hi (re, im)
     uint32_t *fl = fh + kD128Rows * d.pf;              // lo
     uint32_t *vf = fl + kD128Rows * d.pf;              // [max_elem][NP][VW] voltages
-    uint32_t *jobs = vf + NP * VW * max_elem;          // [ncell] first tap << 5 | tap count
+    uint32_t *jobs = vf + NP * VW * max_elem;          // [ncell] gather jobs (see below)
     __shared__ float vred[WAVES];
     const uint32_t *rows_lo = rows + N * N;
 
@@ -150,14 +150,65 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
         const float inv_bw = 1.f / static_cast<float>(cp.bw);
 
         // ---- once per item --------------------------------------------------
-        for (int i = tid; i < 2 * NP * gplane; i += BLOCK) gbh[i] = 0u;     // padding stays 0
+        // Gather jobs.  A wave grids 256 cells at a time and runs as many tap
+        // rounds as the largest tap count among them, several times the mean
+        // on a random layout.  Where the channel's tap indices fit 14 bits,
+        // the jobs are the cells with taps in order of falling tap count
+        // (stable: equal counts in box order), cell << 19 | count << 14 |
+        // first tap, so a wave's cells have about equal counts and cells
+        // without taps (zero in G^T from the start) are skipped; otherwise
+        // every cell in box order, first tap << 5 | count.  Either way each
+        // cell adds its own taps in list order.
+        const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
+        const bool sorted = cs[ncell] < (1 << 14) && ncell <= (1 << 13);
+        int njob = ncell;
         {
-            const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
+            uint32_t *box_jobs = sorted ? gbh : jobs;   // G^T is free until it is cleared below
             for (int i = tid; i < ncell; i += BLOCK) {
                 const int k0 = cs[i];
-                jobs[i] = (static_cast<uint32_t>(k0) << 5) | static_cast<uint32_t>(cs[i + 1] - k0);
+                box_jobs[i] = (static_cast<uint32_t>(k0) << 5) | static_cast<uint32_t>(cs[i + 1] - k0);
+            }
+            if (sorted) {
+                // counting sort by falling count, one count at a time: thread
+                // tid ranks the cells of its own run [r0, r1) in box order
+                int *wsum = reinterpret_cast<int *>(gbh + ncell);   // 4 wave totals
+                const int per = (ncell + BLOCK - 1) / BLOCK;
+                const int r0 = min(ncell, tid * per), r1 = min(ncell, r0 + per);
+                lds_barrier();
+                int base = 0;
+                for (int b = 31; b >= 1; --b) {
+                    int cnt = 0;
+                    for (int i = r0; i < r1; ++i) cnt += (box_jobs[i] & 31u) == static_cast<uint32_t>(b);
+                    // exclusive scan of cnt over the work-group
+                    int inc = cnt;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int v = __shfl_up(inc, o);
+                        if (lane >= o) inc += v;
+                    }
+                    if (lane == 63) wsum[wave] = inc;
+                    lds_barrier();
+                    int before = 0, total = 0;
+#pragma unroll
+                    for (int w = 0; w < WAVES; ++w) {
+                        const int v = wsum[w];
+                        before += w < wave ? v : 0;
+                        total += v;
+                    }
+                    int pos = base + before + inc - cnt;
+                    for (int i = r0; i < r1 && cnt > 0; ++i) {
+                        const uint32_t j = box_jobs[i];
+                        if ((j & 31u) == static_cast<uint32_t>(b)) {
+                            jobs[pos++] = (static_cast<uint32_t>(i) << 19) | (static_cast<uint32_t>(b) << 14) | (j >> 5);
+                            --cnt;
+                        }
+                    }
+                    base += total;
+                    lds_barrier();   // wsum is read before the next count's totals
+                }
+                njob = base;
             }
         }
+        for (int i = tid; i < 2 * NP * gplane; i += BLOCK) gbh[i] = 0u;     // padding stays 0
         const Tap *taps = sd.taps + cp.tap_off;
         // stage-1 B fragments: DFT row k_y = ky0 + r16 at y = 16 ks + 4 g + i,
         // from the full table in global memory, held for the item
@@ -256,14 +307,23 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
                 // the G cells' tap loads are in flight together; each cell
                 // still adds its taps in list order
                 constexpr int G = 4;
-                for (int i0 = tid; i0 < ncell; i0 += G * BLOCK) {
-                    int k0[G], kn[G], kmax = 0;
+                // wave w takes the runs of 256 jobs w, w + 4, ...; lane l
+                // the jobs 64 u + l of a run
+                for (int j0 = 256 * wave + lane; j0 < njob; j0 += G * BLOCK) {
+                    int k0[G], kn[G], cell[G], kmax = 0;
 #pragma unroll
                     for (int u = 0; u < G; ++u) {
-                        const int i = i0 + u * BLOCK;
-                        const uint32_t job = i < ncell ? jobs[i] : 0u;
-                        k0[u] = static_cast<int>(job >> 5);
-                        kn[u] = static_cast<int>(job & 31);
+                        const int j = j0 + 64 * u;
+                        const uint32_t job = j < njob ? jobs[j] : 0u;
+                        if (sorted) {
+                            cell[u] = static_cast<int>(job >> 19);
+                            kn[u] = static_cast<int>((job >> 14) & 31u);
+                            k0[u] = static_cast<int>(job & 0x3fffu);
+                        } else {
+                            cell[u] = j;
+                            kn[u] = static_cast<int>(job & 31u);
+                            k0[u] = static_cast<int>(job >> 5);
+                        }
                         kmax = max(kmax, kn[u]);
                     }
                     float2 a[G][NP];
@@ -290,8 +350,8 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
                     }
 #pragma unroll
                     for (int u = 0; u < G; ++u) {
-                        const int i = i0 + u * BLOCK;
-                        if (i >= ncell) break;
+                        if (j0 + 64 * u >= njob) break;
+                        const int i = cell[u];
                         // box row of cell i: (i + 1/2) / bw is at least 1/(2 bw)
                         // away from an integer, far more than its FP32 error
                         const int by = static_cast<int>((static_cast<float>(i) + 0.5f) * inv_bw);
