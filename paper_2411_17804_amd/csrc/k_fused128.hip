@@ -73,8 +73,11 @@ size_t grid_box_lds(int max_elem, int max_ktaps, int n_pol)
 // taps are compacted into LDS (16-bit element slot, FP32 weight) and each
 // thread keeps its box cells' tap ranges in registers, so per sample the
 // gather reads only LDS: the sample's voltages, staged in LDS as FP32 while
-// the next sample's are already on their way into registers.  Box cells are
-// written in natural order, so the stores are contiguous along the box rows.
+// the next sample's are already on their way into registers.  Cells are
+// taken in order of falling tap count (the plan's cell order), so the 64
+// lanes of a wave hold cells with about the same number of taps and a group
+// of cells needs about as many tap rounds as its cells have taps, not as
+// many as the largest tap count among them.
 template <int NP, int VT>
 __device__ __forceinline__ void grid_phase(const StationDev &sd, const ChanPlan &cp, int c, int n_time, int t0,
                                            int t1, int max_ntap, float2 *lds, float2 *__restrict__ box)
@@ -89,6 +92,7 @@ __device__ __forceinline__ void grid_phase(const StationDev &sd, const ChanPlan 
     float *wl = reinterpret_cast<float *>(vl + static_cast<size_t>(gb_slot(ne) + 1) * NP);   // [ntap]
     uint16_t *el = reinterpret_cast<uint16_t *>(wl + max_ntap);                 // [ntap]
     const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
+    const gptr<int32_t> ord = global_ptr<int32_t>(sd.cell_order) + cp.cell_off;
     const Tap *taps = sd.taps + cp.tap_off;
     const int ncell = cp.bw * cp.bh;
     const int ntap = cs[ncell];
@@ -103,8 +107,9 @@ __device__ __forceinline__ void grid_phase(const StationDev &sd, const ChanPlan 
         el[i] = static_cast<uint16_t>(gb_slot(tp.elem));
     }
     if (t_id < NP) vl[gb_slot(ne) * NP + t_id] = make_float2(0.f, 0.f);
-    // this thread's cells i = tid + BLOCK q (q < nq): first tap << 5 | tap
-    // count, and the cell's offset in the box plane, two 16-bit offsets a word
+    // this thread's cells, the ones at positions i = tid + BLOCK q (q < nq)
+    // of the cell order: first tap << 5 | tap count, and the cell's offset in
+    // the box plane, two 16-bit offsets a word
     const int nq = ncell > t_id ? (ncell - 1 - t_id) / BLOCK + 1 : 0;
     uint32_t job[kGridCells];
     uint32_t boff[kGridCells / 2];
@@ -114,10 +119,11 @@ __device__ __forceinline__ void grid_phase(const StationDev &sd, const ChanPlan 
         uint32_t off = 0;
         job[q] = 0;
         if (q < nq) {
-            const int k0 = cs[i];
-            job[q] = (static_cast<uint32_t>(k0) << 5) | static_cast<uint32_t>(cs[i + 1] - k0);
-            const int by = i / cp.bw;
-            off = static_cast<uint32_t>(by * sd.max_bw + (i - by * cp.bw));
+            const int cell = ord[i];
+            const int k0 = cs[cell];
+            job[q] = (static_cast<uint32_t>(k0) << 5) | static_cast<uint32_t>(cs[cell + 1] - k0);
+            const int by = cell / cp.bw;
+            off = static_cast<uint32_t>(by * sd.max_bw + (cell - by * cp.bw));
         }
         if (q % 2 == 0) boff[q / 2] = off;
         else boff[q / 2] |= off << 16;
