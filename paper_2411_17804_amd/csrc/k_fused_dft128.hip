@@ -12,9 +12,9 @@
 //      into hi/lo and store G^T in LDS;
 //   2. stage 1 (along y, pruned to the box rows), for each pol:
 //        Y^T[x][k_y] = sum_y G^T[x][y] F[k_y][y]
-//      G^T is the A operand, the wave's 16 DFT rows are B fragments held in
-//      registers for the item; each wave rescales its result by a power of
-//      two s2 and splits it again.  The result tiles are laid out as the A
+//      G^T is the A operand, the wave's 16 DFT rows the B operand, read per
+//      K-step from the 32-row table in LDS and turned (below); each wave
+//      rescales its result by a power of two s2 and splits it again.  The result tiles are laid out as the A
 //      fragments of stage 2, so both pols' tiles stay in registers;
 //   3. stage 2 (along x, pruned to the box columns), 16 k_x at a time:
 //        Z[k_y][k_x] = sum_x Y[k_y][x] F[k_x][x]
@@ -28,8 +28,9 @@
 // unchanged, and one DFT table serves every channel.  Rows k >= 32 of that
 // table are rows k mod 32 times i^(x (k div 32)) (w^32 = i for
 // w = exp(2 pi i / 128)), an exact change of signs and halves in FP16 or
-// BF16, so LDS holds only rows 0-31 for stage 2; within one B fragment
-// x mod 4 is the word index, so the change is fixed per word.
+// BF16, so LDS holds only rows 0-31 for both stages; within one B fragment
+// the column (x or y) mod 4 is the word index, so the change is fixed per
+// word.
 #include <algorithm>
 #include <type_traits>
 
@@ -211,28 +212,34 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
         for (int i = tid; i < 2 * NP * gplane; i += BLOCK) gbh[i] = 0u;     // padding stays 0
         const Tap *taps = sd.taps + cp.tap_off;
         // stage-1 B fragments: DFT row k_y = ky0 + r16 at y = 16 ks + 4 g + i,
-        // from the full table in global memory, held for the item
-        vec8 b1[T][4];   // [K-step][re-col hi, re-col lo, im-col hi, im-col lo]
-        {
-            const gptr<uint32_t> fr = global_ptr<uint32_t>(rows) + (ky0 + r16) * N + 4 * g;
-            const gptr<uint32_t> fr_lo = global_ptr<uint32_t>(rows_lo) + (ky0 + r16) * N + 4 * g;
+        // read per K-step from the table in LDS: row k_y is table row
+        // k_y mod 32 times i^(M y), M = k_y div 32 (the same for the whole
+        // wave), and y mod 4 is the word index i, so word i is turned by
+        // J = M i mod 4 quarter turns: (P, Q) -> (P, Q), (-Q, P), (-P, -Q),
+        // (Q, -P) for J = 0, 1, 2, 3, with P = (Re, -Im), Q = (Im, Re)
+        const int m1 = __builtin_amdgcn_readfirstlane(ky0 >> 5);
+        const int f1row = (16 * (wave & 1) + r16) * d.pf + 4 * g;
+        auto b1frag = [&](int ks, vec8 &brh, vec8 &brl, vec8 &bih, vec8 &bil) {
+            const u32x4_t wh = *reinterpret_cast<const u32x4_t *>(&fh[f1row + 16 * ks]);
+            const u32x4_t wl = *reinterpret_cast<const u32x4_t *>(&fl[f1row + 16 * ks]);
+            u32x4_t rh, rl, ih, il;
 #pragma unroll
-            for (int ks = 0; ks < T; ++ks) {
-                u32x4_t rh, rl, ih, il;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const uint32_t h = fr[16 * ks + i], l = fr_lo[16 * ks + i];
-                    rh[i] = neg_hi(h);
-                    rl[i] = neg_hi(l);
-                    ih[i] = swap_halves(h);
-                    il[i] = swap_halves(l);
-                }
-                b1[ks][0] = __builtin_bit_cast(vec8, rh);
-                b1[ks][1] = __builtin_bit_cast(vec8, rl);
-                b1[ks][2] = __builtin_bit_cast(vec8, ih);
-                b1[ks][3] = __builtin_bit_cast(vec8, il);
+            for (int i = 0; i < 4; ++i) {
+                const int j = (m1 * i) & 3;
+                const bool sw = j & 1;
+                const uint32_t mre = (j == 1 || j == 2) ? 0x80008000u : 0u, mim = j >= 2 ? 0x80008000u : 0u;
+                const uint32_t ph = neg_hi(wh[i]), qh = swap_halves(wh[i]);
+                const uint32_t pl = neg_hi(wl[i]), ql = swap_halves(wl[i]);
+                rh[i] = (sw ? qh : ph) ^ mre;
+                ih[i] = (sw ? ph : qh) ^ mim;
+                rl[i] = (sw ? ql : pl) ^ mre;
+                il[i] = (sw ? pl : ql) ^ mim;
             }
-        }
+            brh = __builtin_bit_cast(vec8, rh);
+            brl = __builtin_bit_cast(vec8, rl);
+            bih = __builtin_bit_cast(vec8, ih);
+            bil = __builtin_bit_cast(vec8, il);
+        };
 
         // a sample's voltages: raw words into registers (fetch), then into LDS
         // as FP16 pairs (int8) or float pairs with the largest |component|
@@ -383,14 +390,16 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
 #pragma unroll
                 for (int ks = 0; ks < T; ++ks) {
                     if (ks >= my) break;
+                    vec8 b1[4];
+                    b1frag(ks, b1[0], b1[1], b1[2], b1[3]);
 #pragma unroll
                     for (int mt = 0; mt < T; ++mt) {
                         if (mt >= mx) break;
                         const int off = p * gplane + (16 * mt + r16) * d.pg + 16 * ks + 4 * g;
                         const vec8 ah = __builtin_bit_cast(vec8, *reinterpret_cast<const u32x4_t *>(&gbh[off]));
                         const vec8 al = __builtin_bit_cast(vec8, *reinterpret_cast<const u32x4_t *>(&gbl[off]));
-                        c1[mt][0] = mma3<PREC>(ah, al, b1[ks][0], b1[ks][1], c1[mt][0]);
-                        c1[mt][1] = mma3<PREC>(ah, al, b1[ks][2], b1[ks][3], c1[mt][1]);
+                        c1[mt][0] = mma3<PREC>(ah, al, b1[0], b1[1], c1[mt][0]);
+                        c1[mt][1] = mma3<PREC>(ah, al, b1[2], b1[3], c1[mt][1]);
                     }
                 }
                 float ymax = 0.f;
@@ -422,21 +431,30 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
 
             // ---- 3. stage 2 per 16 k_x, one set of B fragments for both pols;
             // 4. products ---------------------------------------------------------
-            auto tile = [&](auto m_tag, int nt) {
+            // a tile's DFT-row words at K-step ks; tile nt reads rows
+            // 16 (nt & 1) + r16 of the table.  The row offset is opaque:
+            // tiles 2m and 2m + 2 read the same rows, and sharing those loads
+            // would hold them in registers across the tiles in between
+            auto row_off = [&](int nt) {
+                int f;
+                asm volatile("v_mov_b32 %0, %1" : "=v"(f) : "v"((16 * (nt & 1) + r16) * d.pf + 4 * g));
+                return f;
+            };
+            // wh, wl: on entry the words of this tile's first K-step, on exit
+            // those of the next tile's (each K-step's successor is loaded
+            // before its products, so the LDS latency overlaps them)
+            auto tile = [&](auto m_tag, int nt, u32x4_t &wh, u32x4_t &wl) {
                 constexpr int M = decltype(m_tag)::value;
-                // opaque row offset: tiles 2m and 2m + 2 read the same DFT rows,
-                // and sharing those loads would hold them in registers across
-                // the tiles in between
-                int frow;
-                asm volatile("v_mov_b32 %0, %1" : "=v"(frow) : "v"((16 * (nt & 1) + r16) * d.pf + 4 * g));
+                const int frow = row_off(nt), fnext = row_off(nt + 1);
                 floatx4_t z[NP][2];
 #pragma unroll
                 for (int p = 0; p < NP; ++p) z[p][0] = z[p][1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ks = 0; ks < T; ++ks) {
                     if (ks >= mx) break;
-                    const u32x4_t wh = *reinterpret_cast<const u32x4_t *>(&fh[frow + 16 * ks]);
-                    const u32x4_t wl = *reinterpret_cast<const u32x4_t *>(&fl[frow + 16 * ks]);
+                    const int o = ks + 1 < mx ? frow + 16 * (ks + 1) : fnext;
+                    const u32x4_t nh = *reinterpret_cast<const u32x4_t *>(&fh[o]);
+                    const u32x4_t nl = *reinterpret_cast<const u32x4_t *>(&fl[o]);
                     u32x4_t rh, ih, rl, il;
                     turned_block<M>(wh, rh, ih);
                     turned_block<M>(wl, rl, il);
@@ -447,6 +465,8 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
                         z[p][0] = mma3<PREC>(a2[p][ks][0], a2[p][ks][1], brh, brl, z[p][0]);
                         z[p][1] = mma3<PREC>(a2[p][ks][0], a2[p][ks][1], bih, bil, z[p][1]);
                     }
+                    wh = nh;
+                    wl = nl;
                 }
                 // lane holds pixels (k_y = ky0 + 4 g + i, k_x = 16 nt + r16)
 #pragma unroll
@@ -465,22 +485,28 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
             };
             // scheduling barriers keep each tile's fragment loads with its
             // products instead of all eight tiles' loads up front
+            u32x4_t wh, wl;
+            {
+                const int f0 = row_off(0);
+                wh = *reinterpret_cast<const u32x4_t *>(&fh[f0]);
+                wl = *reinterpret_cast<const u32x4_t *>(&fl[f0]);
+            }
             __builtin_amdgcn_sched_barrier(0);
-            tile(std::integral_constant<int, 0>{}, 0);
+            tile(std::integral_constant<int, 0>{}, 0, wh, wl);
             __builtin_amdgcn_sched_barrier(0);
-            tile(std::integral_constant<int, 0>{}, 1);
+            tile(std::integral_constant<int, 0>{}, 1, wh, wl);
             __builtin_amdgcn_sched_barrier(0);
-            tile(std::integral_constant<int, 1>{}, 2);
+            tile(std::integral_constant<int, 1>{}, 2, wh, wl);
             __builtin_amdgcn_sched_barrier(0);
-            tile(std::integral_constant<int, 1>{}, 3);
+            tile(std::integral_constant<int, 1>{}, 3, wh, wl);
             __builtin_amdgcn_sched_barrier(0);
-            tile(std::integral_constant<int, 2>{}, 4);
+            tile(std::integral_constant<int, 2>{}, 4, wh, wl);
             __builtin_amdgcn_sched_barrier(0);
-            tile(std::integral_constant<int, 2>{}, 5);
+            tile(std::integral_constant<int, 2>{}, 5, wh, wl);
             __builtin_amdgcn_sched_barrier(0);
-            tile(std::integral_constant<int, 3>{}, 6);
+            tile(std::integral_constant<int, 3>{}, 6, wh, wl);
             __builtin_amdgcn_sched_barrier(0);
-            tile(std::integral_constant<int, 3>{}, 7);
+            tile(std::integral_constant<int, 3>{}, 7, wh, wl);
             __builtin_amdgcn_sched_barrier(0);
 
             // a block of samples ends: its sums go to the FP64 running sums
