@@ -60,6 +60,9 @@ KERNEL_SOURCES = {
     "fused_dft_cadence": ["k_fused_dft.hip", "mfma_split.hpp"] + _PERSISTENT,
     "fused_dft128_cadence": ["k_fused_dft128.hip", "mfma_split.hpp"] + _PERSISTENT,
     "dft2_tiles128": ["k_dft.hip", "mfma_split.hpp"],
+    "grid_gather": ["k_grid.hip", "volts.hpp"],
+    "fft_rows": ["k_fft.hip", "fft_lds.hpp"],
+    "fft_cols": ["k_fft.hip", "fft_lds.hpp"],
 }
 
 
@@ -154,6 +157,19 @@ def _grid_bytes(cfg, stations, rows_only=False):
     return total
 
 
+def _plane_pass_bytes(cfg, stations, cols):
+    """One pass of the composed FP32 transform (FP32 complex values): the row
+    pass reads and writes the footprint box's rows of every plane (the rest
+    is zero and stays untouched), the column pass reads those rows and writes
+    whole planes."""
+    total = 0
+    for s in stations:
+        for bw, bh in box_sides(cfg, s):
+            rows = min(bh, s.ny)
+            total += cfg.n_time * cfg.n_pol * 8 * s.nx * (rows + (s.ny if cols else rows))
+    return total
+
+
 def _power_bytes(cfg, stations, launches):
     acc = sum(cfg.n_chan * cfg.n_pol ** 2 * s.nx * s.ny * 8 for s in stations)
     field = sum(cfg.n_chan * cfg.n_time * cfg.n_pol * s.nx * s.ny * 8 for s in stations)
@@ -175,6 +191,9 @@ ROOFLINE_KERNELS = {
     "grid_gather": ("hbm", lambda s: True,
                     lambda c, st, n: _grid_bytes(c, st, rows_only=all(s.nx >= 128 for s in st))),
     "square_accumulate": ("hbm", lambda s: True, lambda c, st, n: _power_bytes(c, st, n)),
+    # the composed FP32 path's row and column passes (256 x 256 planes)
+    "fft_rows": ("hbm", lambda s: s.nx > 128, lambda c, st, n: _plane_pass_bytes(c, st, False)),
+    "fft_cols": ("hbm", lambda s: s.nx > 128, lambda c, st, n: _plane_pass_bytes(c, st, True)),
 }
 
 PEAKS = {"alu": (PEAK_FP32_VALU_TFLOPS, "TFLOP/s"), "mfma": (PEAK_FP16_MFMA_TFLOPS, "TFLOP/s"),
