@@ -117,17 +117,27 @@ epic_status epic::cadence_composed(const epic_common *c, const epic_station *s,
     }
     for (int t0 = 0; t0 < c->n_time; t0 += chunk) {
         const int nt = std::min(chunk, c->n_time - t0);
+        bool rows_done = false;
         if (pol_kernels)
             st = launch_grid_pol(sd, p.elem_cell, pol_kernels, s->kernel.support, n_pol, n_chan,
                                  c->n_time, c->volt_type, t0, nt, field, stream);
-        else if (tv)
+        else if (tv) {
+            // FP32 two-pass grids: the row-band gather may do the row pass too
+            const float2 *twx = nullptr;
+            if (region == 2) {
+                st = get_twiddles(s->nx, device, &twx);
+                if (st != EPIC_OK) return st;
+            }
             st = launch_grid_tb(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, tv, field, stream,
-                                region);
-        else
+                                region, twx, &rows_done);
+        } else {
             st = launch_grid(sd, n_pol, n_chan, c->n_time, c->volt_type, t0, nt, field, stream, region);
+        }
         if (st != EPIC_OK) return st;
         const int64_t batch = static_cast<int64_t>(n_chan) * nt * n_pol;
-        if (f32)
+        if (f32 && rows_done)
+            st = launch_fft2_f32_cols(s->nx, s->ny, batch, field, device, stream, sd.chan, nt * n_pol);
+        else if (f32)
             st = launch_fft2_f32(s->nx, s->ny, batch, field, field, device, stream, false,
                                  region == 2 ? sd.chan : nullptr, nt * n_pol);
         else

@@ -234,9 +234,13 @@ epic_status launch_vis_grid(const float2 *vis, const XfftPlanHandle &pl, int n_p
 
 // Gridding of large stations through a sample-blocked copy of the voltages:
 // tv is a device buffer of n_chan * ceil(nt / 8) * n_elem * 8 * n_pol float2.
+// With row_twiddles (the nx-point twiddles of get_twiddles) and region 2,
+// the row-band gather may also do the row pass of the two-pass FP32
+// transform (grids 128 or 256 wide); *rows_done then says whether it did.
 epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
                            int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream,
-                           int region = 0);
+                           int region = 0, const float2 *row_twiddles = nullptr,
+                           bool *rows_done = nullptr);
 constexpr int kGridTbMinElem = 1024;   // stations at least this large take that route
 
 // inverse: (1/(nx ny)) sum_k x[k] exp(-2 pi i k.j / N) instead of the + sign
@@ -248,6 +252,10 @@ bool fft_f32_two_pass(int nx, int ny);
 epic_status launch_fft2_f32(int nx, int ny, int64_t batch, const float2 *in, float2 *out,
                             int device, hipStream_t stream, bool inverse = false,
                             const ChanPlan *chan = nullptr, int items_per_chan = 1);
+// The column pass alone (forward, in place), after a row pass done by the
+// gridding (launch_grid_tb's rows_done): two-pass grids with chan set.
+epic_status launch_fft2_f32_cols(int nx, int ny, int64_t batch, float2 *data, int device,
+                                 hipStream_t stream, const ChanPlan *chan, int items_per_chan);
 
 epic_status launch_power(int n_pol, int npix, int n_chan, int nt, const float2 *field,
                          float2 *acc_sum, float2 *acc_comp, int finalize_n_time, float2 *image,

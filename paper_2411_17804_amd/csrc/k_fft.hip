@@ -260,6 +260,26 @@ epic_status dispatch_ny(int ny, int64_t batch, const float2 *in, float2 *out, co
 
 bool fft_f32_two_pass(int nx, int ny) { return ny == 256 || (ny == 128 && nx >= 128); }
 
+epic_status launch_fft2_f32_cols(int nx, int ny, int64_t batch, float2 *data, int device,
+                                 hipStream_t stream, const ChanPlan *chan, int items_per_chan)
+{
+    if (!chan || !fft_f32_two_pass(nx, ny) || (nx != 128 && nx != 256))
+        return fail(EPIC_ERR_INTERNAL, "fft2: column pass alone on an unexpected grid");
+    const RowBox rb{chan, items_per_chan};
+    const float2 *twy = nullptr;
+    epic_status s = get_twiddles(ny, device, &twy);
+    if (s != EPIC_OK) return s;
+    auto by_ny = [&](auto nx_c) -> epic_status {
+        constexpr int NX = decltype(nx_c)::value;
+        switch (ny) {
+        case 128: return run_cols<NX, 128, false>(batch, data, twy, stream, rb);
+        case 256: return run_cols<NX, 256, false>(batch, data, twy, stream, rb);
+        }
+        return fail(EPIC_ERR_INTERNAL, "fft2: unexpected ny");
+    };
+    return nx == 256 ? by_ny(std::integral_constant<int, 256>{}) : by_ny(std::integral_constant<int, 128>{});
+}
+
 epic_status launch_fft2_f32(int nx, int ny, int64_t batch, const float2 *in, float2 *out,
                             int device, hipStream_t stream, bool inverse, const ChanPlan *chan,
                             int items_per_chan)

@@ -2,6 +2,7 @@
 // gather: each cell of the kernel-footprint box sums weight * voltage over
 // the (element, weight) taps the plan lists for it, in ascending element
 // order, so results are deterministic and no atomics are needed.
+#include "fft_lds.hpp"
 #include "internal.hpp"
 #include "volts.hpp"
 
@@ -280,10 +281,15 @@ __global__ __launch_bounds__(256) void k_grid_tb(StationDev sd, int nt, int nblk
 // launch, so the tap lists are read once; it gathers from LDS, taps in list
 // order (the same sums, in the same order, as k_grid_tb).  Cells outside the
 // channel's box get zeros (region 0); region 2 launches only the box's rows.
-template <int NP, int TB, int H>
+// With NX > 0 (region 2, grids nx = NX <= 256 of the composed FP32 path) the
+// work-group also does the row pass of the two-pass transform: the H NP rows
+// of a pass go through the same Stockham passes in LDS as k_fft_rows does
+// (fft_lds.hpp, the same twiddles, so the same bits) before they are
+// written, and the column pass follows directly.
+template <int NP, int TB, int H, int NX>
 __global__ __launch_bounds__(256) void k_grid_band(StationDev sd, int nt, int nblk, int n_chan, int n_rows,
                                                    const float2 *__restrict__ tv, float2 *__restrict__ grid,
-                                                   int region)
+                                                   int region, const float2 *__restrict__ twx)
 {
     constexpr int BT = 32;                           // taps per cell held in registers
     constexpr int RUN = TB * NP;                     // float2 per slot and sample block in tv
@@ -295,7 +301,15 @@ __global__ __launch_bounds__(256) void k_grid_band(StationDev sd, int nt, int nb
     // lanes' reads would start on the same banks
     constexpr int SLOT = PART + 2;
     static_assert(PART % 2 == 0 && TB % H == 0, "whole 16-byte words per slot and pass");
-    extern __shared__ __align__(16) float2 band[];   // [slots][SLOT]
+    static_assert(NX == 0 || NX <= 256, "one row per work-group pass");
+    constexpr int LP = NX + 1;                       // row pitch of the row-pass lines
+    extern __shared__ __align__(16) float2 lds[];
+    // [H NP][LP] lines of the row pass and NX twiddles, then [slots][SLOT]
+    float2 *lines = lds;
+    float2 *tw = lines + H * NP * LP;
+    float2 *band = NX > 0 ? tw + NX : lds;
+    if constexpr (NX > 0)
+        for (int i = threadIdx.x; i < NX; i += blockDim.x) tw[i] = twx[i];
     const int64_t total = static_cast<int64_t>(n_chan) * n_rows;
     const int64_t id = blockIdx.x;
     // neighbouring rows of one channel back to back on one XCD (work-group
@@ -369,8 +383,28 @@ __global__ __launch_bounds__(256) void k_grid_band(StationDev sd, int nt, int nb
                 const Tap tp = gload<Tap>(taps, k0 + k);
                 add((tp.elem - s0) * SLOT, tp.w);
             }
-            if (x < nx) {
-                const int tb = q * H;   // the pass's first sample
+            const int tb = q * H;   // the pass's first sample
+            if constexpr (NX > 0) {
+                // row pass: the pass's H NP rows through LDS (nx == NX, one
+                // chunk of cells), then out
+                if (x < NX) {
+#pragma unroll
+                    for (int t = 0; t < H; ++t)
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) lines[(t * NP + p) * LP + x] = acc[t][p];
+                }
+                lds_barrier();
+                fft_lines<NX, 256, H * NP, false>(lines, LineMap{H * NP, 0, 0, LP, 1}, H * NP, tw);
+                if (x < NX) {
+                    float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix + static_cast<size_t>(y) * NX + x;
+#pragma unroll
+                    for (int t = 0; t < H; ++t)
+                        if (tb + t < nt)
+#pragma unroll
+                            for (int p = 0; p < NP; ++p)
+                                out[(static_cast<size_t>(t) * NP + p) * npix] = lines[(t * NP + p) * LP + x];
+                }
+            } else if (x < nx) {
                 float2 *out = grid + (static_cast<size_t>(c) * nt + tb) * NP * npix + static_cast<size_t>(y) * nx + x;
 #pragma unroll
                 for (int t = 0; t < H; ++t)
@@ -503,15 +537,20 @@ epic_status launch_grid_pol(const StationDev &sd, const int32_t *elem_cell, cons
 }
 
 epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_time, int volt_type,
-                           int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream, int region)
+                           int t0, int nt, float2 *tv, float2 *grid, hipStream_t stream, int region,
+                           const float2 *row_twiddles, bool *rows_done)
 {
     constexpr int TB = kGridTB;
     const int nblk = (nt + TB - 1) / TB;
+    if (rows_done) *rows_done = false;
     // the row-band gather where the station has its tables, the gather writes
     // whole rows (the whole plane or the box's rows) and one band's words per
-    // pass fit the LDS
+    // pass fit the LDS; with row twiddles (region 2, nx 128 or 256) it does
+    // the row pass too
     constexpr int H = 2;   // samples per pass
-    const size_t band_lds = sizeof(float2) * (H * n_pol + 2) * static_cast<size_t>(sd.max_band);
+    const bool rows = row_twiddles && region == 2 && (sd.nx == 128 || sd.nx == 256);
+    const size_t rows_lds = rows ? sizeof(float2) * (static_cast<size_t>(H * n_pol) * (sd.nx + 1) + sd.nx) : 0;
+    const size_t band_lds = sizeof(float2) * (H * n_pol + 2) * static_cast<size_t>(sd.max_band) + rows_lds;
     const bool banded = sd.band_taps && sd.max_band > 0 && region != 1 && band_lds <= kBandLdsMax;
     const int32_t *slot = banded ? sd.band_slot : nullptr;
     const dim3 tblocks((sd.n_elem + 255) / 256, nblk, n_chan), threads(256);
@@ -537,11 +576,16 @@ epic_status launch_grid_tb(const StationDev &sd, int n_pol, int n_chan, int n_ti
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              static_cast<int>(band_lds)));
             hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(n_wg)), threads, band_lds, stream, sd, nt, nblk,
-                               n_chan, n_rows, tv, grid, region);
+                               n_chan, n_rows, tv, grid, region, row_twiddles);
             EPIC_HIP_TRY(hipGetLastError());
+            if (rows_done) *rows_done = rows;
             return EPIC_OK;
         };
-        return n_pol == 1 ? go(k_grid_band<1, TB, H>) : go(k_grid_band<2, TB, H>);
+        if (rows && sd.nx == 256)
+            return n_pol == 1 ? go(k_grid_band<1, TB, H, 256>) : go(k_grid_band<2, TB, H, 256>);
+        if (rows)
+            return n_pol == 1 ? go(k_grid_band<1, TB, H, 128>) : go(k_grid_band<2, TB, H, 128>);
+        return n_pol == 1 ? go(k_grid_band<1, TB, H, 0>) : go(k_grid_band<2, TB, H, 0>);
     }
     // a sample block of voltages of 1 MB or more (a quarter of an XCD's L2):
     // one-row cell blocks, run block after block of one sample block per XCD
