@@ -184,6 +184,17 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(F
         }
 
         lds_barrier();
+        // the jobs with taps: the cell order puts the cells without taps last
+        // (zero in G^T since the item began), so the gather stops before them
+        int njob = 0;
+        {
+            int hi = ncell;
+            while (njob < hi) {
+                const int mid = (njob + hi) >> 1;
+                if ((jobs[mid] >> 16) & 15) njob = mid + 1;
+                else hi = mid;
+            }
+        }
 
         int cur = 0;
         // blocks of `flush` samples: their sums go to the FP64 running sums
@@ -212,14 +223,14 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(F
                 // adds its taps in list order
                 constexpr int G = 4;
                 const uint32_t *vcur = vf + cur * NP * VW * max_elem;
-                for (int i0 = tid; i0 < ncell; i0 += G * BLOCK) {
+                for (int i0 = tid; i0 < njob; i0 += G * BLOCK) {
                     int k0[G], kn[G], kmax = 0;
 #pragma unroll
                     for (int u = 0; u < G; ++u) {
                         const int i = i0 + u * BLOCK;
-                        const uint32_t job = i < ncell ? jobs[i] : 0u;
+                        const uint32_t job = i < njob ? jobs[i] : 0u;
                         k0[u] = static_cast<int>(job & 0xffff);
-                        kn[u] = i < ncell ? static_cast<int>((job >> 16) & 15) : 0;
+                        kn[u] = i < njob ? static_cast<int>((job >> 16) & 15) : 0;
                         kmax = max(kmax, kn[u]);
                     }
                     float2 a[G][NP];
@@ -247,7 +258,7 @@ __global__ __launch_bounds__(64 * (N / 16)) __attribute__((amdgpu_waves_per_eu(F
 #pragma unroll
                     for (int u = 0; u < G; ++u) {
                         const int i = i0 + u * BLOCK;
-                        if (i >= ncell) break;
+                        if (i >= njob) break;
                         const int cell = static_cast<int>(jobs[i] >> 20);
                         const int by = cell / cp.bw, bx = cell - by * cp.bw;
 #pragma unroll
