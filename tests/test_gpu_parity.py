@@ -429,6 +429,38 @@ def test_fp32_footprint_rows_small_station(torch, monkeypatch):
     epic.cache_clear()
 
 
+def test_fp32_row_pass_in_band_gather_128(torch):
+    # the C5 lattice shrunk onto a 128 x 128 grid (15565 elements, a footprint
+    # of 106 cells, about 35 taps per cell: row-band tables, more taps per
+    # cell than the gather holds in registers, far too many for the fused
+    # 128 x 128 kernel, so the composed path): the row-band gather does the
+    # row pass of the 128-wide transform itself and only the column pass
+    # follows; 13 samples leave a ragged last block of its 8-sample runs
+    import bench
+    from paper_2411_17804_amd import epic
+    cfg = W.make_config(5, chan_subset=[9], n_time=13, precision=W.FP32_FFT)
+    st = cfg.stations[0]
+    st.pos_m = st.pos_m * 0.8
+    st.nx = st.ny = 128
+    bw, bh = bench.box_sides(cfg, st)[0]
+    assert st.n_elem >= 8192 and max(bw, bh) < 128, (st.n_elem, bw, bh)
+    say(f"image_cadence fp32 128x128 composed, {st.n_elem} elements, footprint {bw} x {bh}")
+    v = W.station_volts(cfg, 0)
+    epic.cache_clear()
+    common, (station,) = station_objects(cfg, [to_device_volts(v)])
+    epic.timing_reset()
+    epic.timing_enable(True)
+    epic.image_cadence(common, (station,))
+    torch.cuda.synchronize()
+    epic.timing_enable(False)
+    kern = epic.timing_report()
+    assert "fft_cols" in kern and "fft_rows" not in kern, kern
+    err = oracle.image_error(to_complex(station.image), oracle_image(cfg, 0, v), cfg.n_pol)
+    say(f"  worst error {err.max():.2e}")
+    assert err.max() <= FP32_TOL, err
+    epic.cache_clear()
+
+
 @pytest.mark.parametrize("idx,prec", [(3, "fp16"), (5, "bf16"), (5, "fp32")])
 def test_composed_cadence_in_chunks(torch, monkeypatch, idx, prec):
     # a field budget of 2 MB splits the composed cadence into chunks of a few
