@@ -69,13 +69,14 @@ namespace {
 constexpr int kPathFft = 0, kPathDft = 1, kPathFft128 = 2;
 // Samples summed in FP32 before the FP64 running sums (the bound of the
 // plain block sum, (B - 1) units in the last place, is what limits the error
-// of the mean; in the 128 x 128 class it is also the gridding block).
+// of the mean).
 constexpr int kDefaultFlush = 16;
 const int kFlushCandidates[] = {8, 16};
 // Samples the 128 x 128 FP32 kernel grids at a time (its variants): each
 // work-group's boxes for one sample take about 100 KB on the largest
 // stations, so blocks of a few samples stay in the L2 between gridding and
-// transform.
+// transform, while larger blocks stage the channel's taps into LDS less
+// often; the autotuner measures which wins.
 const int kGridBlocks128[] = {2, 4, 1, 16};
 
 struct Tile {
