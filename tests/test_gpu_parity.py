@@ -461,6 +461,34 @@ def test_fp32_row_pass_in_band_gather_128(torch):
     epic.cache_clear()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_one_pol_row_band_station(torch, prec):
+    # the C5 station with one pol: the row-band gather with 16-byte slots of
+    # one pol (grid_voltages, every row of the plane) and the composed
+    # cadence (FP32: the gather does the row pass; FP16-split: the dense
+    # DFT-matrix passes), 13 samples for a ragged last run
+    import dataclasses
+    from paper_2411_17804_amd import epic
+    p = W.FP32_FFT if prec == "fp32" else W.FP16_SPLIT
+    cfg = dataclasses.replace(W.make_config(5, chan_subset=[40], n_time=13, precision=p), n_pol=1)
+    st = cfg.stations[0]
+    say(f"one-pol C5 station ({st.n_elem} elements), {prec}")
+    v = W.station_volts(cfg, 0)
+    epic.cache_clear()
+    common, (station,) = station_objects(cfg, [to_device_volts(v)], p)
+    grid = torch.zeros((cfg.n_chan, cfg.n_time, 1, st.ny, st.nx, 2), dtype=torch.float32, device="cuda")
+    epic.grid_voltages(common, station, 0, cfg.n_time, grid)
+    epic.image_cadence(common, (station,))
+    torch.cuda.synchronize()
+    ref = oracle.grid(st.pos_m, cfg.wavelengths_m[0], W.GRID_SPACING_WL, st.nx, st.ny, st.kernel_type,
+                      st.support, st.sigma_cells, v[0], t0=0, nt=cfg.n_time)
+    assert _rel(to_complex(grid)[0], ref) <= 1e-6
+    err = oracle.image_error(to_complex(station.image), oracle_image(cfg, 0, v), cfg.n_pol)
+    say(f"  worst error {err.max():.2e}")
+    assert err.max() <= (FP32_TOL if prec == "fp32" else SPLIT_TOL["fp16"]), err
+    epic.cache_clear()
+
+
 @pytest.mark.parametrize("idx,prec", [(3, "fp16"), (5, "bf16"), (5, "fp32")])
 def test_composed_cadence_in_chunks(torch, monkeypatch, idx, prec):
     # a field budget of 2 MB splits the composed cadence into chunks of a few
