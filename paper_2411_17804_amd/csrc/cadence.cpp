@@ -133,8 +133,17 @@ int grid_block128(const Group &g) { return kGridBlocks128[g.tile.variant & 3]; }
 // The 128 x 128 split-precision class runs either its persistent kernel
 // (variant 0) or, per station, the composed path (variant 1): on gfx950 the
 // composed path's separate gridding, transform and squaring kernels can be
-// the faster of the two, so the autotuner measures both.
-bool runs_composed(const Group &g) { return g.path == kPathDft && g.n == 128 && g.tile.variant == 1; }
+// the faster of the two, so the autotuner measures both.  The FP32 classes up
+// to 64 x 64 have the composed path as variant kComposedFft: a persistent
+// work-group images a (station, channel) over the whole cadence, so a call
+// with few channels keeps few work-groups busy, while the composed kernels
+// spread every (channel, sample) over the GPU.
+constexpr int kComposedFft = 2;
+bool runs_composed(const Group &g)
+{
+    return (g.path == kPathDft && g.n == 128 && g.tile.variant == 1) ||
+           (g.path == kPathFft && g.tile.variant == kComposedFft);
+}
 
 // Kernel shapes a class can run (variant numbers the launcher understands).
 std::vector<int> variants_of(const Group &g, const epic_common *c)
@@ -145,8 +154,12 @@ std::vector<int> variants_of(const Group &g, const epic_common *c)
         std::vector<int> v;
         for (int k = 0; k < 2; ++k)
             if (fft64_fits(g.batch, c->n_pol, c->volt_type, k)) v.push_back(k);
-        if (!v.empty()) return v;
+        if (!v.empty()) {
+            v.push_back(kComposedFft);
+            return v;
+        }
     }
+    if (g.path == kPathFft) return {0, kComposedFft};
     return {0};
 }
 
