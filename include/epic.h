@@ -396,8 +396,9 @@ const char *epic_status_string(epic_status status);
 /* Detail of the last failure on the calling thread ("" if none). */
 const char *epic_last_error(void);
 
-/* Free every library-owned device table, workspace and graph.  Must not race
- * with calls in flight on any stream. */
+/* Free every library-owned device table, workspace and graph, and forget the
+ * autotuner's choices (read again from EPIC_TUNE_CACHE when it names a file).
+ * Must not race with calls in flight on any stream. */
 void epic_cache_clear(void);
 
 #ifdef __cplusplus

@@ -130,25 +130,24 @@ std::string class_key(const Group &g, const epic_common *c)
 
 int grid_block128(const Group &g) { return kGridBlocks128[g.tile.variant & 3]; }
 
-// The 128 x 128 split-precision class runs either its persistent kernel
-// (variant 0) or, per station, the composed path (variant 1): on gfx950 the
-// composed path's separate gridding, transform and squaring kernels can be
-// the faster of the two, so the autotuner measures both.  The FP32 classes up
-// to 64 x 64 have the composed path as variant kComposedFft: a persistent
-// work-group images a (station, channel) over the whole cadence, so a call
-// with few channels keeps few work-groups busy, while the composed kernels
-// spread every (channel, sample) over the GPU.
+// Every split-precision class runs either its persistent kernel (variant 0)
+// or, per station, the composed path (variant 1), and the FP32 classes up to
+// 64 x 64 have the composed path as variant kComposedFft: the autotuner
+// measures both.  At 128 x 128 the composed path's separate gridding,
+// transform and squaring kernels can be the faster on gfx950; smaller, a
+// persistent work-group images a (station, channel) over the whole cadence,
+// so a call with few channels keeps few work-groups busy, while the composed
+// kernels spread every (channel, sample) over the GPU.
 constexpr int kComposedFft = 2;
 bool runs_composed(const Group &g)
 {
-    return (g.path == kPathDft && g.n == 128 && g.tile.variant == 1) ||
-           (g.path == kPathFft && g.tile.variant == kComposedFft);
+    return (g.path == kPathDft && g.tile.variant == 1) || (g.path == kPathFft && g.tile.variant == kComposedFft);
 }
 
 // Kernel shapes a class can run (variant numbers the launcher understands).
 std::vector<int> variants_of(const Group &g, const epic_common *c)
 {
-    if (g.path == kPathDft && g.n == 128) return {0, 1};
+    if (g.path == kPathDft) return {0, 1};
     if (g.path == kPathFft128) return {0, 1, 2, 3};
     if (g.path == kPathFft && g.n == 64 && c->n_pol == 2) {
         std::vector<int> v;
@@ -795,6 +794,9 @@ void clear_cadence_cache()
     std::lock_guard<std::mutex> lock(g_mu);
     for (auto &kv : g_plans) free_plan(kv.second);
     g_plans.clear();
+    // the tuner's choices too: the next plan reads EPIC_TUNE_CACHE again
+    g_tuned.clear();
+    g_tune_loaded = false;
 }
 
 }  // namespace epic

@@ -685,25 +685,27 @@ def test_split128_one_launch_mixed_supports(torch, prec):
     epic.cache_clear()
 
 
-def test_autotune_small_cadence(torch):
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_autotune_small_cadence(torch, prec):
     # C1 (4 channels of one small station): the tuner weighs the persistent
     # 32 x 32 kernel, which keeps 4 work-groups busy, against the composed
     # path; whichever it keeps must match the oracle
     from paper_2411_17804_amd import epic
-    cfg = W.make_config(1)
+    p = W.FP32_FFT if prec == "fp32" else W.FP16_SPLIT
+    cfg = W.make_config(1, precision=p)
     v = W.station_volts(cfg, 0)
     epic.cache_clear()
-    common, stations = station_objects(cfg, [to_device_volts(v)])
+    common, stations = station_objects(cfg, [to_device_volts(v)], p)
     epic.autotune(common, stations)
     epic.timing_reset()
     epic.timing_enable(True)
     epic.image_cadence(common, stations)
     torch.cuda.synchronize()
     epic.timing_enable(False)
-    say(f"C1 after autotune: {sorted(epic.timing_report())}")
+    say(f"C1 {prec} after autotune: {sorted(epic.timing_report())}")
     err = oracle.image_error(to_complex(stations[0].image), oracle_image(cfg, 0, v), cfg.n_pol)
     say(f"  worst error {err.max():.2e}")
-    assert err.max() <= FP32_TOL, err
+    assert err.max() <= (FP32_TOL if prec == "fp32" else SPLIT_TOL["fp16"]), err
     epic.cache_clear()
 
 

@@ -24,6 +24,9 @@ def test_noalloc_matches_image_cadence(prec):
     torch = torch_cuda()
     from paper_2411_17804_amd import epic
     epic.load()
+    # no tuned choices from earlier calls: a class tuned to its composed path
+    # would run other kernels in image_cadence than the persistent ones here
+    epic.cache_clear()
     name = "fp32" if prec == W.FP32_FFT else "fp16-split"
     # first call: a hierarchical batch (3 stations, 6 channels, ragged
     # cadence) of grids up to 64, and in split precision one 128 x 128 station
