@@ -166,7 +166,10 @@ epic_status image_cadence(const epic_common *common, const epic_station *station
  * image_cadence for callers that cannot allocate device memory: code under
  * hipGraph stream capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Same arguments, layouts and results as image_cadence (the same
- * kernels run), but the call allocates nothing: every table it needs (the
+ * persistent kernels run; where the autotuner chose the composed path for a
+ * class, this call runs the class's persistent kernel instead, so its images
+ * then agree with image_cadence's within the tolerances rather than bit for
+ * bit), but the call allocates nothing: every table it needs (the
  * stations' kernel cells and weights, the transform tables, the work lists
  * and queue counters) is written into one fixed device array of 64 MiB that
  * the library holds on each GPU until the process ends, and the images
