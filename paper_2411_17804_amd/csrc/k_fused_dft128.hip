@@ -153,15 +153,20 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
         // ---- once per item --------------------------------------------------
         // Gather jobs.  A wave grids 256 cells at a time and runs as many tap
         // rounds as the largest tap count among them, several times the mean
-        // on a random layout.  Where the channel's tap indices fit 14 bits,
-        // the jobs are the cells with taps in order of falling tap count
-        // (stable: equal counts in box order), cell << 19 | count << 14 |
-        // first tap, so a wave's cells have about equal counts and cells
+        // on a random layout.  Where the channel's tap indices fit the bits
+        // that a cell index and a count leave (kbits below), the jobs are the
+        // cells with taps in order of falling tap count (stable: equal counts
+        // in box order), cell << (kbits + 5) | count << kbits | first tap,
+        // so a wave's cells have about equal counts and cells
         // without taps (zero in G^T from the start) are skipped; otherwise
         // every cell in box order, first tap << 5 | count.  Either way each
         // cell adds its own taps in list order.
         const gptr<int32_t> cs = global_ptr<int32_t>(sd.cell_start) + cp.cell_off;
-        const bool sorted = cs[ncell] < (1 << 14) && ncell <= (1 << 13);
+        // field widths: cell index (cbits, enough for ncell), count (5), first
+        // tap (the remaining kbits)
+        const int cbits = 32 - __builtin_clz(static_cast<unsigned>(max(ncell - 1, 1)));
+        const int kbits = 27 - cbits;
+        const bool sorted = cs[ncell] <= (1 << kbits);
         int njob = ncell;
         {
             uint32_t *box_jobs = sorted ? gbh : jobs;   // G^T is free until it is cleared below
@@ -199,7 +204,8 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
                     for (int i = r0; i < r1 && cnt > 0; ++i) {
                         const uint32_t j = box_jobs[i];
                         if ((j & 31u) == static_cast<uint32_t>(b)) {
-                            jobs[pos++] = (static_cast<uint32_t>(i) << 19) | (static_cast<uint32_t>(b) << 14) | (j >> 5);
+                            jobs[pos++] = (static_cast<uint32_t>(i) << (kbits + 5)) | (static_cast<uint32_t>(b) << kbits) |
+                                          (j >> 5);
                             --cnt;
                         }
                     }
@@ -323,9 +329,9 @@ __global__ __launch_bounds__(kD128Block) __attribute__((amdgpu_waves_per_eu(1)))
                         const int j = j0 + 64 * u;
                         const uint32_t job = j < njob ? jobs[j] : 0u;
                         if (sorted) {
-                            cell[u] = static_cast<int>(job >> 19);
-                            kn[u] = static_cast<int>((job >> 14) & 31u);
-                            k0[u] = static_cast<int>(job & 0x3fffu);
+                            cell[u] = static_cast<int>(job >> (kbits + 5));
+                            kn[u] = static_cast<int>((job >> kbits) & 31u);
+                            k0[u] = static_cast<int>(job & ((1u << kbits) - 1u));
                         } else {
                             cell[u] = j;
                             kn[u] = static_cast<int>(job & 31u);
