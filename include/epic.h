@@ -356,18 +356,23 @@ epic_status array_xfft(const epic_common *common, const epic_station *array,
                        const int32_t *pixels, hipStream_t stream);
 
 /*
- * Tile tuning (auxiliary).  image_cadence runs every station whose grid is
- * square and at most 64 x 64 (and, in FP32, every 128 x 128 one) in fused
- * kernels that process one (station, channel, time chunk) item per
- * work-group; the chunk length (16, 32, 64 or 128 samples) trades launch
- * width against per-item setup and partial-sum traffic.  epic_autotune runs each fused kernel class of this call with each
- * candidate on the caller's buffers (it overwrites station images), keeps the
- * fastest for later image_cadence calls of the same class (grid size,
- * footprint tiles, pols, voltage type, precision) and, if the environment
- * variable EPIC_TUNE_CACHE names a file, stores the choices there and reads
- * them back in later processes.  Synchronises the stream.  The chunk length
- * changes only the summation grouping of the time average, never the set of
- * samples summed.
+ * Tile tuning (auxiliary).  image_cadence sorts the stations into kernel
+ * classes (grid size, footprint tiles, pols, voltage type, precision) and
+ * runs each class as one persistent kernel over (station, channel) items.
+ * A class's tile is the flush interval (8 or 16 samples summed in FP32
+ * before the FP64 running sums) and, where it has several, the kernel shape:
+ * the 64 x 64 FP32 kernel with one pol per half of 1024 threads or both pols
+ * on 512, the 128 x 128 FP32 kernel's gridding block (1, 2, 4 or 16
+ * samples), and for every split-precision class and every FP32 class up to
+ * 64 x 64 the composed path (separate gridding, transform and squaring
+ * kernels) instead of the persistent kernel.  epic_autotune runs each class
+ * of this call with each candidate on the caller's buffers (it overwrites
+ * station images), keeps the fastest for later image_cadence calls of the
+ * same class and, if the environment variable EPIC_TUNE_CACHE names a file,
+ * stores the choices there and reads them back in later processes;
+ * epic_cache_clear forgets the choices held in memory.  Synchronises the
+ * stream.  The flush interval changes only the grouping of the time
+ * average's sums, never the set of samples summed.
  */
 epic_status epic_autotune(const epic_common *common, const epic_station *stations,
                           int32_t n_stations, hipStream_t stream);

@@ -444,7 +444,8 @@ def image_cadence_noalloc(common: Common, stations, stream=None):
 
 
 def autotune(common: Common, stations, stream=None):
-    """Time the fused kernels' chunk lengths on these buffers and keep the best."""
+    """Time each kernel class's tiles (flush interval, kernel shape, persistent
+    kernel or composed path) on these buffers and keep the fastest."""
     lib = load()
     c, keep1 = common.to_c()
     arr, keep = _stations_c(stations, common)
